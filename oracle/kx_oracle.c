@@ -1,0 +1,460 @@
+/*
+ * kx_oracle.c -- plain, slow, FP64 CPU reference for the per-grid-point
+ * species production rates and mixture-averaged transport properties of
+ * Danciu & Frouzakis, "KinetiX" (arXiv 2411.02640), Appendix A.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library calls, links or loads
+ * this file; only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no header, helper, table or constant with the
+ * HIP path: it takes the caller's mechanism arrays as they are and evaluates
+ * the textbook definitions, in the order the appendix writes them, one grid
+ * point at a time (OpenMP over points; no blocking, fusion or reuse).
+ *
+ * Readings of the paper taken here (each is listed in the design notes):
+ *  - NASA-7 with two ranges split at t_mid: low range when T < t_mid.
+ *  - log in the Troe blend is base 10; ln in Arrhenius and in the fits.
+ *  - The falloff factor P_r/(1+P_r) F multiplies the whole rate of progress
+ *    once, with k_f = k_inf inside r_i (eq:c_i applied once, not twice).
+ *  - The third-body factor [X]_i multiplies both directions.
+ *  - Wilke: (W_j/W_k)^(1/4) inside phi_kj (the form of the cited Bird et al.
+ *    text); the appendix prints (W_k/W_j)^(1/4).
+ *  - Binary diffusion fits are evaluated at one atmosphere and divided by
+ *    p/p_atm; kind 1 tables hold fits of 1/D_kj instead.
+ *  - D_km falls back to D_kk when sum_{j!=k} X_j/D_kj is exactly zero.
+ *  - P_r is clamped below at the smallest normal double before log10.
+ *  - Units: cgs, concentrations in mol/cm^3, Ea in cal/mol.
+ */
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Own copies of the physical constants (CODATA 2018 exact R; thermochemical
+ * calorie; standard atmosphere). */
+#define KXO_RU 8.31446261815324e7                  /* erg / (mol K) */
+#define KXO_RCAL (8.31446261815324 / 4.184)        /* cal / (mol K) */
+#define KXO_PATM 1013250.0                         /* dyn / cm^2 */
+
+enum { KXO_ELEMENTARY = 0, KXO_THREEBODY = 1, KXO_LINDEMANN = 2, KXO_TROE = 3 };
+
+/* The oracle's own view of a mechanism: plain host arrays, row-major. */
+typedef struct {
+    int32_t ns, nr, ne;
+    const double *elem_mass;     /* [ne] */
+    const int32_t *comp;         /* [ns][ne] */
+    const double *nasa_lo;       /* [ns][7] */
+    const double *nasa_hi;       /* [ns][7] */
+    const double *t_mid;         /* [ns] */
+    const int32_t *rtype;        /* [nr] */
+    const int32_t *rev;          /* [nr] */
+    const int32_t *reac_ptr, *reac_sp, *reac_nu;
+    const int32_t *prod_ptr, *prod_sp, *prod_nu;
+    const double *A, *beta, *Ea;        /* [nr] */
+    const double *A0, *beta0, *Ea0;     /* [nr] */
+    const double *troe;                 /* [nr][4] */
+    const int32_t *eff_ptr, *eff_sp;
+    const double *eff_val, *eff_default;
+    int32_t fit_order;
+    double fit_L0, fit_h;
+    int32_t diff_kind;
+    const double *visc_fit;      /* [ns][order] */
+    const double *cond_fit;      /* [ns][order] */
+    const double *diff_fit;      /* [ns][ns][order] */
+} kxo_mech;
+
+static int g_threads = 0;
+
+void kxo_set_threads(int n) { g_threads = n; }
+
+int kxo_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+static double species_weight(const kxo_mech *m, int k)
+{
+    double w = 0.0;
+    for (int e = 0; e < m->ne; ++e) w += m->comp[k * m->ne + e] * m->elem_mass[e];
+    return w;
+}
+
+/* x^n for integer n by repeated multiplication (n < 0: reciprocal). */
+static double int_pow(double x, int n)
+{
+    double r = 1.0;
+    int a = n < 0 ? -n : n;
+    for (int i = 0; i < a; ++i) r *= x;
+    return n < 0 ? 1.0 / r : r;
+}
+
+/* ---------------------------------------------------------------- thermo */
+
+static const double *nasa_range(const kxo_mech *m, int k, double T)
+{
+    return (T < m->t_mid[k]) ? m->nasa_lo + 7 * k : m->nasa_hi + 7 * k;
+}
+
+/* App. A.1: Cp/R, H/RT (eq:H_RT), S/R (eq:S_R), and G/RT written out from the
+ * closed form eq:Ck.  Any output pointer may be NULL. */
+void kxo_thermo(const kxo_mech *m, double T, double *cp_r, double *h_rt,
+                double *s_r, double *g_rt)
+{
+    const double T2 = T * T, T3 = T2 * T, T4 = T3 * T, lnT = log(T);
+    for (int k = 0; k < m->ns; ++k) {
+        const double *a = nasa_range(m, k, T);
+        if (cp_r) cp_r[k] = a[0] + a[1] * T + a[2] * T2 + a[3] * T3 + a[4] * T4;
+        if (h_rt)
+            h_rt[k] = a[0] + a[1] / 2.0 * T + a[2] / 3.0 * T2 + a[3] / 4.0 * T3 +
+                      a[4] / 5.0 * T4 + a[5] / T;
+        if (s_r)
+            s_r[k] = a[0] * lnT + a[1] * T + a[2] / 2.0 * T2 + a[3] / 3.0 * T3 +
+                     a[4] / 4.0 * T4 + a[6];
+        if (g_rt)
+            g_rt[k] = a[0] * (1.0 - lnT) - a[1] / 2.0 * T - a[2] / 6.0 * T2 -
+                      a[3] / 12.0 * T3 - a[4] / 20.0 * T4 + a[5] / T - a[6];
+    }
+}
+
+/* Mass-specific cp_k = Cp_k / W_k, h_k = H_k / W_k and the mixture
+ * cp = sum_k Y_k cp_k (App. A.1), per point; SoA layout like the rates. */
+void kxo_mixture_thermo(const kxo_mech *m, int64_t n, const double *T, const double *Y,
+                        double *cp_mass, double *h_mass, double *cp_mix)
+{
+    const int ns = m->ns;
+#pragma omp parallel num_threads(g_threads > 0 ? g_threads : kxo_max_threads())
+    {
+        double *cp_r = malloc(sizeof(double) * ns);
+        double *h_rt = malloc(sizeof(double) * ns);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            kxo_thermo(m, T[i], cp_r, h_rt, NULL, NULL);
+            double cp = 0.0;
+            for (int k = 0; k < ns; ++k) {
+                const double W = species_weight(m, k);
+                const double cpk = cp_r[k] * KXO_RU / W;
+                const double hk = h_rt[k] * KXO_RU * T[i] / W;
+                if (cp_mass) cp_mass[(int64_t)k * n + i] = cpk;
+                if (h_mass) h_mass[(int64_t)k * n + i] = hk;
+                cp += Y[(int64_t)k * n + i] * cpk;
+            }
+            if (cp_mix) cp_mix[i] = cp;
+        }
+        free(cp_r);
+        free(h_rt);
+    }
+}
+
+/* ---------------------------------------------------------------- kinetics */
+
+/* eq:arrhenius with E_R = E_a / R. */
+static double arrhenius(double A, double b, double Ea, double T)
+{
+    const double ER = Ea / KXO_RCAL;
+    return A * pow(T, b) * exp(-ER / T);
+}
+
+/* [X]_i = sum_k alpha_ki [X_k] with the reaction's default efficiency for
+ * species not listed (App. A.2, third-body reactions). */
+static double third_body(const kxo_mech *m, int i, const double *C)
+{
+    double X = 0.0;
+    for (int k = 0; k < m->ns; ++k) {
+        double alpha = m->eff_default[i];
+        for (int e = m->eff_ptr[i]; e < m->eff_ptr[i + 1]; ++e)
+            if (m->eff_sp[e] == k) alpha = m->eff_val[e];
+        X += alpha * C[k];
+    }
+    return X;
+}
+
+/* Troe blending factor F (eq:blend, base-10 logarithms). */
+static double troe_F(const double *p4, double T, double Pr)
+{
+    const double alpha = p4[0], T3 = p4[1], T1 = p4[2], T2 = p4[3];
+    double Fcent = (1.0 - alpha) * exp(-T / T3) + alpha * exp(-T / T1);
+    if (!isnan(T2)) Fcent += exp(-T2 / T);
+    const double lFc = log10(Fcent);
+    const double c = -0.4 - 0.67 * lFc;
+    const double nn = 0.75 - 1.27 * lFc;
+    const double d = 0.14;
+    const double lPr = log10(Pr > DBL_MIN ? Pr : DBL_MIN);
+    const double f1 = (lPr + c) / (nn - d * (lPr + c));
+    const double lF = lFc / (1.0 + f1 * f1);
+    return pow(10.0, lF);
+}
+
+/* Net stoichiometric coefficient nu''_ki - nu'_ki. */
+static int net_nu(const kxo_mech *m, int i, int k)
+{
+    int nu = 0;
+    for (int e = m->reac_ptr[i]; e < m->reac_ptr[i + 1]; ++e)
+        if (m->reac_sp[e] == k) nu -= m->reac_nu[e];
+    for (int e = m->prod_ptr[i]; e < m->prod_ptr[i + 1]; ++e)
+        if (m->prod_sp[e] == k) nu += m->prod_nu[e];
+    return nu;
+}
+
+/* Neumaier's compensated summation step. */
+static void neumaier_add(double *sum, double *comp, double x)
+{
+    const double t = *sum + x;
+    if (fabs(*sum) >= fabs(x))
+        *comp += (*sum - t) + x;
+    else
+        *comp += (x - t) + *sum;
+    *sum = t;
+}
+
+/*
+ * Rates for one point.  C_k from Y (W-bar = 1 / sum Y_k/W_k); then per
+ * reaction: k_f (Arrhenius, or k_inf with the falloff modifier), K_c from the
+ * Gibbs energies (eq:K_p, eq:Ck) and (p_atm/RT)^(sum nu), k_r = k_f/K_c, the
+ * law of mass action (eq:r_i) and the modifier c_i (eq:c_i); finally
+ * wdot_k = sum_i nu_ki R_i with compensated summation.
+ * scale_k = sum_i |nu_ki| |c_i| (k_f prod C^nu' + k_r prod C^nu''), the size
+ * of the terms whose difference the net rate is.
+ */
+static void rates_point(const kxo_mech *m, double T, double p, const double *Y,
+                        int64_t stride, double *wdot, double *scale, int64_t ostride,
+                        double *qf_out, double *qr_out, double *c_out, double *ws)
+{
+    const int ns = m->ns, nr = m->nr;
+    double *C = ws, *g = ws + ns, *sum = ws + 2 * ns, *cmp = ws + 3 * ns,
+           *scl = ws + 4 * ns;
+
+    double inv_wbar = 0.0;
+    for (int k = 0; k < ns; ++k) inv_wbar += Y[k * stride] / species_weight(m, k);
+    const double wbar = 1.0 / inv_wbar;
+    for (int k = 0; k < ns; ++k) {
+        const double X = Y[k * stride] * wbar / species_weight(m, k);
+        C[k] = X * p / (KXO_RU * T);
+    }
+    kxo_thermo(m, T, NULL, NULL, NULL, g);
+    for (int k = 0; k < ns; ++k) sum[k] = cmp[k] = scl[k] = 0.0;
+
+    for (int i = 0; i < nr; ++i) {
+        const int type = m->rtype[i];
+        double kf = arrhenius(m->A[i], m->beta[i], m->Ea[i], T);
+        double c = 1.0;
+        if (type == KXO_THREEBODY) {
+            c = third_body(m, i, C);
+        } else if (type == KXO_LINDEMANN || type == KXO_TROE) {
+            const double k0 = arrhenius(m->A0[i], m->beta0[i], m->Ea0[i], T);
+            const double Pr = k0 * third_body(m, i, C) / kf;
+            const double F = (type == KXO_TROE) ? troe_F(m->troe + 4 * i, T, Pr) : 1.0;
+            c = Pr / (1.0 + Pr) * F;
+        }
+        double kr = 0.0;
+        if (m->rev[i]) {
+            double dG = 0.0;
+            int dnu = 0;
+            for (int e = m->prod_ptr[i]; e < m->prod_ptr[i + 1]; ++e) {
+                dG += m->prod_nu[e] * g[m->prod_sp[e]];
+                dnu += m->prod_nu[e];
+            }
+            for (int e = m->reac_ptr[i]; e < m->reac_ptr[i + 1]; ++e) {
+                dG -= m->reac_nu[e] * g[m->reac_sp[e]];
+                dnu -= m->reac_nu[e];
+            }
+            const double Kp = exp(-dG);
+            const double Kc = Kp * int_pow(KXO_PATM / (KXO_RU * T), dnu);
+            kr = kf / Kc;
+        }
+        double Rf = 1.0, Rr = 1.0;
+        for (int e = m->reac_ptr[i]; e < m->reac_ptr[i + 1]; ++e)
+            Rf *= int_pow(C[m->reac_sp[e]], m->reac_nu[e]);
+        for (int e = m->prod_ptr[i]; e < m->prod_ptr[i + 1]; ++e)
+            Rr *= int_pow(C[m->prod_sp[e]], m->prod_nu[e]);
+        const double qf = kf * Rf, qr = kr * Rr;
+        const double R = c * (qf - qr);
+        if (qf_out) qf_out[i] = qf;
+        if (qr_out) qr_out[i] = qr;
+        if (c_out) c_out[i] = c;
+        const double mag = fabs(c) * (fabs(qf) + fabs(qr));
+
+        /* every species touched by reaction i, each once, with its net nu */
+        for (int side = 0; side < 2; ++side) {
+            const int32_t *ptr = side ? m->prod_ptr : m->reac_ptr;
+            const int32_t *sp = side ? m->prod_sp : m->reac_sp;
+            for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+                const int k = sp[e];
+                int seen = 0; /* species already handled for this reaction */
+                for (int f = ptr[i]; f < e; ++f)
+                    if (sp[f] == k) seen = 1;
+                if (side == 1)
+                    for (int f = m->reac_ptr[i]; f < m->reac_ptr[i + 1]; ++f)
+                        if (m->reac_sp[f] == k) seen = 1;
+                if (seen) continue;
+                const int nu = net_nu(m, i, k);
+                if (nu == 0) continue;
+                neumaier_add(&sum[k], &cmp[k], nu * R);
+                scl[k] += abs(nu) * mag;
+            }
+        }
+    }
+    for (int k = 0; k < ns; ++k) {
+        wdot[k * ostride] = sum[k] + cmp[k];
+        if (scale) scale[k * ostride] = scl[k];
+    }
+}
+
+/* Production rates for n points.  T[n], p[n] (dyn/cm^2), Y[ns][n];
+ * wdot[ns][n] (mol/cm^3/s); scale[ns][n] may be NULL. */
+void kxo_production_rates(const kxo_mech *m, int64_t n, const double *T, const double *p,
+                          const double *Y, double *wdot, double *scale)
+{
+#pragma omp parallel num_threads(g_threads > 0 ? g_threads : kxo_max_threads())
+    {
+        double *ws = malloc(sizeof(double) * 5 * (size_t)m->ns);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            rates_point(m, T[i], p[i], Y + i, n, wdot + i, scale ? scale + i : NULL, n,
+                        NULL, NULL, NULL, ws);
+        free(ws);
+    }
+}
+
+/* One point with the per-reaction forward / reverse rates and modifiers
+ * exposed (qf[nr], qr[nr], c[nr]); Y, wdot, scale are contiguous [ns]. */
+void kxo_rates_detail(const kxo_mech *m, double T, double p, const double *Y,
+                      double *wdot, double *scale, double *qf, double *qr, double *c)
+{
+    double *ws = malloc(sizeof(double) * 5 * (size_t)m->ns);
+    rates_point(m, T, p, Y, 1, wdot, scale, 1, qf, qr, c, ws);
+    free(ws);
+}
+
+/* Forward rate constants k_f (k_inf for falloff) and, for falloff reactions,
+ * k_0, at temperature T (for closed-form tests). */
+void kxo_rate_constants(const kxo_mech *m, double T, double *kf, double *k0)
+{
+    for (int i = 0; i < m->nr; ++i) {
+        kf[i] = arrhenius(m->A[i], m->beta[i], m->Ea[i], T);
+        k0[i] = (m->rtype[i] == KXO_LINDEMANN || m->rtype[i] == KXO_TROE)
+                    ? arrhenius(m->A0[i], m->beta0[i], m->Ea0[i], T)
+                    : 0.0;
+    }
+}
+
+/* The Troe blend for parameters p4 at (T, Pr), for closed-form tests. */
+double kxo_troe_F(const double *p4, double T, double Pr) { return troe_F(p4, T, Pr); }
+
+/* --------------------------------------------------------------- transport */
+
+/* sum_{n=1..N} c_n x^(n-1), powers by repeated multiplication. */
+static double power_series(const double *c, int N, double x)
+{
+    double s = 0.0, xn = 1.0;
+    for (int n = 0; n < N; ++n) {
+        s += c[n] * xn;
+        xn *= x;
+    }
+    return s;
+}
+
+/* Pure-species eta_k, lambda_k and the binary D_kj at (T, p) from the ln T fits
+ * (App. A.3, "Polynomial fits"; eq:Dkj at one atmosphere, divided by p/p_atm).
+ * eta[ns], lam[ns], D[ns][ns] (any may be NULL). */
+void kxo_pure_transport(const kxo_mech *m, double T, double p, double *eta, double *lam,
+                        double *D)
+{
+    const int ns = m->ns, N = m->fit_order;
+    const double u = (log(T) - m->fit_L0) / m->fit_h;
+    for (int k = 0; k < ns; ++k) {
+        if (eta) eta[k] = power_series(m->visc_fit + (size_t)k * N, N, u);
+        if (lam) lam[k] = power_series(m->cond_fit + (size_t)k * N, N, u);
+    }
+    if (D)
+        for (int k = 0; k < ns; ++k)
+            for (int j = 0; j < ns; ++j) {
+                const double f = power_series(m->diff_fit + ((size_t)k * ns + j) * N, N, u);
+                D[(size_t)k * ns + j] = (m->diff_kind == 0) ? f * KXO_PATM / p
+                                                            : 1.0 / (f * p / KXO_PATM);
+            }
+}
+
+/* Wilke's phi_kj (Bird et al. form) for given pure viscosities. */
+static double wilke_phi(double Wk, double Wj, double eta_k, double eta_j)
+{
+    const double a = 1.0 + sqrt(eta_k / eta_j) * pow(Wj / Wk, 0.25);
+    return 1.0 / sqrt(8.0) * pow(1.0 + Wk / Wj, -0.5) * a * a;
+}
+
+double kxo_wilke_phi(const kxo_mech *m, double T, int k, int j)
+{
+    double *eta = malloc(sizeof(double) * m->ns);
+    kxo_pure_transport(m, T, KXO_PATM, eta, NULL, NULL);
+    const double r = wilke_phi(species_weight(m, k), species_weight(m, j), eta[k], eta[j]);
+    free(eta);
+    return r;
+}
+
+static void transport_point(const kxo_mech *m, double T, double p, const double *Y,
+                            int64_t stride, double *mu, double *lam_out, double *Dmix,
+                            int64_t ostride, double *ws)
+{
+    const int ns = m->ns;
+    double *X = ws, *eta = ws + ns, *lam = ws + 2 * ns, *W = ws + 3 * ns,
+           *D = ws + 4 * ns; /* D: ns*ns */
+
+    double inv_wbar = 0.0;
+    for (int k = 0; k < ns; ++k) {
+        W[k] = species_weight(m, k);
+        inv_wbar += Y[k * stride] / W[k];
+    }
+    for (int k = 0; k < ns; ++k) X[k] = Y[k * stride] / W[k] / inv_wbar;
+    double wbar = 0.0; /* W-bar = sum_k X_k W_k */
+    for (int k = 0; k < ns; ++k) wbar += X[k] * W[k];
+
+    kxo_pure_transport(m, T, p, eta, lam, D);
+
+    /* Wilke / Bird mixture viscosity */
+    double visc = 0.0;
+    for (int k = 0; k < ns; ++k) {
+        double den = 0.0;
+        for (int j = 0; j < ns; ++j) den += X[j] * wilke_phi(W[k], W[j], eta[k], eta[j]);
+        visc += X[k] * eta[k] / den;
+    }
+    *mu = visc;
+
+    /* Mathur combination averaging */
+    double s1 = 0.0, s2 = 0.0;
+    for (int k = 0; k < ns; ++k) {
+        s1 += X[k] * lam[k];
+        s2 += X[k] / lam[k];
+    }
+    *lam_out = 0.5 * (s1 + 1.0 / s2);
+
+    /* eq:mix_diff */
+    for (int k = 0; k < ns; ++k) {
+        double s = 0.0;
+        for (int j = 0; j < ns; ++j)
+            if (j != k) s += X[j] / D[(size_t)k * ns + j];
+        Dmix[k * ostride] = (s == 0.0) ? D[(size_t)k * ns + k]
+                                       : (wbar - X[k] * W[k]) / wbar / s;
+    }
+}
+
+/* Mixture-averaged transport for n points: mu[n] (g/cm/s), lambda[n]
+ * (erg/cm/s/K), Dmix[ns][n] (cm^2/s). */
+void kxo_transport(const kxo_mech *m, int64_t n, const double *T, const double *p,
+                   const double *Y, double *mu, double *lam, double *Dmix)
+{
+    const size_t wsz = (size_t)m->ns * (4 + (size_t)m->ns);
+#pragma omp parallel num_threads(g_threads > 0 ? g_threads : kxo_max_threads())
+    {
+        double *ws = malloc(sizeof(double) * wsz);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            transport_point(m, T[i], p[i], Y + i, n, mu + i, lam + i, Dmix + i, n, ws);
+        free(ws);
+    }
+}

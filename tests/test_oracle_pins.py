@@ -1,0 +1,488 @@
+"""Pins of the CPU oracle against what the paper's equations and the physics fix.
+
+Each test names the passage of the paper (Appendix A of arXiv 2411.02640) it
+pins and the kind of slip it would catch.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2411_02640_amd import inputs as I
+
+from . import tiny_mechs as TM
+
+U = 2.0 ** -53
+
+
+def _states(ns, n, seed=11, p_atm=(1.0, 40.0), alpha=0.3):
+    return I.make_states(ns, I.StateSpec(n, seed=seed, p_atm_range=p_atm,
+                                         dirichlet_alpha=alpha))
+
+
+# ----------------------------------------------------------------- thermo (A.1)
+@pytest.mark.parametrize("name", ["mech9", "mech53"])
+def test_gibbs_closed_form_equals_h_minus_s(name, request):
+    """eq:Ck against eq:H_RT - eq:S_R (independently written forms): catches a
+    wrong divisor or sign in any of the three."""
+    om = O.OracleMech(request.getfixturevalue(name))
+    for T in (300.0, 650.0, 999.9, 1000.0, 1700.0, 2800.0):
+        cp, h, s, g = om.thermo(T)
+        np.testing.assert_allclose(g, h - s, rtol=0, atol=1e-12 * max(1.0, np.abs(g).max()))
+
+
+def test_cp_is_temperature_derivative_of_h_and_s(mech53):
+    """dH/dT = Cp and dS/dT = Cp/T by central differences (eq:H_RT, eq:S_R)."""
+    om = O.OracleMech(mech53)
+    for T in (400.0, 800.0, 1300.0, 2500.0):
+        d = 1e-3
+        hp = om.thermo(T + d)[1] * (T + d)
+        hm = om.thermo(T - d)[1] * (T - d)
+        sp_, sm = om.thermo(T + d)[2], om.thermo(T - d)[2]
+        cp = om.thermo(T)[0]
+        np.testing.assert_allclose((hp - hm) / (2 * d), cp, rtol=1e-6)
+        np.testing.assert_allclose((sp_ - sm) / (2 * d) * T, cp, rtol=1e-6)
+
+
+def test_reference_state_targets(mech53):
+    """H(298.15)/R and S(298.15)/R equal the targets the generator fitted to."""
+    om = O.OracleMech(mech53)
+    _, h, s, _ = om.thermo(298.15)
+    np.testing.assert_allclose(h * 298.15, mech53["_h298_over_r"], rtol=1e-12, atol=1e-8)
+    np.testing.assert_allclose(s, mech53["_s298_over_r"], rtol=1e-12)
+
+
+def test_range_switch_continuity(mech53):
+    """Both NASA ranges agree at T_mid (low range below, high range from T_mid)."""
+    om = O.OracleMech(mech53)
+    below = om.thermo(np.nextafter(1000.0, 0.0))
+    at = om.thermo(1000.0)
+    for a, b in zip(below, at):
+        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-9)
+
+
+def test_mixture_thermo(mech9):
+    """cp = sum Y_k cp_k reduces to cp_k for a pure species; monatomic species
+    have Cp = 5/2 R."""
+    om = O.OracleMech(mech9)
+    ns = om.ns
+    T = np.full(ns, 1234.5)
+    Y = np.eye(ns)
+    cpk, hk, cp = om.mixture_thermo(T, Y)
+    np.testing.assert_allclose(cp, np.diag(cpk), rtol=1e-15)
+    W = mech9["composition"] @ mech9["elem_mass"]
+    for k in (0, 1):  # the two atoms
+        assert cpk[k, 0] == pytest.approx(2.5 * O.RU / W[k], rel=1e-10)
+
+
+# ----------------------------------------------------------------- kinetics (A.2)
+@pytest.mark.parametrize("name", ["mech9", "mech53"])
+def test_element_and_mass_conservation(name, request):
+    """sum_k a_ke wdot_k = 0 and sum_k W_k wdot_k = 0 (every reaction balanced):
+    catches a flipped side, a wrong nu or a mis-indexed species."""
+    m = request.getfixturevalue(name)
+    om = O.OracleMech(m)
+    T, p, Y = _states(om.ns, 2000)
+    w, s = om.production_rates(T, p, Y)
+    comp = m["composition"].astype(float)
+    for e in range(2):
+        resid = np.abs(comp[:, e] @ w)
+        scale = comp[:, e] @ s
+        assert (resid <= 64 * U * scale).all()
+    W = comp @ m["elem_mass"]
+    assert (np.abs(W @ w) <= 64 * U * (W @ s)).all()
+    assert (w[-1] == 0.0).all()  # the inert diluent
+
+
+@pytest.mark.parametrize("name", ["mech9", "mech53"])
+def test_zero_net_rate_at_constructed_equilibrium(name, request):
+    """At C_k = (p_atm/RT) exp(-G_k/RT + sum_e lam_e a_ke) every reaction has
+    q_f = q_r (eq:K_p, K_c = K_p (p_atm/RT)^sum nu): catches a sign of dG, a
+    wrong (p_atm/RT) power or a swapped reactant/product side."""
+    m = request.getfixturevalue(name)
+    om = O.OracleMech(m)
+    T, p, Y = O.equilibrium_states(om, 60, seed=5, perturb=0.0)
+    covered = np.zeros(om.nr, bool)
+    for i in range(T.size):
+        d = om.rates_detail(T[i], p[i], Y[:, i])
+        # equilibrium concentrations of high-G species underflow at low T;
+        # such reactions have q_f = q_r = 0 and are skipped
+        ok = (d["qf"] > 1e-250) & (d["qr"] > 1e-250)
+        covered |= ok
+        rel = np.abs(d["qf"][ok] - d["qr"][ok]) / d["qf"][ok]
+        assert rel.max() < 1e-11, (i, rel.max())
+        assert (np.abs(d["wdot"]) <= 1e-11 * d["scale"] + 1e-280).all()
+    assert covered.mean() > 0.9
+
+
+def test_perturbed_equilibrium_net_rate_is_small_and_signed():
+    """A 1e-6 perturbation of an equilibrium state gives |q| ~ 1e-6 (q_f + q_r)."""
+    m = TM.abx_mechanism()
+    om = O.OracleMech(m)
+    T, p, Y = O.equilibrium_states(om, 20, seed=6, perturb=1e-6)
+    for i in range(T.size):
+        d = om.rates_detail(T[i], p[i], Y[:, i])
+        r = np.abs(d["qf"] - d["qr"]) / (d["qf"] + d["qr"])
+        assert r.max() < 1e-5 and r.max() > 1e-9
+
+
+def test_arrhenius_closed_forms(oracle_lib):
+    """eq:arrhenius / eq:k_f: beta = E = 0 gives A exactly; E_a with
+    E_R/T = ln 2 halves it; integer beta multiplies by T^beta."""
+    T = 1000.0
+    cases = [(0.0, 0.0, 1.0), (0.0, TM.ea_for_half(T), 0.5), (1.0, 0.0, T),
+             (-1.0, 0.0, 1.0 / T), (2.0, 0.0, T * T), (2.0, TM.ea_for_half(T), 0.5 * T * T)]
+    for beta, Ea, factor in cases:
+        m = TM.single_reaction_mech(0, A=3.3e12, beta=beta, Ea=Ea)
+        kf, _ = O.OracleMech(m).rate_constants(T)
+        assert kf[0] == pytest.approx(3.3e12 * factor, rel=4 * U), (beta, Ea)
+    m = TM.single_reaction_mech(0, A=3.3e12)
+    assert O.OracleMech(m).rate_constants(T)[0][0] == 3.3e12
+
+
+def _single_state(T=1200.0, p_atm=2.0):
+    Y = np.array([0.2, 0.3, 0.1, 0.4])
+    return T, p_atm * O.PATM, Y
+
+
+def test_lindemann_pressure_limits():
+    """P_r -> inf gives k_f -> k_inf; P_r -> 0 gives k_f -> k_0 [M] (App. A.2
+    falloff): catches swapped k_0/k_inf or a missing [X] in P_r."""
+    T, p, Y = _single_state()
+    Mconc = p / (O.RU * T)
+    hi = TM.single_reaction_mech(2, A=1e12, A0=1e40)
+    d = O.OracleMech(hi).rates_detail(T, p, Y)
+    assert d["c"][0] == pytest.approx(1.0, rel=1e-12)
+    lo = TM.single_reaction_mech(2, A=1e12, A0=1e-20)
+    om = O.OracleMech(lo)
+    d = om.rates_detail(T, p, Y)
+    kf, k0 = om.rate_constants(T)
+    assert d["c"][0] * kf[0] == pytest.approx(k0[0] * Mconc, rel=1e-12)
+
+
+def test_troe_blend_closed_forms(oracle_lib):
+    """eq:blend with base-10 logs: F_cent = 1 gives F = 1 (Lindemann); with
+    F_cent = 1/2 the blend equals F_cent at log10 P_r = -c and tends to
+    F_cent^(1/(1 + 1/d^2)) far from the centre (d = 0.14)."""
+    T = 1000.0
+    one = [0.0, 1e300, 1.0, np.nan]
+    for Pr in (1e-8, 0.3, 1.0, 7.0, 1e9):
+        assert O.troe_F(one, T, Pr) == pytest.approx(1.0, rel=1e-15)
+    half = [1.0, 100.0, T / math.log(2.0), np.nan]  # alpha e^{-T/T*} = 1/2
+    lfc = math.log10(0.5)
+    c = -0.4 - 0.67 * lfc
+    assert O.troe_F(half, T, 10.0 ** (-c)) == pytest.approx(0.5, rel=1e-14)
+    lim = 0.5 ** (1.0 / (1.0 + 1.0 / 0.14**2))
+    assert O.troe_F(half, T, 1e300) == pytest.approx(lim, rel=2e-3)
+    assert O.troe_F(half, T, 1e-300) == pytest.approx(lim, rel=2e-3)
+    # the T** term adds exp(-T**/T) to F_cent: with alpha = 0, T*** huge and
+    # T** = T ln 2, F_cent = 1.5
+    three_half = [0.0, 1e300, 1.0, T * math.log(2.0)]
+    lfc = math.log10(1.5)
+    c = -0.4 - 0.67 * lfc
+    assert O.troe_F(three_half, T, 10.0 ** (-c)) == pytest.approx(1.5, rel=1e-14)
+
+
+def test_third_body_single_collider():
+    """[X]_i = [X_m] when only species m collides (eff_default 0, alpha_m 1)."""
+    T, p, Y = _single_state()
+    m = TM.single_reaction_mech(1, A=1e15, eff_default=0.0, eff={TM.B_: 1.0})
+    d = O.OracleMech(m).rates_detail(T, p, Y)
+    W = m["composition"] @ m["elem_mass"]
+    X = Y / W / (Y / W).sum()
+    assert d["c"][0] == pytest.approx(X[TM.B_] * p / (O.RU * T), rel=1e-14)
+
+
+# --- brute force: an independent 50-digit evaluation of App. A.2 -------------
+def _mp_rates(mech, T, p, Y):
+    import mpmath as mp
+    mp.mp.dps = 50
+    T = mp.mpf(T)
+    p = mp.mpf(p)
+    Ru = mp.mpf("8.31446261815324e7")
+    Rc = mp.mpf("8.31446261815324") / mp.mpf("4.184")
+    patm = mp.mpf(1013250)
+    ns, nr = mech["n_species"], mech["n_reactions"]
+    W = [sum(mp.mpf(int(mech["composition"][k][e])) * mp.mpf(mech["elem_mass"][e])
+             for e in range(3)) for k in range(ns)]
+    Yk = [mp.mpf(y) for y in Y]
+    Wbar = 1 / sum(Yk[k] / W[k] for k in range(ns))
+    conc = [Yk[k] * Wbar / W[k] * p / (Ru * T) for k in range(ns)]
+
+    def gibbs(k):
+        a = [mp.mpf(x) for x in (mech["nasa_lo"][k] if T < 1000 else mech["nasa_hi"][k])]
+        H = a[0] + a[1] * T / 2 + a[2] * T**2 / 3 + a[3] * T**3 / 4 + a[4] * T**4 / 5 + a[5] / T
+        S = a[0] * mp.log(T) + a[1] * T + a[2] * T**2 / 2 + a[3] * T**3 / 3 + a[4] * T**4 / 4 + a[6]
+        return H - S
+
+    G = [gibbs(k) for k in range(ns)]
+    wdot = [mp.mpf(0)] * ns
+    qs = []
+    for i in range(nr):
+        reac = [(int(mech["reac_sp"][e]), int(mech["reac_nu"][e]))
+                for e in range(mech["reac_ptr"][i], mech["reac_ptr"][i + 1])]
+        prod = [(int(mech["prod_sp"][e]), int(mech["prod_nu"][e]))
+                for e in range(mech["prod_ptr"][i], mech["prod_ptr"][i + 1])]
+        k = lambda A, b, E: mp.mpf(A) * T ** mp.mpf(b) * mp.e ** (-(mp.mpf(E) / Rc) / T)
+        kf = k(mech["A"][i], mech["beta"][i], mech["Ea"][i])
+        alpha = [mp.mpf(mech["eff_default"][i])] * ns
+        for e in range(mech["eff_ptr"][i], mech["eff_ptr"][i + 1]):
+            alpha[int(mech["eff_sp"][e])] = mp.mpf(mech["eff_val"][e])
+        Xi = sum(alpha[s] * conc[s] for s in range(ns))
+        t = int(mech["rxn_type"][i])
+        if t == 0:
+            c = mp.mpf(1)
+        elif t == 1:
+            c = Xi
+        else:
+            k0 = k(mech["A0"][i], mech["beta0"][i], mech["Ea0"][i])
+            Pr = k0 * Xi / kf
+            F = mp.mpf(1)
+            if t == 3:
+                al, t3, t1, t2 = [mp.mpf(x) if not np.isnan(x) else None
+                                  for x in mech["troe"][i]]
+                Fc = (1 - al) * mp.e ** (-T / t3) + al * mp.e ** (-T / t1)
+                if t2 is not None:
+                    Fc += mp.e ** (-t2 / T)
+                cc = mp.mpf("-0.4") - mp.mpf("0.67") * mp.log10(Fc)
+                nn = mp.mpf("0.75") - mp.mpf("1.27") * mp.log10(Fc)
+                x = mp.log10(Pr) + cc
+                F = mp.mpf(10) ** (mp.log10(Fc) / (1 + (x / (nn - mp.mpf("0.14") * x)) ** 2))
+            c = Pr / (1 + Pr) * F
+        dnu = sum(v for _, v in prod) - sum(v for _, v in reac)
+        dG = sum(v * G[s] for s, v in prod) - sum(v * G[s] for s, v in reac)
+        Kc = mp.e ** (-dG) * (patm / (Ru * T)) ** dnu
+        fwd = kf * mp.fprod(conc[s] ** v for s, v in reac)
+        rev = kf / Kc * mp.fprod(conc[s] ** v for s, v in prod)
+        q = c * (fwd - rev)
+        qs.append((fwd, rev, c))
+        for s, v in reac:
+            wdot[s] -= v * q
+        for s, v in prod:
+            wdot[s] += v * q
+    return [float(x) for x in wdot], qs
+
+
+def test_brute_force_three_species_mpmath():
+    m = TM.abx_mechanism()
+    om = O.OracleMech(m)
+    rng = np.random.default_rng(3)
+    for T in (450.0, 999.0, 1001.0, 1800.0, 2700.0):
+        for p_atm in (0.5, 3.0, 30.0):
+            Y = rng.dirichlet(np.ones(4))
+            d = om.rates_detail(T, p_atm * O.PATM, Y)
+            wref, qs = _mp_rates(m, T, p_atm * O.PATM, Y)
+            for i, (f, r, c) in enumerate(qs):
+                assert d["qf"][i] == pytest.approx(float(f), rel=1e-13)
+                assert d["qr"][i] == pytest.approx(float(r), rel=1e-13)
+                assert d["c"][i] == pytest.approx(float(c), rel=1e-13)
+            err = np.abs(d["wdot"] - np.array(wref))
+            assert (err <= 1e-13 * d["scale"]).all(), (T, p_atm, err / d["scale"])
+
+
+# --- invariances --------------------------------------------------------------
+def _scaled(m, factor):
+    m2 = dict(m)
+    m2["A"] = m["A"] * factor
+    m2["A0"] = m["A0"] * factor
+    return m2
+
+
+def test_linearity_in_prefactor(mech53):
+    """Scaling every A (and A_0, so P_r is unchanged) by c scales wdot by c."""
+    om = O.OracleMech(mech53)
+    om2 = O.OracleMech(_scaled(mech53, 3.7))
+    T, p, Y = _states(om.ns, 500)
+    w, s = om.production_rates(T, p, Y)
+    w2 = om2.production_rates(T, p, Y, with_scale=False)
+    assert (np.abs(w2 - 3.7 * w) <= 1e-13 * 3.7 * s).all()
+
+
+def test_duplicated_half_reactions(mech9):
+    """Each reaction split into two copies with half the prefactor leaves wdot
+    unchanged (sum over reactions in the net production rate)."""
+    m = mech9
+    nr = m["n_reactions"]
+    idx = np.repeat(np.arange(nr), 2)
+    d = dict(m)
+    for key in ("rxn_type", "reversible", "A", "beta", "Ea", "A0", "beta0", "Ea0", "troe",
+                "eff_default"):
+        d[key] = m[key][idx]
+    d["A"] = d["A"] / 2
+    d["A0"] = d["A0"] / 2
+    for side in ("reac", "prod", "eff"):
+        ptr = m[side + "_ptr"]
+        sp, nu = [], []
+        newptr = [0]
+        for i in idx:
+            sl = slice(ptr[i], ptr[i + 1])
+            sp.append(m[side + "_sp"][sl])
+            nu.append(m[side + ("_nu" if side != "eff" else "_val")][sl])
+            newptr.append(newptr[-1] + ptr[i + 1] - ptr[i])
+        d[side + "_ptr"] = np.array(newptr, np.int32)
+        d[side + "_sp"] = np.concatenate(sp).astype(np.int32)
+        d[side + ("_nu" if side != "eff" else "_val")] = np.concatenate(nu)
+    d["n_reactions"] = 2 * nr
+    T, p, Y = _states(m["n_species"], 500)
+    w, s = O.OracleMech(m).production_rates(T, p, Y)
+    w2 = O.OracleMech(d).production_rates(T, p, Y, with_scale=False)
+    assert (np.abs(w2 - w) <= 1e-13 * s).all()
+
+
+def _subset(m, keep):
+    keep = np.asarray(keep)
+    d = dict(m)
+    for key in ("rxn_type", "reversible", "A", "beta", "Ea", "A0", "beta0", "Ea0", "troe",
+                "eff_default"):
+        d[key] = m[key][keep]
+    for side, val in (("reac", "_nu"), ("prod", "_nu"), ("eff", "_val")):
+        ptr = m[side + "_ptr"]
+        sp, nu, newptr = [], [], [0]
+        for i in keep:
+            sl = slice(ptr[i], ptr[i + 1])
+            sp.append(m[side + "_sp"][sl])
+            nu.append(m[side + val][sl])
+            newptr.append(newptr[-1] + ptr[i + 1] - ptr[i])
+        d[side + "_ptr"] = np.array(newptr, np.int32)
+        d[side + "_sp"] = np.concatenate(sp).astype(np.int32) if sp else np.zeros(0, np.int32)
+        d[side + val] = np.concatenate(nu) if nu else np.zeros(0)
+    d["n_reactions"] = len(keep)
+    return d
+
+
+def test_pressure_homogeneity(mech53):
+    """Bimolecular elementary reactions (2 <=> 2, sum nu = 0): wdot ~ p^2 at
+    fixed T and Y; termolecular third-body association ~ p^3 forward."""
+    m = _subset(mech53, np.flatnonzero(mech53["rxn_type"] == 0))
+    om = O.OracleMech(m)
+    T, p, Y = _states(om.ns, 300)
+    w, s = om.production_rates(T, p, Y)
+    w2 = om.production_rates(T, 2 * p, Y, with_scale=False)
+    assert (np.abs(w2 - 4 * w) <= 1e-13 * 4 * s).all()
+
+
+def test_species_and_reaction_permutation(mech9):
+    m = mech9
+    ns, nr = m["n_species"], m["n_reactions"]
+    rng = np.random.default_rng(8)
+    sperm = rng.permutation(ns)           # new species j is old species sperm[j]
+    inv = np.argsort(sperm)
+    rperm = rng.permutation(nr)
+    d = _subset(m, rperm)
+    for key in ("composition", "nasa_lo", "nasa_hi", "t_mid", "visc_fit", "cond_fit"):
+        d[key] = m[key][sperm]
+    d["diff_fit"] = m["diff_fit"][sperm][:, sperm]
+    for key in ("reac_sp", "prod_sp", "eff_sp"):
+        d[key] = inv[d[key]].astype(np.int32)
+    T, p, Y = _states(ns, 400)
+    w, s = O.OracleMech(m).production_rates(T, p, Y)
+    w2 = O.OracleMech(d).production_rates(T, p, Y[sperm], with_scale=False)
+    assert (np.abs(w2 - w[sperm]) <= 1e-13 * s[sperm]).all()
+    mu, lam, Dm = O.OracleMech(m).transport(T, p, Y)
+    mu2, lam2, Dm2 = O.OracleMech(d).transport(T, p, Y[sperm])
+    np.testing.assert_allclose(mu2, mu, rtol=1e-13)
+    np.testing.assert_allclose(lam2, lam, rtol=1e-13)
+    np.testing.assert_allclose(Dm2, Dm[sperm], rtol=1e-13)
+
+
+# ----------------------------------------------------------------- transport (A.3)
+def test_pure_species_limits(mech53):
+    """X_k = 1 gives mu = eta_k (phi_kk = 1) and lambda = lambda_k (Mathur)."""
+    om = O.OracleMech(mech53)
+    ns = om.ns
+    for T in (350.0, 1500.0):
+        Tn = np.full(ns, T)
+        pn = np.full(ns, 2.0 * O.PATM)
+        mu, lam, Dm = om.transport(Tn, pn, np.eye(ns))
+        eta, lk, D = om.pure_transport(T, 2.0 * O.PATM)
+        np.testing.assert_allclose(mu, eta, rtol=1e-14)
+        np.testing.assert_allclose(lam, lk, rtol=1e-14)
+        # the fallback D_kk for the pure species itself
+        np.testing.assert_allclose(np.diag(Dm), np.diag(D), rtol=1e-15)
+        # every other species is a trace species in pure k: D_jm = D_jk
+        for k in (0, 7, ns - 1):
+            others = np.arange(ns) != k
+            np.testing.assert_allclose(Dm[others, k], D[others, k], rtol=1e-14)
+
+
+def test_wilke_reciprocity_pins_mass_exponent(mech9):
+    """Wilke's factors satisfy phi_jk = phi_kj (eta_j/eta_k)(W_k/W_j) (Bird,
+    Stewart & Lightfoot); the (W_k/W_j)^(1/4) printed in the appendix would not."""
+    om = O.OracleMech(mech9)
+    W = mech9["composition"] @ mech9["elem_mass"]
+    T = 1100.0
+    eta = om.pure_transport(T, O.PATM)[0]
+    for k in range(om.ns):
+        assert om.wilke_phi(T, k, k) == pytest.approx(1.0, rel=1e-15)
+        for j in range(om.ns):
+            lhs = om.wilke_phi(T, j, k)
+            rhs = om.wilke_phi(T, k, j) * eta[j] / eta[k] * W[k] / W[j]
+            assert lhs == pytest.approx(rhs, rel=1e-13)
+
+
+def test_equal_species_mixture():
+    """Two species with the same W and eta: any mixture has mu = eta; with the
+    same W the mixture D_km of the binary pair equals D_kj."""
+    comp = [(1, 1, 0), (1, 1, 0), (0, 0, 2)]
+    nasa = [[3.5, 0, 0, 0, 0, 0, 4.0]] * 3
+    visc = np.array([[2e-4, 5e-5, 1e-6, 2e-7, 0.0]] * 3)
+    diff = np.tile([1.1, 0.7, 0.2, 0.01, 0.0], (3, 3, 1))
+    m = TM.build(comp, nasa, [], visc=visc, diff=diff)
+    om = O.OracleMech(m)
+    Y = np.array([[0.3, 0.7, 0.0], [0.9, 0.1, 0.0]]).T.copy()
+    T = np.array([800.0, 2000.0])
+    p = np.array([1.0, 5.0]) * O.PATM
+    mu, lam, Dm = om.transport(T, p, Y)
+    for i in range(2):
+        eta, _, D = om.pure_transport(T[i], p[i])
+        assert mu[i] == pytest.approx(eta[0], rel=1e-14)
+        assert Dm[0, i] == pytest.approx(D[0, 1], rel=1e-14)
+
+
+def test_diffusion_pressure_scaling_and_symmetry(mech53):
+    """D_kj ~ 1/p exactly (eq:Dkj at 1 atm divided by p); eta and lambda do not
+    depend on p; the D_kj table is symmetric."""
+    om = O.OracleMech(mech53)
+    T, p, Y = _states(om.ns, 200)
+    mu, lam, Dm = om.transport(T, p, Y)
+    mu2, lam2, Dm2 = om.transport(T, 2 * p, Y)
+    np.testing.assert_array_equal(mu, mu2)
+    np.testing.assert_array_equal(lam, lam2)
+    np.testing.assert_allclose(Dm2, Dm / 2, rtol=4 * U)
+    eta, lk, D = om.pure_transport(1234.0, 3.0 * O.PATM)
+    np.testing.assert_array_equal(D, D.T)
+
+
+def test_trace_species_blanc_limit(mech53):
+    """X_k -> 0: D_km -> (sum_{j != k} X_j / D_kj)^-1 (Blanc's law)."""
+    om = O.OracleMech(mech53)
+    ns = om.ns
+    rng = np.random.default_rng(4)
+    Y = rng.dirichlet(np.ones(ns))
+    Y[5] = 0.0
+    T, p = 1500.0, 4.0 * O.PATM
+    _, _, Dm = om.transport(np.array([T]), np.array([p]), Y[:, None].copy())
+    _, _, D = om.pure_transport(T, p)
+    W = mech53["composition"] @ mech53["elem_mass"]
+    X = Y / W / (Y / W).sum()
+    blanc = 1.0 / np.sum(np.delete(X / D[5], 5))
+    assert Dm[5, 0] == pytest.approx(blanc, rel=1e-13)
+
+
+def test_fit_evaluation_matches_kinetic_theory(mech53):
+    """The oracle's evaluation of the ln T fits reproduces the independent
+    kinetic-theory values the fits were made from (catches a wrong basis
+    shift/scale or a reversed coefficient order)."""
+    om = O.OracleMech(mech53)
+    W = mech53["composition"] @ mech53["elem_mass"]
+    for T in (420.0, 1111.0, 2600.0):
+        eta, lam, D = om.pure_transport(T, O.PATM)
+        ref = np.array([I._pure_viscosity(T, W[k], mech53["_sigma_cm"][k],
+                                          mech53["_eps_k"][k]) for k in range(om.ns)])
+        np.testing.assert_allclose(eta, ref, rtol=5e-3)
+        k, j = 3, 17
+        Dref = I._binary_diffusion_1atm(T, W[k], W[j], mech53["_sigma_cm"][k],
+                                        mech53["_sigma_cm"][j], mech53["_eps_k"][k],
+                                        mech53["_eps_k"][j])
+        assert D[k, j] == pytest.approx(Dref, rel=3e-2)

@@ -1,0 +1,105 @@
+"""Hand-built tiny mechanisms for closed-form and brute-force checks."""
+import math
+
+import numpy as np
+
+RCAL = 8.31446261815324 / 4.184
+
+
+def _csr(lists):
+    ptr, sp, nu = [0], [], []
+    for lst in lists:
+        for s, v in lst:
+            sp.append(s)
+            nu.append(v)
+        ptr.append(len(sp))
+    return np.array(ptr, np.int32), np.array(sp, np.int32), np.array(nu, np.int32)
+
+
+def build(species_comp, nasa, reactions, visc=None, cond=None, diff=None):
+    """reactions: list of dicts with keys type, reac [(sp, nu)], prod [(sp, nu)],
+    A, beta, Ea and optionally A0, beta0, Ea0, troe (4), eff {sp: alpha},
+    eff_default."""
+    ns = len(species_comp)
+    nr = len(reactions)
+    comp = np.array(species_comp, np.int32)
+    nasa = np.asarray(nasa, np.float64)
+    rp, rs, rn = _csr([r["reac"] for r in reactions])
+    pp, ps, pn = _csr([r["prod"] for r in reactions])
+    eff_ptr, eff_sp, eff_val = [0], [], []
+    for r in reactions:
+        for s, a in sorted(r.get("eff", {}).items()):
+            eff_sp.append(s)
+            eff_val.append(a)
+        eff_ptr.append(len(eff_sp))
+    fo = 5
+    if visc is None:
+        visc = np.tile([2e-4, 5e-5, 1e-6, 0.0, 0.0], (ns, 1))
+    if cond is None:
+        cond = np.tile([5e3, 2e3, 1e2, 0.0, 0.0], (ns, 1))
+    if diff is None:
+        diff = np.tile([1.0, 0.8, 0.2, 0.0, 0.0], (ns, ns, 1))
+    return {
+        "name": "tiny", "n_species": ns, "n_reactions": nr, "n_elements": comp.shape[1],
+        "elem_mass": np.array([1.008, 15.999, 14.007][: comp.shape[1]]),
+        "composition": comp, "nasa_lo": nasa.copy(), "nasa_hi": nasa.copy(),
+        "t_mid": np.full(ns, 1000.0),
+        "rxn_type": np.array([r["type"] for r in reactions], np.int32),
+        "reversible": np.array([r.get("rev", 1) for r in reactions], np.int32),
+        "reac_ptr": rp, "reac_sp": rs, "reac_nu": rn,
+        "prod_ptr": pp, "prod_sp": ps, "prod_nu": pn,
+        "A": np.array([r["A"] for r in reactions], float),
+        "beta": np.array([r["beta"] for r in reactions], float),
+        "Ea": np.array([r["Ea"] for r in reactions], float),
+        "A0": np.array([r.get("A0", 0.0) for r in reactions], float),
+        "beta0": np.array([r.get("beta0", 0.0) for r in reactions], float),
+        "Ea0": np.array([r.get("Ea0", 0.0) for r in reactions], float),
+        "troe": np.array([r.get("troe", [0, 0, 0, 0]) for r in reactions], float),
+        "eff_ptr": np.array(eff_ptr, np.int32), "eff_sp": np.array(eff_sp, np.int32),
+        "eff_val": np.array(eff_val, float),
+        "eff_default": np.array([r.get("eff_default", 1.0) for r in reactions], float),
+        "fit_order": fo, "fit_L0": 7.0, "fit_h": 1.2, "diff_fit_kind": 0,
+        "visc_fit": np.asarray(visc, float), "cond_fit": np.asarray(cond, float),
+        "diff_fit": np.asarray(diff, float),
+    }
+
+
+A_, B_, AB_, D_ = 0, 1, 2, 3
+ABX_COMP = [(1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 2)]
+ABX_NASA = [
+    [2.5, 0.0, 0.0, 0.0, 0.0, 2.5e4, 4.2],
+    [2.5, 0.0, 0.0, 0.0, 0.0, 2.9e4, 5.1],
+    [3.3, 1.1e-3, -3.0e-7, 4.0e-11, -2.0e-15, 4.5e3, 3.9],
+    [3.5, 2.0e-4, 0.0, 0.0, 0.0, -1.0e3, 4.0],
+]
+
+
+def abx_mechanism():
+    """{A, B, AB, D}: A + B <=> AB as elementary, three-body, Troe and a
+    single-collider Lindemann reaction, plus AB + A <=> B + 2 A."""
+    rx = [
+        dict(type=0, reac=[(A_, 1), (B_, 1)], prod=[(AB_, 1)], A=3.0e13, beta=0.4, Ea=1.2e3),
+        dict(type=1, reac=[(A_, 1), (B_, 1)], prod=[(AB_, 1)], A=2.0e15, beta=-0.8, Ea=0.0,
+             eff={B_: 2.5, D_: 0.7}),
+        dict(type=3, reac=[(A_, 1), (B_, 1)], prod=[(AB_, 1)], A=1.5e12, beta=0.3, Ea=5.0e3,
+             A0=4.0e18, beta0=-1.1, Ea0=2.0e3, troe=[0.62, 150.0, 1800.0, 4500.0],
+             eff={AB_: 3.0}),
+        dict(type=0, reac=[(AB_, 1), (A_, 1)], prod=[(B_, 1), (A_, 2)], A=7.0e14, beta=0.0,
+             Ea=3.1e4),
+        dict(type=2, reac=[(A_, 1), (B_, 1)], prod=[(AB_, 1)], A=9.0e12, beta=0.1, Ea=800.0,
+             A0=2.0e17, beta0=-0.5, Ea0=0.0, eff_default=0.0, eff={B_: 1.0}),
+    ]
+    return build(ABX_COMP, ABX_NASA, rx)
+
+
+def single_reaction_mech(rtype, A=1e13, beta=0.0, Ea=0.0, A0=0.0, beta0=0.0, Ea0=0.0,
+                         troe=(0, 0, 0, 0), eff=None, eff_default=1.0):
+    rx = [dict(type=rtype, reac=[(A_, 1), (B_, 1)], prod=[(AB_, 1)], A=A, beta=beta, Ea=Ea,
+               A0=A0, beta0=beta0, Ea0=Ea0, troe=list(troe), eff=eff or {},
+               eff_default=eff_default)]
+    return build(ABX_COMP, ABX_NASA, rx)
+
+
+def ea_for_half(T):
+    """E_a (cal/mol) with exp(-E_a/(R T)) = 1/2 at temperature T."""
+    return math.log(2.0) * RCAL * T
