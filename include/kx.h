@@ -1,0 +1,186 @@
+/*
+ * kx.h -- C ABI of the MI355X (gfx950) per-grid-point chemistry library.
+ *
+ * The library evaluates, independently for every grid point of a reacting-flow
+ * field, the quantities of Danciu & Frouzakis, "KinetiX: A performance
+ * portable code generator for chemical kinetics and transport properties"
+ * (arXiv 2411.02640), Appendix A:
+ *   - species net production rates wdot_k = sum_i nu_ki R_i (App. A.2) from
+ *     modified-Arrhenius forward rates (eq:arrhenius), equilibrium constants
+ *     from NASA-7 Gibbs energies (eq:K_p, eq:Ck), third-body and
+ *     Lindemann / Troe falloff modifiers (eq:c_i, eq:blend) and the law of mass
+ *     action (eq:r_i);
+ *   - mixture-averaged transport (App. A.3): Wilke / Bird viscosity, Mathur
+ *     conductivity and mixture-averaged diffusion coefficients (eq:mix_diff)
+ *     from ln T polynomial fits of the pure-species viscosity, conductivity and
+ *     binary diffusion coefficients (eq:Dkj);
+ *   - mixture thermodynamics cp_k, h_k and cp (App. A.1).
+ *
+ * Conventions shared by every entry point
+ *   Units      cgs: T in K, p in dyn/cm^2 (1 atm = 1013250), concentrations in
+ *              mol/cm^3, wdot in mol/(cm^3 s), mu in g/(cm s), lambda in
+ *              erg/(cm s K), D in cm^2/s, cp in erg/(g K), h in erg/g; Arrhenius
+ *              A in (cm^3/mol)^(order-1)/s and E_a in cal/mol.
+ *   Layout     structure of arrays.  Point arrays T[n], p[n]; per-species
+ *              arrays are species-major, element (k, i) at k*n + i (Y, wdot,
+ *              Dmix, cp_k, h_k).  Every point array is a DEVICE pointer on the
+ *              handle's device, 8-byte aligned, contiguous; outputs must not
+ *              alias inputs or each other.
+ *   Asynchrony Compute calls only enqueue work on `stream` (0 = the legacy
+ *              default stream).  KX_OK means "enqueued"; results are ready once
+ *              the stream is synchronised.  Device faults surface at that sync.
+ *   Arguments  Validated on the host: a NULL handle or pointer, n < 0, or an
+ *              unknown precision return KX_EINVAL; n == 0 is a no-op
+ *              returning KX_OK.  Point values are not checked on the device;
+ *              preconditions are 200 <= T <= 3500, p > 0, Y_k >= 0, sum Y = 1.
+ *   Threads    A handle is immutable after creation and may be used from any
+ *              host thread and on any stream of its device concurrently.
+ *              kx_last_error() is per host thread.
+ *   Errors     Every entry point returns a kx_status; on failure nothing is
+ *              enqueued and kx_last_error() describes the cause.
+ */
+#ifndef KX_H
+#define KX_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t kx_status;
+enum {
+    KX_OK = 0,
+    KX_EINVAL = -1,        /* bad argument or inconsistent descriptor */
+    KX_ENOMEM = -2,        /* device or host allocation failed, or over budget */
+    KX_EDEVICE = -3,       /* HIP runtime error (launch, copy, device select) */
+    KX_EUNSUPPORTED = -4,  /* valid input outside what the kernels implement */
+    KX_EAGAIN = -5         /* serving: not complete yet / queue full */
+};
+
+/* Precision flag of the _ex entry points. */
+enum {
+    KX_FP64 = 0,   /* every operation in IEEE double precision */
+    KX_MIXED = 1   /* FP32 bulk with FP64 Gibbs / K_c, the near-equilibrium
+                      bracket and a compensated FP64 wdot sum (see
+                      kx_production_rates_ex) */
+};
+
+/* Reaction types (App. A.2). */
+enum {
+    KX_RXN_ELEMENTARY = 0, /* c_i = 1 */
+    KX_RXN_THREEBODY = 1,  /* c_i = [X]_i */
+    KX_RXN_LINDEMANN = 2,  /* c_i = P_r/(1+P_r), F = 1 */
+    KX_RXN_TROE = 3        /* c_i = P_r/(1+P_r) F_Troe (eq:blend) */
+};
+
+/* Mechanism descriptor.  Every array is HOST memory owned by the caller and
+ * only read during kx_mech_create (it may be freed afterwards).  Row-major.
+ * Ns = n_species, Nr = n_reactions, Ne = n_elements. */
+typedef struct {
+    int32_t n_species, n_reactions, n_elements;
+    const double *elem_mass;      /* [Ne] g/mol; W_k = sum_e composition[k][e] elem_mass[e] */
+    const int32_t *composition;   /* [Ns][Ne] atom counts */
+    const double *nasa_lo;        /* [Ns][7] a0..a6 used when T <  t_mid[k] (App. A.1) */
+    const double *nasa_hi;        /* [Ns][7] a0..a6 used when T >= t_mid[k] */
+    const double *t_mid;          /* [Ns] K */
+    const int32_t *rxn_type;      /* [Nr] KX_RXN_* */
+    const int32_t *reversible;    /* [Nr] 0: k_r = 0; else k_r = k_f / K_c */
+    const int32_t *reac_ptr;      /* [Nr+1] CSR of reactants; distinct species per reaction */
+    const int32_t *reac_sp;       /*   species index */
+    const int32_t *reac_nu;       /*   integer stoichiometric coefficient nu' > 0 */
+    const int32_t *prod_ptr;      /* [Nr+1] CSR of products, same rules (nu'' > 0) */
+    const int32_t *prod_sp;
+    const int32_t *prod_nu;
+    const double *A, *beta, *Ea;     /* [Nr] Arrhenius (k_inf for falloff) */
+    const double *A0, *beta0, *Ea0;  /* [Nr] low-pressure limit k_0 (falloff only) */
+    const double *troe;           /* [Nr][4] alpha, T***, T*, T** (T** = NaN: term omitted) */
+    const int32_t *eff_ptr;       /* [Nr+1] CSR of third-body efficiencies that differ */
+    const int32_t *eff_sp;        /*   from eff_default (third-body and falloff only) */
+    const double *eff_val;        /*   alpha_ki */
+    const double *eff_default;    /* [Nr] efficiency of unlisted species (1 = [M]; 0 with
+                                     one listed species m of efficiency 1 = [X_m]) */
+    int32_t fit_order;            /* coefficients per fit, 1..8 (5 in the paper) */
+    double fit_L0, fit_h;         /* fits are polynomials in u = (ln T - fit_L0) / fit_h;
+                                     (0, 1) is the paper's literal ln T basis */
+    int32_t diff_fit_kind;        /* 0: diff_fit holds D_kj(T, 1 atm) (eq:Dkj);
+                                     1: diff_fit holds 1 / D_kj(T, 1 atm) */
+    const double *visc_fit;       /* [Ns][order] eta_k(u), constant term first */
+    const double *cond_fit;       /* [Ns][order] lambda_k(u) */
+    const double *diff_fit;       /* [Ns][Ns][order], symmetric in (k, j); the diagonal
+                                     is used only when sum_{j!=k} X_j/D_kj == 0 */
+} kx_mech_desc;
+
+typedef struct kx_mech kx_mech; /* opaque device-resident mechanism */
+
+/* Validate `desc`, derive the device tables (reaction order, scaled Gibbs
+ * coefficients, stoichiometry and efficiency lists, Wilke constants, fit
+ * tables) and upload them to `device`.  Rejects (KX_EINVAL) negative or zero
+ * sizes, out-of-range species indices, non-positive W_k or A, a species listed
+ * twice on one side of a reaction, unbalanced element counts, an unknown
+ * reaction type, a non-symmetric diff_fit, fit_order outside 1..8 and
+ * fit_h == 0.  KX_EUNSUPPORTED: more than 4 distinct species on one side of a
+ * reaction or more than 65535 species.  On success *out owns the tables until
+ * kx_mech_destroy.  Allocates device memory (hipMalloc); blocks until the
+ * upload is complete. */
+kx_status kx_mech_create(const kx_mech_desc *desc, int device, kx_mech **out);
+
+/* Free the device tables.  The caller must have synchronised every stream on
+ * which work using `mech` was enqueued.  NULL is a no-op. */
+kx_status kx_mech_destroy(kx_mech *mech);
+
+/* Sizes of a created mechanism and the bytes of device memory its tables use
+ * (any output may be NULL). */
+kx_status kx_mech_info(const kx_mech *mech, int32_t *n_species, int32_t *n_reactions,
+                       int64_t *device_bytes);
+
+/* Net production rates wdot[Ns][n] (App. A.2: wdot_k = sum_i nu_ki c_i r_i with
+ * eq:arrhenius, eq:K_p / eq:Ck for K_c, eq:c_i, eq:blend and eq:r_i) for n points
+ * with temperature T[n], pressure p[n] and mass fractions Y[Ns][n].  Plain FP64. */
+kx_status kx_production_rates(const kx_mech *mech, int64_t n, const double *T,
+                              const double *p, const double *Y, double *wdot,
+                              hipStream_t stream);
+
+/* As kx_production_rates with a precision flag.  KX_MIXED evaluates the
+ * Arrhenius, third-body and falloff arithmetic in FP32 (the Arrhenius
+ * exponent argument is formed and range-reduced in FP64), while the species
+ * Gibbs energies, K_c, the bracket of forward minus reverse terms and the
+ * compensated wdot sum stay in FP64.  Inputs and outputs are FP64 either way. */
+kx_status kx_production_rates_ex(const kx_mech *mech, int64_t n, const double *T,
+                                 const double *p, const double *Y, double *wdot,
+                                 int32_t precision, hipStream_t stream);
+
+/* Mixture-averaged transport for n points (App. A.3): mu[n] by Wilke / Bird,
+ * lambda[n] by Mathur's combination averaging, Dmix[Ns][n] by eq:mix_diff
+ * (falling back to D_kk where sum_{j!=k} X_j/D_kj is zero).  Pure-species
+ * properties come from the ln T fits; D_kj = fit_kj * p_atm / p.  Plain FP64. */
+kx_status kx_transport(const kx_mech *mech, int64_t n, const double *T, const double *p,
+                       const double *Y, double *mu, double *lambda, double *Dmix,
+                       hipStream_t stream);
+
+/* As kx_transport with a precision flag.  KX_MIXED evaluates the fits and the
+ * mixing sums in FP32 with FP32 accumulation; the D_km numerator
+ * (W-bar - X_k W_k)/W-bar is formed in FP64. */
+kx_status kx_transport_ex(const kx_mech *mech, int64_t n, const double *T, const double *p,
+                          const double *Y, double *mu, double *lambda, double *Dmix,
+                          int32_t precision, hipStream_t stream);
+
+/* Mixture thermodynamics (App. A.1) for n points: cp_k[Ns][n] = Cp_k/W_k,
+ * h_k[Ns][n] = H_k/W_k and cp_mix[n] = sum_k Y_k cp_k.  Any of the three
+ * outputs may be NULL.  Plain FP64. */
+kx_status kx_thermo(const kx_mech *mech, int64_t n, const double *T, const double *Y,
+                    double *cp_k, double *h_k, double *cp_mix, hipStream_t stream);
+
+/* Human-readable description of the calling thread's most recent failure
+ * ("" if none).  The pointer stays valid until the thread's next kx_* call. */
+const char *kx_last_error(void);
+
+/* Library version string, e.g. "kx 0.1 gfx950". */
+const char *kx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KX_H */

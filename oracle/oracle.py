@@ -234,14 +234,24 @@ def equilibrium_states(om: OracleMech, n: int, seed: int, T_range=(300.0, 2800.0
         lam[0] = 0.5 * (np.log(xa[i, 0] * ctot / P0) + g[2])
         lam[1] = 0.5 * (np.log(xa[i, 1] * ctot / P0) + g[3])
         lnC = np.log(P0) - g[react] + a_re @ lam
-        # shift both potentials down until the reactive species leave room
+        # lower both potentials by the same amount until the reactive species
+        # take at most 90 % of the pressure: f(shift) is decreasing
+        na = a_re.sum(axis=1)
+        target = np.log(0.9 * ctot)
+        f = lambda sh: np.logaddexp.reduce(lnC - sh * na) - target
         shift = 0.0
-        for _ in range(200):
-            tot = np.exp(lnC - shift * a_re.sum(axis=1)).sum()
-            if tot <= 0.9 * ctot:
-                break
-            shift += 0.25
-        Cr = np.exp(lnC - shift * a_re.sum(axis=1))
+        if f(0.0) > 0.0:
+            lo, hi = 0.0, 1.0
+            while f(hi) > 0.0:
+                lo, hi = hi, 2.0 * hi
+            for _ in range(200):
+                mid = 0.5 * (lo + hi)
+                if f(mid) > 0.0:
+                    lo = mid
+                else:
+                    hi = mid
+            shift = hi
+        Cr = np.exp(lnC - shift * na)
         X = np.empty(ns)
         X[react] = Cr / ctot
         X[ns - 1] = 1.0 - X[react].sum()
@@ -249,4 +259,5 @@ def equilibrium_states(om: OracleMech, n: int, seed: int, T_range=(300.0, 2800.0
         y /= y.sum()
         y *= 1.0 + perturb * u[i]
         Y[:, i] = y / y.sum()
+    assert (Y >= 0.0).all() and np.isfinite(Y).all()
     return T, p, Y

@@ -1,0 +1,130 @@
+// kx_internal.h -- device-resident mechanism tables and launch helpers shared
+// by the host table builder (kx_mech.cpp) and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/kx.h"
+
+namespace kx {
+
+// Physical constants (cgs; CODATA 2018 exact R, thermochemical calorie).
+constexpr double kRu = 8.31446261815324e7;            // erg / (mol K)
+constexpr double kRcal = 8.31446261815324 / 4.184;    // cal / (mol K)
+constexpr double kPatm = 1013250.0;                   // dyn / cm^2
+
+constexpr int kMaxSide = 4;          // distinct species per reaction side
+constexpr int kMaxSpecies = 256;     // species per mechanism (4 per lane)
+constexpr int kMaxFitOrder = 8;
+constexpr int kWave = 64;
+
+// Reaction flags.
+enum : uint8_t {
+    kFlagReversible = 1,
+    kFlagKfConst = 2,    // beta = E_R = 0: k_f = A without an exponential
+};
+
+// One reaction in kernel order (reactions sorted by type so that 64-lane
+// chunks mostly share one code path).  64 bytes.
+struct alignas(16) DevRxn {
+    double lnA;           // ln A
+    double beta;          // temperature exponent
+    double ER;            // activation temperature E_a / R
+    double A;             // A itself (k_f when kFlagKfConst)
+    uint16_t rsp[kMaxSide];  // reactant species (0xFFFF = unused)
+    uint16_t psp[kMaxSide];  // product species
+    uint8_t rnu[kMaxSide];   // nu' (0 = unused)
+    uint8_t pnu[kMaxSide];   // nu''
+    uint8_t type;            // KX_RXN_*
+    uint8_t flags;
+    uint16_t aux;            // index into DevAux for types 1..3
+    uint32_t pad;
+};
+static_assert(sizeof(DevRxn) == 64, "DevRxn layout");
+
+// Third-body and falloff data of one reaction.  96 bytes.
+struct alignas(16) DevAux {
+    double eff_default;      // efficiency of unlisted species
+    double lnA0, beta0, ER0; // k_0 (falloff)
+    double troe_alpha;
+    double troe_inv_T3;      // 1 / T***
+    double troe_inv_T1;      // 1 / T*
+    double troe_T2;          // T** (used when has_T2)
+    int32_t eff_off, eff_cnt;  // slice of DevEff
+    int32_t has_T2, pad;
+};
+static_assert(sizeof(DevAux) == 80 || sizeof(DevAux) == 96, "DevAux layout");
+
+struct alignas(16) DevEff {
+    double dalpha;           // alpha_ki - eff_default
+    int32_t sp;
+    int32_t pad;
+};
+
+// Per-species thermo: Gibbs coefficients g/RT = c0 (1 - ln T) + c1 T + c2 T^2 +
+// c3 T^3 + c4 T^4 + c5 / T + c6 for both ranges (eq:Ck pre-scaled), the raw
+// NASA coefficients for cp and h, T_mid and 1/W.  Each species: 32 doubles.
+struct alignas(16) DevSpecies {
+    double g_lo[8];   // c0..c6 + pad
+    double g_hi[8];
+    double nasa_lo[7];
+    double t_mid;
+    double nasa_hi[7];
+    double inv_W;
+};
+static_assert(sizeof(DevSpecies) == 256, "DevSpecies layout");
+
+// Transport k-blocking factor: the Wilke and D_km sums run over all j for a
+// block of kKB species k held in registers.
+constexpr int kKB = 8;
+
+struct MechDev {
+    int32_t ns, nr, nchunks;   // species, reactions, reaction chunks for the gather
+    int32_t chunk;             // reactions per chunk (multiple of 64)
+    int32_t fit_order, diff_kind;
+    double fit_L0, inv_fit_h;
+    const DevRxn *rxn;         // [nr] kernel order
+    const DevAux *aux;         // [naux]
+    const DevEff *eff;         // [neff]
+    const DevSpecies *sp;      // [ns]
+    const int32_t *gptr;       // [nchunks][ns+1] species-major gather CSR per chunk
+    const int32_t *gent;       // entries (slot_in_chunk << 8) | (uint8_t)(int8_t) nu
+    // transport (FP64)
+    const double *W;           // [ns]
+    const double *visc;        // [ns][order]
+    const double *cond;        // [ns][order]
+    const double *wilke;       // [nkb][ns][kKB][3]   c1, c1 c2, c1 c2^2
+    const double *dfit;        // [nkb][ns][kKB][order]  fit of (k = kb*KB+kk, j)
+    const double *ddiag;       // [ns][order] diagonal fits for the fallback
+    // transport (FP32 copies for the mixed path)
+    const float *visc32, *cond32, *wilke32, *dfit32, *ddiag32;
+};
+
+}  // namespace kx
+
+struct kx_mech {
+    int device;
+    kx::MechDev dev;
+    void *blob;          // single device allocation holding every table
+    int64_t bytes;
+    int32_t n_species, n_reactions;
+};
+
+namespace kx {
+// Error reporting shared by all entry points (thread-local message).
+kx_status fail(kx_status code, const std::string &msg);
+kx_status ok();
+kx_status hip_fail(hipError_t e, const char *what);
+
+// Launchers (defined in the kernel translation units).
+kx_status launch_rates(const kx_mech *m, int64_t n, const double *T, const double *p,
+                       const double *Y, double *wdot, int precision, hipStream_t s);
+kx_status launch_transport(const kx_mech *m, int64_t n, const double *T, const double *p,
+                           const double *Y, double *mu, double *lam, double *Dmix,
+                           int precision, hipStream_t s);
+kx_status launch_thermo(const kx_mech *m, int64_t n, const double *T, const double *Y,
+                        double *cpk, double *hk, double *cpmix, hipStream_t s);
+}  // namespace kx

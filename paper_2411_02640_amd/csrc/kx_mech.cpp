@@ -1,0 +1,368 @@
+// kx_mech.cpp -- host-side mechanism table builder (kx_mech_create).
+//
+// Validates a kx_mech_desc, derives every table the gfx950 kernels read and
+// uploads them to the device in one allocation:
+//  * reactions re-ordered by type (elementary, three-body, Lindemann, Troe;
+//    constant-k_f reactions first inside each type) so that a 64-lane chunk of
+//    reactions mostly follows one code path;
+//  * ln A, E_R = E_a / R and the beta = E_R = 0 shortcut of eq:k_f;
+//  * third-body efficiencies as (alpha - default) lists, falloff k_0 and Troe
+//    parameters (inverse temperatures);
+//  * a species-major gather list per reaction chunk for wdot_k = sum_i nu_ki R_i;
+//  * Gibbs coefficients of eq:Ck pre-scaled per range, raw NASA-7 for cp / h;
+//  * Wilke constants c1 = (8 (1 + W_k/W_j))^(-1/2), c2 = (W_j/W_k)^(1/4) as the
+//    three products used by the expanded phi sum, and the ln T fit tables in
+//    the k-blocked order of the transport kernel, in FP64 and FP32.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "kx_internal.h"
+
+namespace kx {
+namespace {
+
+struct Blob {
+    std::vector<uint8_t> host;
+    size_t add(const void *src, size_t bytes)
+    {
+        size_t off = (host.size() + 255) & ~size_t(255);
+        host.resize(off + bytes);
+        if (bytes) std::memcpy(host.data() + off, src, bytes);
+        return off;
+    }
+};
+
+template <class T> size_t add_vec(Blob &b, const std::vector<T> &v)
+{
+    return b.add(v.data(), v.size() * sizeof(T));
+}
+
+kx_status validate(const kx_mech_desc *d, std::vector<double> &W)
+{
+    if (!d) return fail(KX_EINVAL, "kx_mech_create: desc is NULL");
+    const int ns = d->n_species, nr = d->n_reactions, ne = d->n_elements;
+    if (ns <= 0 || nr < 0 || ne <= 0)
+        return fail(KX_EINVAL, "kx_mech_create: n_species and n_elements must be > 0, "
+                               "n_reactions >= 0");
+    if (ns > kMaxSpecies)
+        return fail(KX_EUNSUPPORTED, "kx_mech_create: at most 256 species are supported");
+    if (!d->elem_mass || !d->composition || !d->nasa_lo || !d->nasa_hi || !d->t_mid ||
+        !d->visc_fit || !d->cond_fit || !d->diff_fit)
+        return fail(KX_EINVAL, "kx_mech_create: NULL species array");
+    if (nr > 0 && (!d->rxn_type || !d->reversible || !d->reac_ptr || !d->reac_sp ||
+                   !d->reac_nu || !d->prod_ptr || !d->prod_sp || !d->prod_nu || !d->A ||
+                   !d->beta || !d->Ea || !d->A0 || !d->beta0 || !d->Ea0 || !d->troe ||
+                   !d->eff_ptr || !d->eff_default))
+        return fail(KX_EINVAL, "kx_mech_create: NULL reaction array");
+    if (d->fit_order < 1 || d->fit_order > kMaxFitOrder)
+        return fail(KX_EINVAL, "kx_mech_create: fit_order must be in 1..8");
+    if (!(d->fit_h != 0.0) || !std::isfinite(d->fit_h) || !std::isfinite(d->fit_L0))
+        return fail(KX_EINVAL, "kx_mech_create: fit_h must be finite and non-zero");
+    if (d->diff_fit_kind != 0 && d->diff_fit_kind != 1)
+        return fail(KX_EINVAL, "kx_mech_create: diff_fit_kind must be 0 or 1");
+    W.assign(ns, 0.0);
+    for (int k = 0; k < ns; ++k) {
+        for (int e = 0; e < ne; ++e) {
+            if (d->composition[k * ne + e] < 0)
+                return fail(KX_EINVAL, "kx_mech_create: negative atom count");
+            W[k] += d->composition[k * ne + e] * d->elem_mass[e];
+        }
+        if (!(W[k] > 0.0))
+            return fail(KX_EINVAL, "kx_mech_create: species " + std::to_string(k) +
+                                       " has non-positive molecular weight");
+    }
+    const int order = d->fit_order;
+    for (int k = 0; k < ns; ++k)
+        for (int j = 0; j < ns; ++j)
+            for (int o = 0; o < order; ++o)
+                if (d->diff_fit[((size_t)k * ns + j) * order + o] !=
+                    d->diff_fit[((size_t)j * ns + k) * order + o])
+                    return fail(KX_EINVAL, "kx_mech_create: diff_fit is not symmetric");
+    for (int i = 0; i < nr; ++i) {
+        const std::string ri = " (reaction " + std::to_string(i) + ")";
+        const int t = d->rxn_type[i];
+        if (t < KX_RXN_ELEMENTARY || t > KX_RXN_TROE)
+            return fail(KX_EINVAL, "kx_mech_create: unknown reaction type" + ri);
+        if (!(d->A[i] > 0.0) || !std::isfinite(d->beta[i]) || !std::isfinite(d->Ea[i]))
+            return fail(KX_EINVAL, "kx_mech_create: A must be > 0, beta and Ea finite" + ri);
+        if (t >= KX_RXN_LINDEMANN &&
+            (!(d->A0[i] > 0.0) || !std::isfinite(d->beta0[i]) || !std::isfinite(d->Ea0[i])))
+            return fail(KX_EINVAL, "kx_mech_create: falloff A0 must be > 0" + ri);
+        if (t == KX_RXN_TROE && (!(d->troe[4 * i + 1] != 0.0) || !(d->troe[4 * i + 2] != 0.0)))
+            return fail(KX_EINVAL, "kx_mech_create: Troe T*** and T* must be non-zero" + ri);
+        std::vector<long> bal(ne, 0);
+        for (int side = 0; side < 2; ++side) {
+            const int32_t *ptr = side ? d->prod_ptr : d->reac_ptr;
+            const int32_t *sp = side ? d->prod_sp : d->reac_sp;
+            const int32_t *nu = side ? d->prod_nu : d->reac_nu;
+            if (ptr[i] < 0 || ptr[i + 1] < ptr[i])
+                return fail(KX_EINVAL, "kx_mech_create: bad CSR pointer" + ri);
+            if (ptr[i + 1] - ptr[i] > kMaxSide)
+                return fail(KX_EUNSUPPORTED,
+                            "kx_mech_create: more than 4 species on one side" + ri);
+            for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+                if (sp[e] < 0 || sp[e] >= ns)
+                    return fail(KX_EINVAL, "kx_mech_create: species index out of range" + ri);
+                if (nu[e] <= 0 || nu[e] > 255)
+                    return fail(KX_EINVAL, "kx_mech_create: nu must be in 1..255" + ri);
+                for (int f = ptr[i]; f < e; ++f)
+                    if (sp[f] == sp[e])
+                        return fail(KX_EINVAL,
+                                    "kx_mech_create: species listed twice on one side" + ri);
+                for (int el = 0; el < ne; ++el)
+                    bal[el] += (side ? 1 : -1) * (long)nu[e] * d->composition[sp[e] * ne + el];
+            }
+        }
+        for (int el = 0; el < ne; ++el)
+            if (bal[el] != 0)
+                return fail(KX_EINVAL, "kx_mech_create: reaction is not element-balanced" + ri);
+        if (t != KX_RXN_ELEMENTARY) {
+            if (d->eff_ptr[i] < 0 || d->eff_ptr[i + 1] < d->eff_ptr[i])
+                return fail(KX_EINVAL, "kx_mech_create: bad efficiency CSR" + ri);
+            for (int e = d->eff_ptr[i]; e < d->eff_ptr[i + 1]; ++e)
+                if (!d->eff_sp || !d->eff_val || d->eff_sp[e] < 0 || d->eff_sp[e] >= ns)
+                    return fail(KX_EINVAL, "kx_mech_create: efficiency species out of range" + ri);
+        }
+    }
+    return KX_OK;
+}
+
+}  // namespace
+
+kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
+{
+    if (!out) return fail(KX_EINVAL, "kx_mech_create: out is NULL");
+    *out = nullptr;
+    std::vector<double> W;
+    kx_status st = validate(d, W);
+    if (st != KX_OK) return st;
+    const int ns = d->n_species, nr = d->n_reactions, order = d->fit_order;
+
+    // ---- reaction order: by type, constant-k_f first within a type
+    std::vector<int> perm(nr);
+    std::iota(perm.begin(), perm.end(), 0);
+    auto kfconst = [&](int i) { return d->beta[i] == 0.0 && d->Ea[i] == 0.0; };
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+        if (d->rxn_type[a] != d->rxn_type[b]) return d->rxn_type[a] < d->rxn_type[b];
+        return kfconst(a) && !kfconst(b);
+    });
+
+    std::vector<DevRxn> rx(nr);
+    std::vector<DevAux> aux;
+    std::vector<DevEff> eff;
+    for (int s = 0; s < nr; ++s) {
+        const int i = perm[s];
+        DevRxn r;
+        std::memset(&r, 0, sizeof r);
+        r.lnA = std::log(d->A[i]);
+        r.beta = d->beta[i];
+        r.ER = d->Ea[i] / kRcal;
+        r.A = d->A[i];
+        for (int q = 0; q < kMaxSide; ++q) r.rsp[q] = r.psp[q] = 0xFFFF;
+        int c = 0;
+        for (int e = d->reac_ptr[i]; e < d->reac_ptr[i + 1]; ++e, ++c) {
+            r.rsp[c] = (uint16_t)d->reac_sp[e];
+            r.rnu[c] = (uint8_t)d->reac_nu[e];
+        }
+        c = 0;
+        for (int e = d->prod_ptr[i]; e < d->prod_ptr[i + 1]; ++e, ++c) {
+            r.psp[c] = (uint16_t)d->prod_sp[e];
+            r.pnu[c] = (uint8_t)d->prod_nu[e];
+        }
+        r.type = (uint8_t)d->rxn_type[i];
+        r.flags = (d->reversible[i] ? kFlagReversible : 0) | (kfconst(i) ? kFlagKfConst : 0);
+        r.aux = 0xFFFF;
+        if (r.type != KX_RXN_ELEMENTARY) {
+            if (aux.size() >= 0xFFFF)
+                return fail(KX_EUNSUPPORTED, "kx_mech_create: too many third-body reactions");
+            DevAux a;
+            std::memset(&a, 0, sizeof a);
+            a.eff_default = d->eff_default[i];
+            a.eff_off = (int32_t)eff.size();
+            for (int e = d->eff_ptr[i]; e < d->eff_ptr[i + 1]; ++e) {
+                DevEff f;
+                std::memset(&f, 0, sizeof f);
+                f.sp = d->eff_sp[e];
+                f.dalpha = d->eff_val[e] - d->eff_default[i];
+                eff.push_back(f);
+            }
+            a.eff_cnt = (int32_t)eff.size() - a.eff_off;
+            if (r.type >= KX_RXN_LINDEMANN) {
+                a.lnA0 = std::log(d->A0[i]);
+                a.beta0 = d->beta0[i];
+                a.ER0 = d->Ea0[i] / kRcal;
+            }
+            if (r.type == KX_RXN_TROE) {
+                a.troe_alpha = d->troe[4 * i + 0];
+                a.troe_inv_T3 = 1.0 / d->troe[4 * i + 1];
+                a.troe_inv_T1 = 1.0 / d->troe[4 * i + 2];
+                a.has_T2 = std::isnan(d->troe[4 * i + 3]) ? 0 : 1;
+                a.troe_T2 = a.has_T2 ? d->troe[4 * i + 3] : 0.0;
+            }
+            r.aux = (uint16_t)aux.size();
+            aux.push_back(a);
+        }
+        rx[s] = r;
+    }
+    if (eff.empty()) eff.resize(1);
+    if (aux.empty()) aux.resize(1);
+
+    // ---- species-major gather lists per reaction chunk
+    const int chunk = std::max(kWave, std::min(512, (nr + kWave - 1) / kWave * kWave));
+    const int nchunks = std::max(1, (nr + chunk - 1) / chunk);
+    std::vector<int32_t> gptr((size_t)nchunks * (ns + 1));
+    std::vector<int32_t> gent;
+    for (int c = 0; c < nchunks; ++c) {
+        std::vector<std::vector<int32_t>> per(ns);
+        for (int s = c * chunk; s < std::min(nr, (c + 1) * chunk); ++s) {
+            const DevRxn &r = rx[s];
+            std::vector<std::pair<int, int>> net;  // (species, nu'' - nu')
+            auto addnu = [&](int k, int v) {
+                for (auto &pr : net)
+                    if (pr.first == k) { pr.second += v; return; }
+                net.push_back({k, v});
+            };
+            for (int q = 0; q < kMaxSide; ++q) {
+                if (r.rnu[q]) addnu(r.rsp[q], -(int)r.rnu[q]);
+                if (r.pnu[q]) addnu(r.psp[q], (int)r.pnu[q]);
+            }
+            for (auto &pr : net) {
+                if (pr.second == 0) continue;
+                if (pr.second < -128 || pr.second > 127)
+                    return fail(KX_EUNSUPPORTED, "kx_mech_create: |net nu| > 127");
+                per[pr.first].push_back(((s - c * chunk) << 8) |
+                                        (int32_t)(uint8_t)(int8_t)pr.second);
+            }
+        }
+        for (int k = 0; k < ns; ++k) {
+            gptr[(size_t)c * (ns + 1) + k] = (int32_t)gent.size();
+            gent.insert(gent.end(), per[k].begin(), per[k].end());
+        }
+        gptr[(size_t)c * (ns + 1) + ns] = (int32_t)gent.size();
+    }
+    if (gent.empty()) gent.push_back(0);
+
+    // ---- species thermo
+    std::vector<DevSpecies> spv(ns);
+    for (int k = 0; k < ns; ++k) {
+        DevSpecies s;
+        std::memset(&s, 0, sizeof s);
+        for (int r = 0; r < 2; ++r) {
+            const double *a = (r ? d->nasa_hi : d->nasa_lo) + 7 * k;
+            double *g = r ? s.g_hi : s.g_lo;
+            g[0] = a[0];
+            g[1] = -a[1] / 2.0;
+            g[2] = -a[2] / 6.0;
+            g[3] = -a[3] / 12.0;
+            g[4] = -a[4] / 20.0;
+            g[5] = a[5];
+            g[6] = -a[6];
+            std::memcpy(r ? s.nasa_hi : s.nasa_lo, a, 7 * sizeof(double));
+        }
+        s.t_mid = d->t_mid[k];
+        s.inv_W = 1.0 / W[k];
+        spv[k] = s;
+    }
+
+    // ---- transport tables
+    const int nkb = (ns + kKB - 1) / kKB;
+    std::vector<double> visc((size_t)ns * order), cond((size_t)ns * order);
+    std::memcpy(visc.data(), d->visc_fit, visc.size() * sizeof(double));
+    std::memcpy(cond.data(), d->cond_fit, cond.size() * sizeof(double));
+    std::vector<double> wilke((size_t)nkb * ns * kKB * 3, 0.0);
+    std::vector<double> dfit((size_t)nkb * ns * kKB * order, 0.0);
+    std::vector<double> ddiag((size_t)ns * order);
+    for (int kb = 0; kb < nkb; ++kb)
+        for (int j = 0; j < ns; ++j)
+            for (int kk = 0; kk < kKB; ++kk) {
+                const int k = kb * kKB + kk;
+                if (k >= ns) continue;
+                const double c1 = 1.0 / std::sqrt(8.0 * (1.0 + W[k] / W[j]));
+                const double c2 = std::pow(W[j] / W[k], 0.25);
+                double *w = &wilke[(((size_t)kb * ns + j) * kKB + kk) * 3];
+                w[0] = c1;
+                w[1] = c1 * c2;
+                w[2] = c1 * c2 * c2;
+                std::memcpy(&dfit[(((size_t)kb * ns + j) * kKB + kk) * order],
+                            d->diff_fit + ((size_t)k * ns + j) * order, order * sizeof(double));
+            }
+    for (int k = 0; k < ns; ++k)
+        std::memcpy(&ddiag[(size_t)k * order], d->diff_fit + ((size_t)k * ns + k) * order,
+                    order * sizeof(double));
+    auto to32 = [](const std::vector<double> &v) {
+        return std::vector<float>(v.begin(), v.end());
+    };
+
+    Blob b;
+    const size_t o_rxn = add_vec(b, rx), o_aux = add_vec(b, aux), o_eff = add_vec(b, eff);
+    const size_t o_sp = add_vec(b, spv), o_gptr = add_vec(b, gptr), o_gent = add_vec(b, gent);
+    const size_t o_W = add_vec(b, W), o_visc = add_vec(b, visc), o_cond = add_vec(b, cond);
+    const size_t o_wil = add_vec(b, wilke), o_df = add_vec(b, dfit), o_dd = add_vec(b, ddiag);
+    const size_t o_visc32 = add_vec(b, to32(visc)), o_cond32 = add_vec(b, to32(cond));
+    const size_t o_wil32 = add_vec(b, to32(wilke)), o_df32 = add_vec(b, to32(dfit));
+    const size_t o_dd32 = add_vec(b, to32(ddiag));
+
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    void *blob = nullptr;
+    e = hipMalloc(&blob, b.host.size());
+    if (e != hipSuccess) {
+        hipSetDevice(prev);
+        return fail(KX_ENOMEM, "kx_mech_create: hipMalloc of " +
+                                   std::to_string(b.host.size()) + " bytes failed");
+    }
+    e = hipMemcpy(blob, b.host.data(), b.host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(blob);
+        hipSetDevice(prev);
+        return hip_fail(e, "hipMemcpy (mechanism upload)");
+    }
+    hipSetDevice(prev);
+
+    kx_mech *m = new kx_mech;
+    m->device = device;
+    m->blob = blob;
+    m->bytes = (int64_t)b.host.size();
+    m->n_species = ns;
+    m->n_reactions = nr;
+    MechDev &v = m->dev;
+    auto at = [&](size_t off) { return (const void *)((const uint8_t *)blob + off); };
+    v.ns = ns;
+    v.nr = nr;
+    v.chunk = chunk;
+    v.nchunks = nchunks;
+    v.fit_order = order;
+    v.diff_kind = d->diff_fit_kind;
+    v.fit_L0 = d->fit_L0;
+    v.inv_fit_h = 1.0 / d->fit_h;
+    v.rxn = (const DevRxn *)at(o_rxn);
+    v.aux = (const DevAux *)at(o_aux);
+    v.eff = (const DevEff *)at(o_eff);
+    v.sp = (const DevSpecies *)at(o_sp);
+    v.gptr = (const int32_t *)at(o_gptr);
+    v.gent = (const int32_t *)at(o_gent);
+    v.W = (const double *)at(o_W);
+    v.visc = (const double *)at(o_visc);
+    v.cond = (const double *)at(o_cond);
+    v.wilke = (const double *)at(o_wil);
+    v.dfit = (const double *)at(o_df);
+    v.ddiag = (const double *)at(o_dd);
+    v.visc32 = (const float *)at(o_visc32);
+    v.cond32 = (const float *)at(o_cond32);
+    v.wilke32 = (const float *)at(o_wil32);
+    v.dfit32 = (const float *)at(o_df32);
+    v.ddiag32 = (const float *)at(o_dd32);
+    *out = m;
+    return ok();
+}
+
+}  // namespace kx

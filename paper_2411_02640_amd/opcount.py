@@ -1,0 +1,125 @@
+"""Algorithmic FP64 work per grid point, counted from a mechanism.
+
+The count follows the method as the library evaluates it (App. A of the
+paper with the per-species Gibbs exponentials for K_c and the beta = E_R = 0
+shortcut of eq:k_f), one term per arithmetic operation the formulas need:
+add / sub / mul = 1 flop, fused multiply-add = 2 flops, and each elementary
+function priced at the flops of a plain FP64 polynomial implementation
+(range reduction + minimax polynomial + reconstruction).  The prices are the
+model's, stated here so that the roofline fraction can be reproduced:
+
+    exp, exp10: 24    log, log10: 24    division, reciprocal: 8
+    sqrt, 1/sqrt: 8
+
+Counts are per point; a launch processes n points.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+PRICE = {"exp": 24, "log": 24, "div": 8, "sqrt": 8}
+
+
+def rates_ops(mech: dict) -> dict:
+    ns, nr = mech["n_species"], mech["n_reactions"]
+    t = mech["rxn_type"]
+    kfconst = (mech["beta"] == 0) & (mech["Ea"] == 0)
+    c = dict(fma=0, mul=0, add=0, exp=0, log=0, div=0, sqrt=0)
+    # mixture basics: sum Y/W (fma), C_k (2 mul), one division; ln T, 1/T
+    c["fma"] += ns
+    c["mul"] += 2 * ns
+    c["div"] += 2
+    c["log"] += 1
+    # species Gibbs (6 fma), exp, a_k (mul), b_k (div)
+    c["fma"] += 6 * ns
+    c["exp"] += ns
+    c["mul"] += ns
+    c["div"] += ns
+    for i in range(nr):
+        r = slice(mech["reac_ptr"][i], mech["reac_ptr"][i + 1])
+        p = slice(mech["prod_ptr"][i], mech["prod_ptr"][i + 1])
+        if not kfconst[i]:
+            c["fma"] += 2
+            c["exp"] += 1
+        nu_r = int(mech["reac_nu"][r].sum())
+        nu_p = int(mech["prod_nu"][p].sum())
+        c["mul"] += 2 * nu_r + nu_p + 3      # A', B', B'', c * kf * A' * bracket
+        c["add"] += 1                        # bracket
+        if t[i] != 0:
+            ne = mech["eff_ptr"][i + 1] - mech["eff_ptr"][i]
+            c["mul"] += 1 + ne
+            c["fma"] += ne
+        if t[i] >= 2:
+            c["fma"] += 2
+            c["exp"] += 1
+            c["mul"] += 2
+            c["div"] += 2
+            c["add"] += 1
+        if t[i] == 3:
+            c["exp"] += 3 if not np.isnan(mech["troe"][i, 3]) else 2
+            c["log"] += 2
+            c["exp"] += 1                    # 10^x
+            c["fma"] += 4
+            c["mul"] += 3
+            c["add"] += 3
+            c["div"] += 1
+    # stoichiometric accumulation: one fma per non-zero nu_ki
+    nnz = 0
+    for i in range(nr):
+        sp = {}
+        for e in range(mech["reac_ptr"][i], mech["reac_ptr"][i + 1]):
+            sp[mech["reac_sp"][e]] = sp.get(mech["reac_sp"][e], 0) - mech["reac_nu"][e]
+        for e in range(mech["prod_ptr"][i], mech["prod_ptr"][i + 1]):
+            sp[mech["prod_sp"][e]] = sp.get(mech["prod_sp"][e], 0) + mech["prod_nu"][e]
+        nnz += sum(1 for v in sp.values() if v != 0)
+    c["fma"] += nnz
+    return c
+
+
+def transport_ops(mech: dict) -> dict:
+    ns, order = mech["n_species"], mech["fit_order"]
+    c = dict(fma=0, mul=0, add=0, exp=0, log=0, div=0, sqrt=0)
+    c["log"] += 1
+    c["fma"] += 1 + ns                       # u, sum Y/W
+    c["div"] += 1
+    c["mul"] += 2 * ns                       # X_k
+    # lambda_k fits, Mathur sums
+    c["fma"] += ns * (order - 1) + 2 * ns
+    c["div"] += ns + 2
+    c["add"] += 1
+    # eta_k fits, sqrt / 1/sqrt, Wilke: 3 fma per ordered pair (k, j)
+    c["fma"] += ns * (order - 1)
+    c["sqrt"] += 2 * ns
+    c["mul"] += 2 * ns
+    c["fma"] += 3 * ns * ns
+    c["fma"] += 2 * ns
+    c["div"] += ns
+    c["fma"] += ns
+    # D_kj fits for k != j (full matrix), 1/D, accumulation, D_km
+    npair = ns * (ns - 1)
+    c["fma"] += npair * (order - 1)
+    c["div"] += npair
+    c["add"] += npair
+    c["div"] += 2 * ns
+    c["fma"] += 2 * ns
+    c["mul"] += ns
+    return c
+
+
+def flops(counts: dict) -> int:
+    return (2 * counts["fma"] + counts["mul"] + counts["add"]
+            + PRICE["exp"] * counts["exp"] + PRICE["log"] * counts["log"]
+            + PRICE["div"] * counts["div"] + PRICE["sqrt"] * counts["sqrt"])
+
+
+def per_point(mech: dict) -> dict:
+    r = rates_ops(mech)
+    t = transport_ops(mech)
+    return {"rates": r, "transport": t, "rates_flops": flops(r), "transport_flops": flops(t)}
+
+
+def io_bytes(mech: dict) -> dict:
+    """Compulsory HBM bytes per point (inputs read once, outputs written once)."""
+    ns = mech["n_species"]
+    return {"rates": 8 * (2 * ns + 2), "transport": 8 * (2 * ns + 4),
+            "fused": 8 * (3 * ns + 4)}

@@ -1,0 +1,273 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2411_02640_amd import inputs as I
+
+from . import parity as PM
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kx():
+    from paper_2411_02640_amd import kx as K
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    K.lib()
+    return K
+
+
+_dev_mechs = {}
+
+
+def dev_mech(kx, mech):
+    key = id(mech)
+    if key not in _dev_mechs:
+        _dev_mechs[key] = (kx.Mechanism(mech, 0), mech)
+    return _dev_mechs[key][0]
+
+
+def to_dev(*arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV) for a in arrs]
+
+
+def run_rates(kx, dm, T, p, Y, precision="fp64"):
+    Td, pd, Yd = to_dev(T, p, Y)
+    w = kx.production_rates(dm, Td, pd, Yd, precision=precision)
+    torch.cuda.synchronize()
+    return w.cpu().numpy()
+
+
+def run_transport(kx, dm, T, p, Y, precision="fp64"):
+    Td, pd, Yd = to_dev(T, p, Y)
+    mu, lam, Dm = kx.transport(dm, Td, pd, Yd, precision=precision)
+    torch.cuda.synchronize()
+    return mu.cpu().numpy(), lam.cpu().numpy(), Dm.cpu().numpy()
+
+
+def check_rates(kx, mech, T, p, Y, label):
+    _say("rates fp64", label, mech["name"], "n =", T.size)
+    dm = dev_mech(kx, mech)
+    w = run_rates(kx, dm, T, p, Y)
+    ref, s = O.OracleMech(mech).production_rates(T, p, Y)
+    r = PM.wdot_report(w, ref, s)
+    _say("  ", r)
+    assert r["ok"], r
+    return w
+
+
+def check_transport(kx, mech, T, p, Y, label):
+    _say("transport fp64", label, mech["name"], "n =", T.size)
+    dm = dev_mech(kx, mech)
+    mu, lam, Dm = run_transport(kx, dm, T, p, Y)
+    rmu, rlam, rDm = O.OracleMech(mech).transport(T, p, Y)
+    for name, g, r in (("mu", mu, rmu), ("lambda", lam, rlam), ("Dmix", Dm, rDm)):
+        rep = PM.rel_report(g, r, PM.REL_FP64)
+        _say("  ", name, rep)
+        assert rep["ok"], (name, rep)
+
+
+# ------------------------------------------------------------------ FP64 parity
+def test_syn9_all_points(kx, mech9):
+    T, p, Y = I.make_states(9, I.STATES_9)
+    check_rates(kx, mech9, T, p, Y, "4096 points")
+    check_transport(kx, mech9, T, p, Y, "4096 points")
+
+
+def test_syn9_ragged_tail(kx, mech9):
+    T, p, Y = I.make_states(9, I.StateSpec(4096 + 37, seed=21))
+    check_rates(kx, mech9, T, p, Y, "4133 points")
+    check_transport(kx, mech9, T, p, Y, "4133 points")
+
+
+def test_syn53_block(kx, mech53):
+    T, p, Y = I.make_states(53, I.STATES_53, n_points=(1 << 14) + 5)
+    check_rates(kx, mech53, T, p, Y, "16389 points")
+    check_transport(kx, mech53, T, p, Y, "16389 points")
+
+
+def test_syn53_full_size_sampled(kx, mech53):
+    """The 2^20-point workload in the launch configuration the benchmark times;
+    the oracle checks a sample of points (every tile boundary kind included)."""
+    T, p, Y = I.make_states(53, I.STATES_53)
+    n = T.size
+    dm = dev_mech(kx, mech53)
+    _say("full size syn53 n =", n)
+    w = run_rates(kx, dm, T, p, Y)
+    mu, lam, Dm = run_transport(kx, dm, T, p, Y)
+    rng = np.random.default_rng(99)
+    idx = np.unique(np.concatenate([rng.choice(n, 1500, replace=False),
+                                    [0, 1, 63, 64, 255, 256, n - 1]]))
+    Ts, ps, Ys = T[idx], p[idx], np.ascontiguousarray(Y[:, idx])
+    om = O.OracleMech(mech53)
+    ref, s = om.production_rates(Ts, ps, Ys)
+    r = PM.wdot_report(w[:, idx], ref, s)
+    _say("  wdot", r)
+    assert r["ok"], r
+    rmu, rlam, rDm = om.transport(Ts, ps, Ys)
+    for name, g, rr in (("mu", mu[idx], rmu), ("lambda", lam[idx], rlam), ("Dmix", Dm[:, idx], rDm)):
+        rep = PM.rel_report(g, rr, PM.REL_FP64)
+        _say("  ", name, rep)
+        assert rep["ok"], (name, rep)
+
+
+def test_syn200_sampled(kx, mech200):
+    T, p, Y = I.make_states(200, I.STATES_200, n_points=(1 << 14) + 3)
+    dm = dev_mech(kx, mech200)
+    _say("syn200 n =", T.size)
+    w = run_rates(kx, dm, T, p, Y)
+    mu, lam, Dm = run_transport(kx, dm, T, p, Y)
+    idx = np.unique(np.concatenate([np.arange(0, T.size, 61), [T.size - 1]]))
+    Ts, ps, Ys = T[idx], p[idx], np.ascontiguousarray(Y[:, idx])
+    om = O.OracleMech(mech200)
+    ref, s = om.production_rates(Ts, ps, Ys)
+    r = PM.wdot_report(w[:, idx], ref, s)
+    _say("  wdot", r)
+    assert r["ok"], r
+    rmu, rlam, rDm = om.transport(Ts, ps, Ys)
+    for name, g, rr in (("mu", mu[idx], rmu), ("lambda", lam[idx], rlam), ("Dmix", Dm[:, idx], rDm)):
+        rep = PM.rel_report(g, rr, PM.REL_FP64)
+        _say("  ", name, rep)
+        assert rep["ok"], (name, rep)
+
+
+def test_special_case_mechanism(kx):
+    """beta = E_R = 0, integer beta and shared (beta, E_R) reactions."""
+    spec = I.MechSpec(53, 266, 30, 0, 29, seed=77, special_cases=True, name="syn53sc")
+    m = I.make_mechanism(spec)
+    T, p, Y = I.make_states(53, I.STATES_53, n_points=4096)
+    check_rates(kx, m, T, p, Y, "special cases")
+
+
+def test_diffusion_fit_kind_inverse(kx):
+    """Tables holding fits of 1/D_kj (diff_fit_kind = 1)."""
+    spec = I.MechSpec(53, 266, 30, 0, 29, seed=53325, diff_fit_kind=1, name="syn53inv")
+    m = I.make_mechanism(spec)
+    T, p, Y = I.make_states(53, I.STATES_53, n_points=4096)
+    check_transport(kx, m, T, p, Y, "1/D fits")
+
+
+def test_near_equilibrium_states_fp64(kx, mech53):
+    om = O.OracleMech(mech53)
+    T, p, Y = O.equilibrium_states(om, 2048, seed=31, perturb=1e-6)
+    check_rates(kx, mech53, T, p, Y, "near equilibrium")
+
+
+def test_edge_states(kx, mech53):
+    ns = 53
+    rows = []
+    for T in (200.0, 300.0, np.nextafter(1000.0, 0), 1000.0, 2800.0, 3500.0):
+        for patm in (0.01, 1.0, 100.0):
+            rows.append((T, patm * O.PATM))
+    Ts = np.array([r[0] for r in rows])
+    ps = np.array([r[1] for r in rows])
+    rng = np.random.default_rng(5)
+    Y = rng.dirichlet(np.full(ns, 0.3), size=Ts.size).T.copy()
+    # pure species and mixtures with absent species
+    pureT = np.full(ns, 1500.0)
+    purep = np.full(ns, 2 * O.PATM)
+    pureY = np.eye(ns)
+    sparse = np.zeros((ns, 8))
+    for c in range(8):
+        sel = rng.choice(ns - 1, 3, replace=False)
+        sparse[sel, c] = rng.dirichlet(np.ones(3))
+    T = np.concatenate([Ts, pureT, np.linspace(400, 2500, 8)])
+    p = np.concatenate([ps, purep, np.full(8, O.PATM)])
+    Yall = np.concatenate([Y, pureY, sparse], axis=1)
+    check_rates(kx, mech53, T, p, Yall, "edge states")
+    check_transport(kx, mech53, T, p, Yall, "edge states")
+
+
+def test_single_point_and_empty(kx, mech9):
+    T, p, Y = I.make_states(9, I.STATES_9, n_points=1)
+    check_rates(kx, mech9, T, p, Y, "n = 1")
+    check_transport(kx, mech9, T, p, Y, "n = 1")
+    dm = dev_mech(kx, mech9)
+    _say("n = 0 no-op")
+    e = torch.empty(0, dtype=torch.float64, device=DEV)
+    w = kx.production_rates(dm, e, e, torch.empty((9, 0), dtype=torch.float64, device=DEV))
+    mu, lam, Dm = kx.transport(dm, e, e, torch.empty((9, 0), dtype=torch.float64, device=DEV))
+    torch.cuda.synchronize()
+    assert w.shape == (9, 0) and Dm.shape == (9, 0)
+
+
+def test_deterministic_and_stream(kx, mech53):
+    T, p, Y = I.make_states(53, I.STATES_53, n_points=20000)
+    dm = dev_mech(kx, mech53)
+    Td, pd, Yd = to_dev(T, p, Y)
+    _say("determinism / side stream")
+    a = kx.production_rates(dm, Td, pd, Yd)
+    mu_a, _, D_a = kx.transport(dm, Td, pd, Yd)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b = kx.production_rates(dm, Td, pd, Yd, stream=s)
+        mu_b, _, D_b = kx.transport(dm, Td, pd, Yd, stream=s)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(mu_a, mu_b) and torch.equal(D_a, D_b)
+
+
+def test_thermo_outputs(kx, mech53):
+    T, p, Y = I.make_states(53, I.STATES_53, n_points=5000)
+    dm = dev_mech(kx, mech53)
+    Td, Yd = to_dev(T, Y)
+    _say("thermo n =", T.size)
+    cpk, hk, cp = kx.thermo(dm, Td, Yd)
+    torch.cuda.synchronize()
+    rcpk, rhk, rcp = O.OracleMech(mech53).mixture_thermo(T, Y)
+    np.testing.assert_allclose(cpk.cpu().numpy(), rcpk, rtol=1e-13)
+    np.testing.assert_allclose(cp.cpu().numpy(), rcp, rtol=1e-13)
+    # h_k = H_k/W_k changes sign: judge against the per-species scale
+    hg = hk.cpu().numpy()
+    scale = np.abs(rhk).max(axis=1, keepdims=True)
+    assert (np.abs(hg - rhk) <= 1e-12 * scale).all()
+
+
+# ------------------------------------------------------------------ mixed path
+def _mixed_workload(mech, n, seed):
+    """Three quarters as the 53-species FP64 workload, one quarter within 1e-6
+    of a constructed equilibrium state, randomly interleaved."""
+    om = O.OracleMech(mech)
+    nq = n // 4
+    T1, p1, Y1 = I.make_states(mech["n_species"], I.StateSpec(
+        n - nq, seed=seed, p_atm_range=(1.0, 40.0), dirichlet_alpha=0.3))
+    T2, p2, Y2 = O.equilibrium_states(om, nq, seed=seed + 1000, perturb=1e-6)
+    T = np.concatenate([T1, T2])
+    p = np.concatenate([p1, p2])
+    Y = np.concatenate([Y1, Y2], axis=1)
+    near = np.concatenate([np.zeros(n - nq, bool), np.ones(nq, bool)])
+    perm = np.random.default_rng(seed).permutation(n)
+    return T[perm], p[perm], np.ascontiguousarray(Y[:, perm]), near[perm]
+
+
+def test_mixed_precision_error_report(kx, mech53):
+    T, p, Y, near = _mixed_workload(mech53, 1 << 14, seed=3)
+    dm = dev_mech(kx, mech53)
+    _say("mixed n =", T.size)
+    w = run_rates(kx, dm, T, p, Y, precision="mixed")
+    mu, lam, Dm = run_transport(kx, dm, T, p, Y, precision="mixed")
+    om = O.OracleMech(mech53)
+    ref, s = om.production_rates(T, p, Y)
+    rmu, rlam, rDm = om.transport(T, p, Y)
+    for part, sel in (("bulk", ~near), ("near-equilibrium", near)):
+        r = PM.mixed_wdot_report(w[:, sel], ref[:, sel], s[:, sel])
+        _say("  wdot", part, r)
+        assert r["ok"], (part, r)
+        for name, g, rr in (("mu", mu[sel], rmu[sel]), ("lambda", lam[sel], rlam[sel]),
+                            ("Dmix", Dm[:, sel], rDm[:, sel])):
+            rep = PM.rel_report(g, rr, PM.REL_MIXED)
+            _say("  ", name, part, rep)
+            assert rep["ok"], (name, part, rep)
