@@ -99,7 +99,7 @@ def main():
     log("generating mechanism and states")
     mech = I.make_mechanism(spec)
     T, p, Y = I.make_states(spec.n_species, sspec, n_points=args.points)
-    n, ns, nr = T.size, mech["n_species"], mech["n_reactions"]
+    n, ns, nr = int(T.size), int(mech["n_species"]), int(mech["n_reactions"])
     dm = kx.Mechanism(mech, 0)
     Td, pd, Yd = [torch.from_numpy(a).to("cuda:0") for a in (T, p, Y)]
     kw = dict(dtype=torch.float64, device="cuda:0")
@@ -128,6 +128,7 @@ def main():
             "transport": (t_ms, ops["transport_flops"], io["transport"])}
     dom = max(kern, key=lambda k: kern[k][0])
     ms, fl, by = kern[dom]
+    fl, by = float(fl), float(by)
     achieved = fl * n / (ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved,
                 "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -136,6 +137,7 @@ def main():
                 "hbm_gbs_compulsory": by * n / (ms * 1e-3) / 1e9}
     other = [k for k in kern if k != dom][0]
     oms, ofl, oby = kern[other]
+    ofl = float(ofl)
     roofline["other_kernel"] = {"kernel": other, "achieved": ofl * n / (oms * 1e-3) / 1e12,
                                 "frac": ofl * n / (oms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS,
                                 "ms": oms}

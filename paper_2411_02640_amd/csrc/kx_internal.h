@@ -16,7 +16,7 @@ constexpr double kRu = 8.31446261815324e7;            // erg / (mol K)
 constexpr double kRcal = 8.31446261815324 / 4.184;    // cal / (mol K)
 constexpr double kPatm = 1013250.0;                   // dyn / cm^2
 
-constexpr int kMaxSide = 4;          // distinct species per reaction side
+constexpr int kMaxSide = 3;          // molecules per reaction side (sum of nu)
 constexpr int kMaxSpecies = 256;     // species per mechanism (4 per lane)
 constexpr int kMaxFitOrder = 8;
 constexpr int kWave = 64;
@@ -27,25 +27,30 @@ enum : uint8_t {
     kFlagKfConst = 2,    // beta = E_R = 0: k_f = A without an exponential
 };
 
-// One reaction in kernel order (reactions sorted by type so that 64-lane
-// chunks mostly share one code path).  64 bytes.
+// One reaction slot in kernel order.  Reactions are sorted heaviest type
+// first (Troe, Lindemann, three-body, elementary, constant-k_f elementary) so
+// that the expensive falloff code runs in as few 64-lane iterations as
+// possible.  Each side lists one LDS byte offset per molecule (a species
+// with nu = 2 appears twice); unused entries point at a dummy species whose
+// per-point factors are 1.  48 bytes.
 struct alignas(16) DevRxn {
-    double lnA;           // ln A
-    double beta;          // temperature exponent
-    double ER;            // activation temperature E_a / R
-    double A;             // A itself (k_f when kFlagKfConst)
-    uint16_t rsp[kMaxSide];  // reactant species (0xFFFF = unused)
-    uint16_t psp[kMaxSide];  // product species
-    uint8_t rnu[kMaxSide];   // nu' (0 = unused)
-    uint8_t pnu[kMaxSide];   // nu''
+    double lnA;              // ln A
+    double beta;             // temperature exponent
+    double ER;               // activation temperature E_a / R
+    double A;                // A itself (k_f when kFlagKfConst)
+    uint16_t roff[kMaxSide]; // reactant molecules: 16 * species
+    uint16_t poff[kMaxSide]; // product molecules
     uint8_t type;            // KX_RXN_*
     uint8_t flags;
     uint16_t aux;            // index into DevAux for types 1..3
-    uint32_t pad;
 };
-static_assert(sizeof(DevRxn) == 64, "DevRxn layout");
+static_assert(sizeof(DevRxn) == 48, "DevRxn layout");
 
-// Third-body and falloff data of one reaction.  96 bytes.
+// Third-body and falloff data of one reaction.  Up to kInlineEff explicit
+// efficiencies are stored inline (LDS byte offset of the species and
+// alpha - default; unused entries point at the dummy species with 0); any
+// further ones are in DevEff[ext_off .. ext_off + ext_cnt).  160 bytes.
+constexpr int kInlineEff = 8;
 struct alignas(16) DevAux {
     double eff_default;      // efficiency of unlisted species
     double lnA0, beta0, ER0; // k_0 (falloff)
@@ -53,10 +58,11 @@ struct alignas(16) DevAux {
     double troe_inv_T3;      // 1 / T***
     double troe_inv_T1;      // 1 / T*
     double troe_T2;          // T** (used when has_T2)
-    int32_t eff_off, eff_cnt;  // slice of DevEff
-    int32_t has_T2, pad;
+    double dalpha[kInlineEff];
+    uint16_t eoff[kInlineEff];
+    int32_t has_T2, ext_off, ext_cnt, pad;
 };
-static_assert(sizeof(DevAux) == 80 || sizeof(DevAux) == 96, "DevAux layout");
+static_assert(sizeof(DevAux) == 160, "DevAux layout");
 
 struct alignas(16) DevEff {
     double dalpha;           // alpha_ki - eff_default
@@ -84,14 +90,18 @@ constexpr int kKB = 8;
 struct MechDev {
     int32_t ns, nr, nchunks;   // species, reactions, reaction chunks for the gather
     int32_t chunk;             // reactions per chunk (multiple of 64)
+    int32_t gpass;             // species passes of the gather (ceil(ns / 64))
     int32_t fit_order, diff_kind;
     double fit_L0, inv_fit_h;
     const DevRxn *rxn;         // [nr] kernel order
     const DevAux *aux;         // [naux]
     const DevEff *eff;         // [neff]
     const DevSpecies *sp;      // [ns]
-    const int32_t *gptr;       // [nchunks][ns+1] species-major gather CSR per chunk
-    const int32_t *gent;       // entries (slot_in_chunk << 8) | (uint8_t)(int8_t) nu
+    const int32_t *glen;       // [nchunks] uniform trip count of the gather
+    const int32_t *goff;       // [nchunks] first entry of each chunk
+    const int32_t *gent;       // [chunk][it][64 * gpass] entries, lane-interleaved:
+                               // (8 * slot_in_chunk) << 8 | (uint8_t)(int8_t) nu; padding
+                               // entries read the zero element after the chunk
     // transport (FP64)
     const double *W;           // [ns]
     const double *visc;        // [ns][order]

@@ -2,13 +2,17 @@
 //
 // Validates a kx_mech_desc, derives every table the gfx950 kernels read and
 // uploads them to the device in one allocation:
-//  * reactions re-ordered by type (elementary, three-body, Lindemann, Troe;
-//    constant-k_f reactions first inside each type) so that a 64-lane chunk of
-//    reactions mostly follows one code path;
+//  * reactions re-ordered heaviest type first (Troe, Lindemann, three-body,
+//    elementary; constant-k_f reactions last inside each type) so that the
+//    falloff code runs in as few 64-lane iterations as possible and a partial
+//    last iteration holds the cheapest reactions;
+//  * each reaction side as a list of LDS byte offsets, one per molecule, padded
+//    with a dummy species whose per-point factors are 1;
 //  * ln A, E_R = E_a / R and the beta = E_R = 0 shortcut of eq:k_f;
 //  * third-body efficiencies as (alpha - default) lists, falloff k_0 and Troe
 //    parameters (inverse temperatures);
-//  * a species-major gather list per reaction chunk for wdot_k = sum_i nu_ki R_i;
+//  * a species-major gather list per reaction chunk for wdot_k = sum_i nu_ki R_i,
+//    padded to one trip count and interleaved for coalesced loads;
 //  * Gibbs coefficients of eq:Ck pre-scaled per range, raw NASA-7 for cp / h;
 //  * Wilke constants c1 = (8 (1 + W_k/W_j))^(-1/2), c2 = (W_j/W_k)^(1/4) as the
 //    three products used by the expanded phi sum, and the ln T fit tables in
@@ -103,9 +107,11 @@ kx_status validate(const kx_mech_desc *d, std::vector<double> &W)
             const int32_t *nu = side ? d->prod_nu : d->reac_nu;
             if (ptr[i] < 0 || ptr[i + 1] < ptr[i])
                 return fail(KX_EINVAL, "kx_mech_create: bad CSR pointer" + ri);
-            if (ptr[i + 1] - ptr[i] > kMaxSide)
+            long molecules = 0;
+            for (int e = ptr[i]; e < ptr[i + 1]; ++e) molecules += nu[e] > 0 ? nu[e] : 0;
+            if (molecules > kMaxSide)
                 return fail(KX_EUNSUPPORTED,
-                            "kx_mech_create: more than 4 species on one side" + ri);
+                            "kx_mech_create: more than 3 molecules on one side" + ri);
             for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
                 if (sp[e] < 0 || sp[e] >= ns)
                     return fail(KX_EINVAL, "kx_mech_create: species index out of range" + ri);
@@ -144,13 +150,13 @@ kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
     if (st != KX_OK) return st;
     const int ns = d->n_species, nr = d->n_reactions, order = d->fit_order;
 
-    // ---- reaction order: by type, constant-k_f first within a type
+    // ---- reaction order: heaviest type first, constant-k_f last within a type
     std::vector<int> perm(nr);
     std::iota(perm.begin(), perm.end(), 0);
     auto kfconst = [&](int i) { return d->beta[i] == 0.0 && d->Ea[i] == 0.0; };
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
-        if (d->rxn_type[a] != d->rxn_type[b]) return d->rxn_type[a] < d->rxn_type[b];
-        return kfconst(a) && !kfconst(b);
+        if (d->rxn_type[a] != d->rxn_type[b]) return d->rxn_type[a] > d->rxn_type[b];
+        return !kfconst(a) && kfconst(b);
     });
 
     std::vector<DevRxn> rx(nr);
@@ -164,17 +170,14 @@ kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
         r.beta = d->beta[i];
         r.ER = d->Ea[i] / kRcal;
         r.A = d->A[i];
-        for (int q = 0; q < kMaxSide; ++q) r.rsp[q] = r.psp[q] = 0xFFFF;
+        const uint16_t dummy = (uint16_t)(16 * ns);
+        for (int q = 0; q < kMaxSide; ++q) r.roff[q] = r.poff[q] = dummy;
         int c = 0;
-        for (int e = d->reac_ptr[i]; e < d->reac_ptr[i + 1]; ++e, ++c) {
-            r.rsp[c] = (uint16_t)d->reac_sp[e];
-            r.rnu[c] = (uint8_t)d->reac_nu[e];
-        }
+        for (int e = d->reac_ptr[i]; e < d->reac_ptr[i + 1]; ++e)
+            for (int v = 0; v < d->reac_nu[e]; ++v) r.roff[c++] = (uint16_t)(16 * d->reac_sp[e]);
         c = 0;
-        for (int e = d->prod_ptr[i]; e < d->prod_ptr[i + 1]; ++e, ++c) {
-            r.psp[c] = (uint16_t)d->prod_sp[e];
-            r.pnu[c] = (uint8_t)d->prod_nu[e];
-        }
+        for (int e = d->prod_ptr[i]; e < d->prod_ptr[i + 1]; ++e)
+            for (int v = 0; v < d->prod_nu[e]; ++v) r.poff[c++] = (uint16_t)(16 * d->prod_sp[e]);
         r.type = (uint8_t)d->rxn_type[i];
         r.flags = (d->reversible[i] ? kFlagReversible : 0) | (kfconst(i) ? kFlagKfConst : 0);
         r.aux = 0xFFFF;
@@ -184,15 +187,27 @@ kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
             DevAux a;
             std::memset(&a, 0, sizeof a);
             a.eff_default = d->eff_default[i];
-            a.eff_off = (int32_t)eff.size();
-            for (int e = d->eff_ptr[i]; e < d->eff_ptr[i + 1]; ++e) {
-                DevEff f;
-                std::memset(&f, 0, sizeof f);
-                f.sp = d->eff_sp[e];
-                f.dalpha = d->eff_val[e] - d->eff_default[i];
-                eff.push_back(f);
+            for (int q = 0; q < kInlineEff; ++q) {
+                a.eoff[q] = (uint16_t)(16 * ns);  // dummy species, alpha - default = 0
+                a.dalpha[q] = 0.0;
             }
-            a.eff_cnt = (int32_t)eff.size() - a.eff_off;
+            int q = 0;
+            a.ext_off = (int32_t)eff.size();
+            for (int e = d->eff_ptr[i]; e < d->eff_ptr[i + 1]; ++e) {
+                const double da = d->eff_val[e] - d->eff_default[i];
+                if (q < kInlineEff) {
+                    a.eoff[q] = (uint16_t)(16 * d->eff_sp[e]);
+                    a.dalpha[q] = da;
+                    ++q;
+                } else {
+                    DevEff f;
+                    std::memset(&f, 0, sizeof f);
+                    f.sp = d->eff_sp[e];
+                    f.dalpha = da;
+                    eff.push_back(f);
+                }
+            }
+            a.ext_cnt = (int32_t)eff.size() - a.ext_off;
             if (r.type >= KX_RXN_LINDEMANN) {
                 a.lnA0 = std::log(d->A0[i]);
                 a.beta0 = d->beta0[i];
@@ -213,38 +228,41 @@ kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
     if (eff.empty()) eff.resize(1);
     if (aux.empty()) aux.resize(1);
 
-    // ---- species-major gather lists per reaction chunk
+    // ---- species-major gather lists per reaction chunk, padded to a uniform
+    // trip count and interleaved so that lane k reads entry (it, k) coalesced
     const int chunk = std::max(kWave, std::min(512, (nr + kWave - 1) / kWave * kWave));
     const int nchunks = std::max(1, (nr + chunk - 1) / chunk);
-    std::vector<int32_t> gptr((size_t)nchunks * (ns + 1));
-    std::vector<int32_t> gent;
+    const int gpass = (ns + kWave - 1) / kWave;
+    const int gw = kWave * gpass;
+    std::vector<int32_t> glen(nchunks), goff(nchunks), gent;
     for (int c = 0; c < nchunks; ++c) {
-        std::vector<std::vector<int32_t>> per(ns);
+        std::vector<std::vector<int32_t>> per(gw);
         for (int s = c * chunk; s < std::min(nr, (c + 1) * chunk); ++s) {
-            const DevRxn &r = rx[s];
+            const int i = perm[s];
             std::vector<std::pair<int, int>> net;  // (species, nu'' - nu')
             auto addnu = [&](int k, int v) {
                 for (auto &pr : net)
                     if (pr.first == k) { pr.second += v; return; }
                 net.push_back({k, v});
             };
-            for (int q = 0; q < kMaxSide; ++q) {
-                if (r.rnu[q]) addnu(r.rsp[q], -(int)r.rnu[q]);
-                if (r.pnu[q]) addnu(r.psp[q], (int)r.pnu[q]);
-            }
+            for (int e = d->reac_ptr[i]; e < d->reac_ptr[i + 1]; ++e)
+                addnu(d->reac_sp[e], -d->reac_nu[e]);
+            for (int e = d->prod_ptr[i]; e < d->prod_ptr[i + 1]; ++e)
+                addnu(d->prod_sp[e], d->prod_nu[e]);
             for (auto &pr : net) {
                 if (pr.second == 0) continue;
-                if (pr.second < -128 || pr.second > 127)
-                    return fail(KX_EUNSUPPORTED, "kx_mech_create: |net nu| > 127");
-                per[pr.first].push_back(((s - c * chunk) << 8) |
+                per[pr.first].push_back(((8 * (s - c * chunk)) << 8) |
                                         (int32_t)(uint8_t)(int8_t)pr.second);
             }
         }
-        for (int k = 0; k < ns; ++k) {
-            gptr[(size_t)c * (ns + 1) + k] = (int32_t)gent.size();
-            gent.insert(gent.end(), per[k].begin(), per[k].end());
-        }
-        gptr[(size_t)c * (ns + 1) + ns] = (int32_t)gent.size();
+        size_t len = 0;
+        for (auto &v : per) len = std::max(len, v.size());
+        len = (len + 7) / 8 * 8;  // the kernel consumes entries eight at a time
+        glen[c] = (int32_t)len;
+        goff[c] = (int32_t)gent.size();
+        const int32_t pad = (8 * chunk) << 8;  // zero element, nu = 0
+        for (size_t it = 0; it < len; ++it)
+            for (int k = 0; k < gw; ++k) gent.push_back(it < per[k].size() ? per[k][it] : pad);
     }
     if (gent.empty()) gent.push_back(0);
 
@@ -282,7 +300,12 @@ kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
         for (int j = 0; j < ns; ++j)
             for (int kk = 0; kk < kKB; ++kk) {
                 const int k = kb * kKB + kk;
-                if (k >= ns) continue;
+                if (k >= ns) {
+                    // padding rows of the last block: a fit identically 1 keeps
+                    // the branch-free pair loop finite (their sums are unused)
+                    dfit[(((size_t)kb * ns + j) * kKB + kk) * order] = 1.0;
+                    continue;
+                }
                 const double c1 = 1.0 / std::sqrt(8.0 * (1.0 + W[k] / W[j]));
                 const double c2 = std::pow(W[j] / W[k], 0.25);
                 double *w = &wilke[(((size_t)kb * ns + j) * kKB + kk) * 3];
@@ -301,7 +324,8 @@ kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
 
     Blob b;
     const size_t o_rxn = add_vec(b, rx), o_aux = add_vec(b, aux), o_eff = add_vec(b, eff);
-    const size_t o_sp = add_vec(b, spv), o_gptr = add_vec(b, gptr), o_gent = add_vec(b, gent);
+    const size_t o_sp = add_vec(b, spv), o_glen = add_vec(b, glen), o_goff = add_vec(b, goff);
+    const size_t o_gent = add_vec(b, gent);
     const size_t o_W = add_vec(b, W), o_visc = add_vec(b, visc), o_cond = add_vec(b, cond);
     const size_t o_wil = add_vec(b, wilke), o_df = add_vec(b, dfit), o_dd = add_vec(b, ddiag);
     const size_t o_visc32 = add_vec(b, to32(visc)), o_cond32 = add_vec(b, to32(cond));
@@ -340,6 +364,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
     v.nr = nr;
     v.chunk = chunk;
     v.nchunks = nchunks;
+    v.gpass = gpass;
     v.fit_order = order;
     v.diff_kind = d->diff_fit_kind;
     v.fit_L0 = d->fit_L0;
@@ -348,7 +373,8 @@ kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
     v.aux = (const DevAux *)at(o_aux);
     v.eff = (const DevEff *)at(o_eff);
     v.sp = (const DevSpecies *)at(o_sp);
-    v.gptr = (const int32_t *)at(o_gptr);
+    v.glen = (const int32_t *)at(o_glen);
+    v.goff = (const int32_t *)at(o_goff);
     v.gent = (const int32_t *)at(o_gent);
     v.W = (const double *)at(o_W);
     v.visc = (const double *)at(o_visc);

@@ -18,28 +18,35 @@
 #include <float.h>
 
 #include "kx_internal.h"
+#include "kx_math.h"
 
 namespace kx {
 namespace {
 
 constexpr int kBlock = 256;
 
+// Horner evaluation of a wave-uniform polynomial (coefficients in scalar
+// registers, constant term first) at a per-lane point.
+__device__ __forceinline__ double fma_u(double a, double b, double c) { return fma_s(a, b, c); }
+__device__ __forceinline__ float fma_u(float a, float b, float c) { return fmaf_s(a, b, c); }
+
 template <int ORDER, class F>
 __device__ __forceinline__ F horner(const F *__restrict__ c, F u, int order)
 {
-    if (ORDER > 0) {
-        F r = c[ORDER - 1];
+    if (ORDER > 1) {
+        F r = u * c[ORDER - 1] + c[ORDER - 2];
 #pragma unroll
-        for (int o = ORDER - 2; o >= 0; --o) r = r * u + c[o];
+        for (int o = ORDER - 3; o >= 0; --o) r = fma_u(r, u, c[o]);
         return r;
     }
+    if (ORDER == 1) return c[0];
     F r = c[order - 1];
-    for (int o = order - 2; o >= 0; --o) r = r * u + c[o];
+    for (int o = order - 2; o >= 0; --o) r = fma_u(r, u, c[o]);
     return r;
 }
 
-// FP64 path.
-template <int ORDER>
+// FP64 path.  KIND is the diffusion fit kind (0: D_kj, 1: 1/D_kj).
+template <int ORDER, int KIND>
 __global__ __launch_bounds__(kBlock) void transport_f64(MechDev m, int64_t n,
                                                         const double *__restrict__ T,
                                                         const double *__restrict__ P,
@@ -64,11 +71,11 @@ __global__ __launch_bounds__(kBlock) void transport_f64(MechDev m, int64_t n,
     for (int k = 0; k < ns; ++k) {
         const double X = Yi[(int64_t)k * n] * m.sp[k].inv_W * xf;
         const double lk = horner<ORDER>(m.cond + k * order, u, order);
-        s1 += X * lk;
-        s2 += X / lk;
-        wbar += X * m.W[k];
+        s1 = fma(X, lk, s1);
+        s2 = fma(X, krcp(lk), s2);
+        wbar = fma(X, m.W[k], wbar);
     }
-    lam[i] = 0.5 * (s1 + 1.0 / s2);
+    lam[i] = 0.5 * (s1 + krcp(s2));
 
     const int nkb = (ns + kKB - 1) / kKB;
     double visc = 0.0;
@@ -77,9 +84,12 @@ __global__ __launch_bounds__(kBlock) void transport_f64(MechDev m, int64_t n,
 #pragma unroll
         for (int kk = 0; kk < kKB; ++kk) S1[kk] = S2[kk] = S3[kk] = 0.0;
         const double *wl = m.wilke + (size_t)kb * ns * kKB * 3;
+        double ynext = Yi[0];
         for (int j = 0; j < ns; ++j, wl += kKB * 3) {
-            const double Xj = Yi[(int64_t)j * n] * m.sp[j].inv_W * xf;
-            const double rj = rsqrt(horner<ORDER>(m.visc + j * order, u, order));
+            const double yj = ynext;
+            if (j + 1 < ns) ynext = Yi[(int64_t)(j + 1) * n];
+            const double Xj = yj * m.sp[j].inv_W * xf;
+            const double rj = krsqrt(horner<ORDER>(m.visc + j * order, u, order));
             const double v = Xj * rj, w = v * rj;
 #pragma unroll
             for (int kk = 0; kk < kKB; ++kk) {
@@ -93,10 +103,10 @@ __global__ __launch_bounds__(kBlock) void transport_f64(MechDev m, int64_t n,
             const int k = kb * kKB + kk;
             if (k < ns) {
                 const double ek = horner<ORDER>(m.visc + k * order, u, order);
-                const double sk = sqrt(ek);
-                const double den = fma(sk * sk, S3[kk], fma(2.0 * sk, S2[kk], S1[kk]));
+                const double sk = ek * krsqrt(ek);
+                const double den = fma(ek, S3[kk], fma(2.0 * sk, S2[kk], S1[kk]));
                 const double Xk = Yi[(int64_t)k * n] * m.sp[k].inv_W * xf;
-                visc += Xk * ek / den;
+                visc = fma(Xk * ek, krcp(den), visc);
             }
         }
     }
@@ -106,19 +116,29 @@ __global__ __launch_bounds__(kBlock) void transport_f64(MechDev m, int64_t n,
         double acc[kKB];
 #pragma unroll
         for (int kk = 0; kk < kKB; ++kk) acc[kk] = 0.0;
-        const double *df = m.dfit + (size_t)kb * ns * kKB * order;
-        for (int j = 0; j < ns; ++j, df += kKB * order) {
-            const double Xj = Yi[(int64_t)j * n] * m.sp[j].inv_W * xf;
+        const double *dfb = m.dfit + (size_t)kb * ns * kKB * order;
+        // sum_{j != k} X_j / D_kj for the kKB species of this block.  Padding
+        // rows (k >= ns) hold a fit identically 1; the j-range that contains
+        // the block's own species masks the diagonal term.
+        auto pairs = [&](int j0, int j1, bool diag) {
+            double ynext = j0 < j1 ? Yi[(int64_t)j0 * n] : 0.0;
+            for (int j = j0; j < j1; ++j) {
+                const double yj = ynext;
+                if (j + 1 < j1) ynext = Yi[(int64_t)(j + 1) * n];
+                const double Xj = yj * m.sp[j].inv_W * xf;
+                const double *df = dfb + (size_t)j * kKB * order;
 #pragma unroll
-            for (int kk = 0; kk < kKB; ++kk) {
-                const int k = kb * kKB + kk;
-                if (k < ns && k != j) {
+                for (int kk = 0; kk < kKB; ++kk) {
                     const double f = horner<ORDER>(df + kk * order, u, order);
-                    // kind 0: 1/D_kj = (p/p_atm) / f; kind 1: 1/D_kj = f (p/p_atm)
-                    acc[kk] += (m.diff_kind == 0) ? Xj / f : Xj * f;
+                    const double x = (diag && kb * kKB + kk == j) ? 0.0 : Xj;
+                    acc[kk] = fma(x, KIND == 0 ? krcp(f) : f, acc[kk]);
                 }
             }
-        }
+        };
+        const int jd0 = kb * kKB, jd1 = min(jd0 + kKB, ns);
+        pairs(0, jd0, false);
+        pairs(jd0, jd1, true);
+        pairs(jd1, ns, false);
 #pragma unroll
         for (int kk = 0; kk < kKB; ++kk) {
             const int k = kb * kKB + kk;
@@ -127,10 +147,10 @@ __global__ __launch_bounds__(kBlock) void transport_f64(MechDev m, int64_t n,
                 double D;
                 if (acc[kk] == 0.0) {
                     const double f = horner<ORDER>(m.ddiag + k * order, u, order);
-                    D = (m.diff_kind == 0) ? f / pr : 1.0 / (f * pr);
+                    D = (KIND == 0) ? f / pr : 1.0 / (f * pr);
                 } else {
                     // sum_{j!=k} X_j / D_kj = (p/p_atm) acc for either fit kind
-                    D = (wbar - Xk * m.W[k]) / wbar / (acc[kk] * pr);
+                    D = (wbar - Xk * m.W[k]) / (wbar * acc[kk] * pr);
                 }
                 Dmix[(int64_t)k * n + i] = D;
             }
@@ -167,8 +187,8 @@ __global__ __launch_bounds__(kBlock) void transport_mixed(MechDev m, int64_t n,
         const double Xd = Yi[(int64_t)k * n] * m.sp[k].inv_W * xf;
         const float X = (float)Xd;
         const float lk = horner<ORDER>(m.cond32 + k * order, u, order);
-        s1 += X * lk;
-        s2 += X / lk;
+        s1 = fmaf(X, lk, s1);
+        s2 += __fdividef(X, lk);
         wbar += Xd * m.W[k];
     }
     lam[i] = (double)(0.5f * (s1 + 1.0f / s2));
@@ -180,8 +200,11 @@ __global__ __launch_bounds__(kBlock) void transport_mixed(MechDev m, int64_t n,
 #pragma unroll
         for (int kk = 0; kk < kKB; ++kk) S1[kk] = S2[kk] = S3[kk] = 0.0f;
         const float *wl = m.wilke32 + (size_t)kb * ns * kKB * 3;
+        double ynext = Yi[0];
         for (int j = 0; j < ns; ++j, wl += kKB * 3) {
-            const float Xj = (float)(Yi[(int64_t)j * n] * m.sp[j].inv_W * xf);
+            const double yj = ynext;
+            if (j + 1 < ns) ynext = Yi[(int64_t)(j + 1) * n];
+            const float Xj = (float)(yj * m.sp[j].inv_W * xf);
             const float rj = rsqrtf(horner<ORDER>(m.visc32 + j * order, u, order));
             const float v = Xj * rj, w = v * rj;
 #pragma unroll
@@ -199,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void transport_mixed(MechDev m, int64_t n,
                 const float sk = sqrtf(ek);
                 const float den = fmaf(sk * sk, S3[kk], fmaf(2.0f * sk, S2[kk], S1[kk]));
                 const float Xk = (float)(Yi[(int64_t)k * n] * m.sp[k].inv_W * xf);
-                visc += Xk * ek / den;
+                visc += __fdividef(Xk * ek, den);
             }
         }
     }
@@ -210,14 +233,17 @@ __global__ __launch_bounds__(kBlock) void transport_mixed(MechDev m, int64_t n,
 #pragma unroll
         for (int kk = 0; kk < kKB; ++kk) acc[kk] = 0.0f;
         const float *df = m.dfit32 + (size_t)kb * ns * kKB * order;
+        double ynext = Yi[0];
         for (int j = 0; j < ns; ++j, df += kKB * order) {
-            const float Xj = (float)(Yi[(int64_t)j * n] * m.sp[j].inv_W * xf);
+            const double yj = ynext;
+            if (j + 1 < ns) ynext = Yi[(int64_t)(j + 1) * n];
+            const float Xj = (float)(yj * m.sp[j].inv_W * xf);
 #pragma unroll
             for (int kk = 0; kk < kKB; ++kk) {
                 const int k = kb * kKB + kk;
                 if (k < ns && k != j) {
                     const float f = horner<ORDER>(df + kk * order, u, order);
-                    acc[kk] += (m.diff_kind == 0) ? Xj / f : Xj * f;
+                    acc[kk] += (m.diff_kind == 0) ? __fdividef(Xj, f) : Xj * f;
                 }
             }
         }
@@ -286,7 +312,8 @@ kx_status launch_transport(const kx_mech *mech, int64_t n, const double *T, cons
         hipLaunchKernelGGL(k, dim3((unsigned)nblk), dim3(kBlock), 0, s, m, n, T, p, Y, mu,
                            lam, Dmix);
     } else {
-        auto k = o5 ? transport_f64<5> : transport_f64<0>;
+        auto k = m.diff_kind == 0 ? (o5 ? transport_f64<5, 0> : transport_f64<0, 0>)
+                                  : (o5 ? transport_f64<5, 1> : transport_f64<0, 1>);
         hipLaunchKernelGGL(k, dim3((unsigned)nblk), dim3(kBlock), 0, s, m, n, T, p, Y, mu,
                            lam, Dmix);
     }
