@@ -83,8 +83,8 @@ struct alignas(16) DevSpecies {
 };
 static_assert(sizeof(DevSpecies) == 256, "DevSpecies layout");
 
-// Transport k-blocking factor: the Wilke and D_km sums run over all j for a
-// block of kKB species k held in registers.
+// Transport tables are blocked by kKB species k so that the coefficients of
+// one (k-block, j) step are contiguous for scalar loads.
 constexpr int kKB = 8;
 
 struct MechDev {
@@ -106,11 +106,12 @@ struct MechDev {
     const double *W;           // [ns]
     const double *visc;        // [ns][order]
     const double *cond;        // [ns][order]
-    const double *wilke;       // [nkb][ns][kKB][3]   c1, c1 c2, c1 c2^2
+    const double *wq;          // [ns] W_k^(1/4)
+    const double *wilke;       // [nkb][ns][kKB] c1_kj = (8 (1 + W_k/W_j))^(-1/2)
     const double *dfit;        // [nkb][ns][kKB][order]  fit of (k = kb*KB+kk, j)
     const double *ddiag;       // [ns][order] diagonal fits for the fallback
     // transport (FP32 copies for the mixed path)
-    const float *visc32, *cond32, *wilke32, *dfit32, *ddiag32;
+    const float *visc32, *cond32, *wq32, *wilke32, *dfit32, *ddiag32;
 };
 
 }  // namespace kx

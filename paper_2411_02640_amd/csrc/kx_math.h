@@ -83,6 +83,14 @@ __device__ __forceinline__ double krcp(double d)
     return __builtin_fma(r, e, r);
 }
 
+// One Newton step only: about 2^-48 relative error (v_rcp_f64's ~2^-24
+// squared), used where the result feeds a sum of positive terms.
+__device__ __forceinline__ double krcp1(double d)
+{
+    const double r = __builtin_amdgcn_rcp(d);
+    return __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+}
+
 __device__ __forceinline__ double krsqrt(double x)
 {
     double r = __builtin_amdgcn_rsq(x);

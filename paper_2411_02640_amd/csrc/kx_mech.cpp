@@ -14,9 +14,9 @@
 //  * a species-major gather list per reaction chunk for wdot_k = sum_i nu_ki R_i,
 //    padded to one trip count and interleaved for coalesced loads;
 //  * Gibbs coefficients of eq:Ck pre-scaled per range, raw NASA-7 for cp / h;
-//  * Wilke constants c1 = (8 (1 + W_k/W_j))^(-1/2), c2 = (W_j/W_k)^(1/4) as the
-//    three products used by the expanded phi sum, and the ln T fit tables in
-//    the k-blocked order of the transport kernel, in FP64 and FP32.
+//  * Wilke constants c1_kj = (8 (1 + W_k/W_j))^(-1/2) and W_k^(1/4) (so that
+//    (W_j/W_k)^(1/4) separates into per-species factors), and the ln T fit
+//    tables in the k-blocked order of the transport kernel, in FP64 and FP32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -293,7 +293,8 @@ kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
     std::vector<double> visc((size_t)ns * order), cond((size_t)ns * order);
     std::memcpy(visc.data(), d->visc_fit, visc.size() * sizeof(double));
     std::memcpy(cond.data(), d->cond_fit, cond.size() * sizeof(double));
-    std::vector<double> wilke((size_t)nkb * ns * kKB * 3, 0.0);
+    std::vector<double> wilke((size_t)nkb * ns * kKB, 0.0), wq(ns);
+    for (int k = 0; k < ns; ++k) wq[k] = std::pow(W[k], 0.25);
     std::vector<double> dfit((size_t)nkb * ns * kKB * order, 0.0);
     std::vector<double> ddiag((size_t)ns * order);
     for (int kb = 0; kb < nkb; ++kb)
@@ -306,12 +307,9 @@ kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
                     dfit[(((size_t)kb * ns + j) * kKB + kk) * order] = 1.0;
                     continue;
                 }
-                const double c1 = 1.0 / std::sqrt(8.0 * (1.0 + W[k] / W[j]));
-                const double c2 = std::pow(W[j] / W[k], 0.25);
-                double *w = &wilke[(((size_t)kb * ns + j) * kKB + kk) * 3];
-                w[0] = c1;
-                w[1] = c1 * c2;
-                w[2] = c1 * c2 * c2;
+                // phi_kj = c1_kj (1 + sigma_k rho_j)^2 with c2_kj = (W_j/W_k)^(1/4)
+                // = wq_j / wq_k folded into the per-species factors
+                wilke[((size_t)kb * ns + j) * kKB + kk] = 1.0 / std::sqrt(8.0 * (1.0 + W[k] / W[j]));
                 std::memcpy(&dfit[(((size_t)kb * ns + j) * kKB + kk) * order],
                             d->diff_fit + ((size_t)k * ns + j) * order, order * sizeof(double));
             }
@@ -328,6 +326,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
     const size_t o_gent = add_vec(b, gent);
     const size_t o_W = add_vec(b, W), o_visc = add_vec(b, visc), o_cond = add_vec(b, cond);
     const size_t o_wil = add_vec(b, wilke), o_df = add_vec(b, dfit), o_dd = add_vec(b, ddiag);
+    const size_t o_wq = add_vec(b, wq), o_wq32 = add_vec(b, to32(wq));
     const size_t o_visc32 = add_vec(b, to32(visc)), o_cond32 = add_vec(b, to32(cond));
     const size_t o_wil32 = add_vec(b, to32(wilke)), o_df32 = add_vec(b, to32(dfit));
     const size_t o_dd32 = add_vec(b, to32(ddiag));
@@ -380,6 +379,8 @@ kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
     v.visc = (const double *)at(o_visc);
     v.cond = (const double *)at(o_cond);
     v.wilke = (const double *)at(o_wil);
+    v.wq = (const double *)at(o_wq);
+    v.wq32 = (const float *)at(o_wq32);
     v.dfit = (const double *)at(o_df);
     v.ddiag = (const double *)at(o_dd);
     v.visc32 = (const float *)at(o_visc32);

@@ -1,21 +1,25 @@
 // kx_transport.hip -- mixture-averaged transport and mixture thermo on gfx950.
 //
-// One grid point per lane.  Every mechanism constant is wave-uniform, so the
-// compiler keeps it in scalar registers (one scalar load serves 64 points).
-// The quadratic sums run over a block of kKB species k held in registers
-// while j streams over all species; X_j is recomputed from Y_j (a coalesced,
-// L2-resident re-read) instead of being held per lane.
+// Each lane evaluates P grid points.  Every mechanism constant is
+// wave-uniform, so it is read with scalar loads into scalar registers and used
+// directly as an instruction operand; one fetched coefficient serves the P
+// points of all 64 lanes.  The quadratic sums run over a block of KB species k
+// held in registers while j streams over all species; X_j is recomputed from
+// Y_j (a coalesced re-read) instead of being held per lane.
 //
 //  * pure species (App. A.3 "Polynomial fits"): eta_k, lambda_k, D_kj as
 //    polynomials in u = (ln T - L0)/h (Horner), D_kj divided by p/p_atm;
-//  * Wilke / Bird viscosity with the squared bracket expanded:
-//      sum_j X_j phi_kj = sum_j c1 X_j + 2 s_k sum_j c1 c2 X_j r_j
-//                         + s_k^2 sum_j c1 c2^2 X_j r_j^2,
-//    s_k = sqrt(eta_k), r_j = 1/sqrt(eta_j), c1 = (8 (1 + W_k/W_j))^(-1/2),
-//    c2 = (W_j/W_k)^(1/4) -- three FMAs per pair, all terms positive;
+//  * Wilke / Bird viscosity with phi_kj = c1_kj (1 + sigma_k rho_j)^2, where
+//    c1_kj = (8 (1 + W_k/W_j))^(-1/2), sigma_k = sqrt(eta_k) / W_k^(1/4) and
+//    rho_j = W_j^(1/4) / sqrt(eta_j): (W_j/W_k)^(1/4) separates into
+//    per-species factors, so each pair reads one coefficient;
 //  * Mathur conductivity; eq:mix_diff for D_km with the full (k, j) matrix
-//    evaluated (no symmetric reuse, so nothing but kKB accumulators is live).
+//    evaluated (no symmetric reuse, so only the KB accumulators are live),
+//    1/D_kj by v_rcp_f64 and one Newton step (each term of this positive
+//    sum then carries about 2^-48 relative error).
 #include <float.h>
+
+#include <type_traits>
 
 #include "kx_internal.h"
 #include "kx_math.h"
@@ -45,225 +49,192 @@ __device__ __forceinline__ F horner(const F *__restrict__ c, F u, int order)
     return r;
 }
 
-// FP64 path.  KIND is the diffusion fit kind (0: D_kj, 1: 1/D_kj).
-template <int ORDER, int KIND>
-__global__ __launch_bounds__(kBlock) void transport_f64(MechDev m, int64_t n,
-                                                        const double *__restrict__ T,
-                                                        const double *__restrict__ P,
-                                                        const double *__restrict__ Y,
-                                                        double *__restrict__ mu,
-                                                        double *__restrict__ lam,
-                                                        double *__restrict__ Dmix)
+// Mixture-averaged transport for P points per lane.  F is the arithmetic
+// type of the fits and mixing sums (double: FP64 path; float: mixed path);
+// KIND is the diffusion fit kind (0: D_kj, 1: 1/D_kj); KB species k are held
+// in registers per step of the j loop, which serves the Wilke and the D_km
+// sums together.  Every uniform coefficient fetched by a scalar load feeds
+// P lanes' worth of arithmetic.
+template <class F> __device__ __forceinline__ F rcp_fast(F x);
+template <> __device__ __forceinline__ double rcp_fast<double>(double x) { return krcp1(x); }
+template <> __device__ __forceinline__ float rcp_fast<float>(float x)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+    return __builtin_amdgcn_rcpf(x);
+}
+template <class F> __device__ __forceinline__ F rsqrt_acc(F x);
+template <> __device__ __forceinline__ double rsqrt_acc<double>(double x) { return krsqrt(x); }
+template <> __device__ __forceinline__ float rsqrt_acc<float>(float x) { return rsqrtf(x); }
+template <class F> __device__ __forceinline__ F rcp_acc(F x);
+template <> __device__ __forceinline__ double rcp_acc<double>(double x) { return krcp(x); }
+template <> __device__ __forceinline__ float rcp_acc<float>(float x) { return 1.0f / x; }
+
+template <class F> struct Tabs;
+template <> struct Tabs<double> {
+    static __device__ const double *visc(const MechDev &m) { return m.visc; }
+    static __device__ const double *cond(const MechDev &m) { return m.cond; }
+    static __device__ const double *wq(const MechDev &m) { return m.wq; }
+    static __device__ const double *wilke(const MechDev &m) { return m.wilke; }
+    static __device__ const double *dfit(const MechDev &m) { return m.dfit; }
+    static __device__ const double *ddiag(const MechDev &m) { return m.ddiag; }
+};
+template <> struct Tabs<float> {
+    static __device__ const float *visc(const MechDev &m) { return m.visc32; }
+    static __device__ const float *cond(const MechDev &m) { return m.cond32; }
+    static __device__ const float *wq(const MechDev &m) { return m.wq32; }
+    static __device__ const float *wilke(const MechDev &m) { return m.wilke32; }
+    static __device__ const float *dfit(const MechDev &m) { return m.dfit32; }
+    static __device__ const float *ddiag(const MechDev &m) { return m.ddiag32; }
+};
+
+template <class F, int ORDER, int KIND, int P, int KB>
+__global__ __launch_bounds__(kBlock) void transport_kernel(MechDev m, int64_t n,
+                                                           const double *__restrict__ T,
+                                                           const double *__restrict__ Pp,
+                                                           const double *__restrict__ Y,
+                                                           double *__restrict__ mu,
+                                                           double *__restrict__ lam,
+                                                           double *__restrict__ Dmix)
+{
+    using Tb = Tabs<F>;
     const int ns = m.ns, order = m.fit_order;
-    const double Ti = T[i], pi = P[i];
-    const double u = (log(Ti) - m.fit_L0) * m.inv_fit_h;
-    const double pr = pi / kPatm;
-    const double *Yi = Y + i;
-
-    double sYW = 0.0;
-    for (int k = 0; k < ns; ++k) sYW += Yi[(int64_t)k * n] * m.sp[k].inv_W;
-    const double xf = 1.0 / sYW;  // X_k = Y_k / W_k * xf
-
-    double s1 = 0.0, s2 = 0.0, wbar = 0.0;
-    for (int k = 0; k < ns; ++k) {
-        const double X = Yi[(int64_t)k * n] * m.sp[k].inv_W * xf;
-        const double lk = horner<ORDER>(m.cond + k * order, u, order);
-        s1 = fma(X, lk, s1);
-        s2 = fma(X, krcp(lk), s2);
-        wbar = fma(X, m.W[k], wbar);
+    // point q of this lane: i[q] (clamped to n - 1 past the end; not stored)
+    int64_t idx[P];
+    bool act[P];
+    F u[P];
+    double pr[P], xf[P], wbar[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int64_t ir = (int64_t)blockIdx.x * kBlock * P + threadIdx.x + (int64_t)kBlock * q;
+        act[q] = ir < n;
+        idx[q] = act[q] ? ir : n - 1;
+        const double Ti = T[idx[q]];
+        u[q] = (F)((log(Ti) - m.fit_L0) * m.inv_fit_h);
+        pr[q] = Pp[idx[q]] / kPatm;
     }
-    lam[i] = 0.5 * (s1 + krcp(s2));
+    auto Yat = [&](int k, int q) { return Y[(int64_t)k * n + idx[q]]; };
 
-    const int nkb = (ns + kKB - 1) / kKB;
-    double visc = 0.0;
-    for (int kb = 0; kb < nkb; ++kb) {
-        double S1[kKB], S2[kKB], S3[kKB];
+    // X_k = (Y_k / W_k) xf; W-bar = sum_k X_k W_k; Mathur conductivity
+    {
+        double sYW[P];
 #pragma unroll
-        for (int kk = 0; kk < kKB; ++kk) S1[kk] = S2[kk] = S3[kk] = 0.0;
-        const double *wl = m.wilke + (size_t)kb * ns * kKB * 3;
-        double ynext = Yi[0];
-        for (int j = 0; j < ns; ++j, wl += kKB * 3) {
-            const double yj = ynext;
-            if (j + 1 < ns) ynext = Yi[(int64_t)(j + 1) * n];
-            const double Xj = yj * m.sp[j].inv_W * xf;
-            const double rj = krsqrt(horner<ORDER>(m.visc + j * order, u, order));
-            const double v = Xj * rj, w = v * rj;
+        for (int q = 0; q < P; ++q) sYW[q] = 0.0;
+        for (int k = 0; k < ns; ++k) {
+            const double iw = m.sp[k].inv_W;
 #pragma unroll
-            for (int kk = 0; kk < kKB; ++kk) {
-                S1[kk] = fma(wl[3 * kk + 0], Xj, S1[kk]);
-                S2[kk] = fma(wl[3 * kk + 1], v, S2[kk]);
-                S3[kk] = fma(wl[3 * kk + 2], w, S3[kk]);
+            for (int q = 0; q < P; ++q) sYW[q] = fma(Yat(k, q), iw, sYW[q]);
+        }
+        F s1[P], s2[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            xf[q] = 1.0 / sYW[q];
+            wbar[q] = 0.0;
+            s1[q] = s2[q] = (F)0;
+        }
+        for (int k = 0; k < ns; ++k) {
+            const double iw = m.sp[k].inv_W, Wk = m.W[k];
+            const F *cf = Tb::cond(m) + k * order;
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const double X = Yat(k, q) * iw * xf[q];
+                const F lk = horner<ORDER>(cf, u[q], order);
+                s1[q] = fma((F)X, lk, s1[q]);
+                s2[q] = fma((F)X, rcp_acc(lk), s2[q]);
+                wbar[q] = fma(X, Wk, wbar[q]);
             }
         }
 #pragma unroll
-        for (int kk = 0; kk < kKB; ++kk) {
-            const int k = kb * kKB + kk;
-            if (k < ns) {
-                const double ek = horner<ORDER>(m.visc + k * order, u, order);
-                const double sk = ek * krsqrt(ek);
-                const double den = fma(ek, S3[kk], fma(2.0 * sk, S2[kk], S1[kk]));
-                const double Xk = Yi[(int64_t)k * n] * m.sp[k].inv_W * xf;
-                visc = fma(Xk * ek, krcp(den), visc);
+        for (int q = 0; q < P; ++q)
+            if (act[q]) lam[idx[q]] = (double)((F)0.5 * (s1[q] + rcp_acc(s2[q])));
+    }
+
+    F visc[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) visc[q] = (F)0;
+    const int nkb = (ns + KB - 1) / KB;
+    for (int kb = 0; kb < nkb; ++kb) {
+        // table rows of this block inside the kKB-blocked tables
+        const int tb = (kb * KB) / kKB, toff = (kb * KB) % kKB;
+        F sig[P][KB], den[P][KB], acc[P][KB];
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+            const int k = kb * KB + kk;
+            const bool valid = k < ns;
+            const int kc = valid ? k : 0;
+            const F wk = Tb::wq(m)[kc];
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const F ek = horner<ORDER>(Tb::visc(m) + kc * order, u[q], order);
+                // sigma_k = sqrt(eta_k) / W_k^(1/4)
+                sig[q][kk] = valid ? ek * rsqrt_acc(ek) * rcp_acc(wk) : (F)0;
+                den[q][kk] = acc[q][kk] = (F)0;
             }
         }
-    }
-    mu[i] = visc;
-
-    for (int kb = 0; kb < nkb; ++kb) {
-        double acc[kKB];
-#pragma unroll
-        for (int kk = 0; kk < kKB; ++kk) acc[kk] = 0.0;
-        const double *dfb = m.dfit + (size_t)kb * ns * kKB * order;
-        // sum_{j != k} X_j / D_kj for the kKB species of this block.  Padding
-        // rows (k >= ns) hold a fit identically 1; the j-range that contains
-        // the block's own species masks the diagonal term.
-        auto pairs = [&](int j0, int j1, bool diag) {
-            double ynext = j0 < j1 ? Yi[(int64_t)j0 * n] : 0.0;
+        const F *c1b = Tb::wilke(m) + (size_t)tb * ns * kKB + toff;
+        const F *dfb = Tb::dfit(m) + ((size_t)tb * ns * kKB + toff) * order;
+        auto steps = [&](int j0, int j1, bool diag) {
             for (int j = j0; j < j1; ++j) {
-                const double yj = ynext;
-                if (j + 1 < j1) ynext = Yi[(int64_t)(j + 1) * n];
-                const double Xj = yj * m.sp[j].inv_W * xf;
-                const double *df = dfb + (size_t)j * kKB * order;
+                const double iw = m.sp[j].inv_W;
+                const F wj = Tb::wq(m)[j];
+                const F *vj = Tb::visc(m) + j * order;
+                F Xj[P], rho[P];
 #pragma unroll
-                for (int kk = 0; kk < kKB; ++kk) {
-                    const double f = horner<ORDER>(df + kk * order, u, order);
-                    const double x = (diag && kb * kKB + kk == j) ? 0.0 : Xj;
-                    acc[kk] = fma(x, KIND == 0 ? krcp(f) : f, acc[kk]);
+                for (int q = 0; q < P; ++q) {
+                    Xj[q] = (F)(Yat(j, q) * iw * xf[q]);
+                    // rho_j = W_j^(1/4) / sqrt(eta_j)
+                    rho[q] = wj * rsqrt_acc(horner<ORDER>(vj, u[q], order));
+                }
+                const F *c1 = c1b + (size_t)j * kKB;
+                const F *df = dfb + (size_t)j * kKB * order;
+#pragma unroll
+                for (int kk = 0; kk < KB; ++kk) {
+                    const F c = c1[kk];
+                    const bool self = diag && kb * KB + kk == j;
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        // Wilke: X_j phi_kj = c1 X_j (1 + sigma_k rho_j)^2
+                        const F t = fma(sig[q][kk], rho[q], (F)1);
+                        const F xt = Xj[q] * t;
+                        den[q][kk] = fma(c, xt * t, den[q][kk]);
+                        // D_km: X_j / D_kj (j != k)
+                        const F f = horner<ORDER>(df + kk * order, u[q], order);
+                        const F x = self ? (F)0 : Xj[q];
+                        acc[q][kk] = fma(x, KIND == 0 ? rcp_fast(f) : f, acc[q][kk]);
+                    }
                 }
             }
         };
-        const int jd0 = kb * kKB, jd1 = min(jd0 + kKB, ns);
-        pairs(0, jd0, false);
-        pairs(jd0, jd1, true);
-        pairs(jd1, ns, false);
+        const int jd0 = kb * KB, jd1 = min(jd0 + KB, ns);
+        steps(0, jd0, false);
+        steps(jd0, jd1, true);
+        steps(jd1, ns, false);
 #pragma unroll
-        for (int kk = 0; kk < kKB; ++kk) {
-            const int k = kb * kKB + kk;
+        for (int kk = 0; kk < KB; ++kk) {
+            const int k = kb * KB + kk;
             if (k < ns) {
-                const double Xk = Yi[(int64_t)k * n] * m.sp[k].inv_W * xf;
-                double D;
-                if (acc[kk] == 0.0) {
-                    const double f = horner<ORDER>(m.ddiag + k * order, u, order);
-                    D = (KIND == 0) ? f / pr : 1.0 / (f * pr);
-                } else {
-                    // sum_{j!=k} X_j / D_kj = (p/p_atm) acc for either fit kind
-                    D = (wbar - Xk * m.W[k]) / (wbar * acc[kk] * pr);
-                }
-                Dmix[(int64_t)k * n + i] = D;
-            }
-        }
-    }
-}
-
-// Mixed path: fits and mixing sums in FP32 with FP32 accumulation; the
-// D_km numerator (W-bar - X_k W_k)/W-bar in FP64.
-template <int ORDER>
-__global__ __launch_bounds__(kBlock) void transport_mixed(MechDev m, int64_t n,
-                                                          const double *__restrict__ T,
-                                                          const double *__restrict__ P,
-                                                          const double *__restrict__ Y,
-                                                          double *__restrict__ mu,
-                                                          double *__restrict__ lam,
-                                                          double *__restrict__ Dmix)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int ns = m.ns, order = m.fit_order;
-    const double Ti = T[i], pi = P[i];
-    const float u = (float)((log(Ti) - m.fit_L0) * m.inv_fit_h);
-    const float pr = (float)(pi / kPatm);
-    const double *Yi = Y + i;
-
-    double sYW = 0.0;
-    for (int k = 0; k < ns; ++k) sYW += Yi[(int64_t)k * n] * m.sp[k].inv_W;
-    const double xf = 1.0 / sYW;
-
-    float s1 = 0.0f, s2 = 0.0f;
-    double wbar = 0.0;
-    for (int k = 0; k < ns; ++k) {
-        const double Xd = Yi[(int64_t)k * n] * m.sp[k].inv_W * xf;
-        const float X = (float)Xd;
-        const float lk = horner<ORDER>(m.cond32 + k * order, u, order);
-        s1 = fmaf(X, lk, s1);
-        s2 += __fdividef(X, lk);
-        wbar += Xd * m.W[k];
-    }
-    lam[i] = (double)(0.5f * (s1 + 1.0f / s2));
-
-    const int nkb = (ns + kKB - 1) / kKB;
-    float visc = 0.0f;
-    for (int kb = 0; kb < nkb; ++kb) {
-        float S1[kKB], S2[kKB], S3[kKB];
+                const double iw = m.sp[k].inv_W, Wk = m.W[k];
+                const F *ek_c = Tb::visc(m) + k * order;
 #pragma unroll
-        for (int kk = 0; kk < kKB; ++kk) S1[kk] = S2[kk] = S3[kk] = 0.0f;
-        const float *wl = m.wilke32 + (size_t)kb * ns * kKB * 3;
-        double ynext = Yi[0];
-        for (int j = 0; j < ns; ++j, wl += kKB * 3) {
-            const double yj = ynext;
-            if (j + 1 < ns) ynext = Yi[(int64_t)(j + 1) * n];
-            const float Xj = (float)(yj * m.sp[j].inv_W * xf);
-            const float rj = rsqrtf(horner<ORDER>(m.visc32 + j * order, u, order));
-            const float v = Xj * rj, w = v * rj;
-#pragma unroll
-            for (int kk = 0; kk < kKB; ++kk) {
-                S1[kk] = fmaf(wl[3 * kk + 0], Xj, S1[kk]);
-                S2[kk] = fmaf(wl[3 * kk + 1], v, S2[kk]);
-                S3[kk] = fmaf(wl[3 * kk + 2], w, S3[kk]);
-            }
-        }
-#pragma unroll
-        for (int kk = 0; kk < kKB; ++kk) {
-            const int k = kb * kKB + kk;
-            if (k < ns) {
-                const float ek = horner<ORDER>(m.visc32 + k * order, u, order);
-                const float sk = sqrtf(ek);
-                const float den = fmaf(sk * sk, S3[kk], fmaf(2.0f * sk, S2[kk], S1[kk]));
-                const float Xk = (float)(Yi[(int64_t)k * n] * m.sp[k].inv_W * xf);
-                visc += __fdividef(Xk * ek, den);
-            }
-        }
-    }
-    mu[i] = (double)visc;
-
-    for (int kb = 0; kb < nkb; ++kb) {
-        float acc[kKB];
-#pragma unroll
-        for (int kk = 0; kk < kKB; ++kk) acc[kk] = 0.0f;
-        const float *df = m.dfit32 + (size_t)kb * ns * kKB * order;
-        double ynext = Yi[0];
-        for (int j = 0; j < ns; ++j, df += kKB * order) {
-            const double yj = ynext;
-            if (j + 1 < ns) ynext = Yi[(int64_t)(j + 1) * n];
-            const float Xj = (float)(yj * m.sp[j].inv_W * xf);
-#pragma unroll
-            for (int kk = 0; kk < kKB; ++kk) {
-                const int k = kb * kKB + kk;
-                if (k < ns && k != j) {
-                    const float f = horner<ORDER>(df + kk * order, u, order);
-                    acc[kk] += (m.diff_kind == 0) ? __fdividef(Xj, f) : Xj * f;
+                for (int q = 0; q < P; ++q) {
+                    const double Xk = Yat(k, q) * iw * xf[q];
+                    const F ek = horner<ORDER>(ek_c, u[q], order);
+                    visc[q] = fma((F)Xk * ek, rcp_acc(den[q][kk]), visc[q]);
+                    double D;
+                    if (acc[q][kk] == (F)0) {
+                        const F f = horner<ORDER>(Tb::ddiag(m) + k * order, u[q], order);
+                        D = (KIND == 0) ? (double)f / pr[q] : 1.0 / ((double)f * pr[q]);
+                    } else {
+                        // sum_{j!=k} X_j / D_kj = (p/p_atm) acc for either fit kind;
+                        // the numerator (W-bar - X_k W_k)/W-bar is formed in FP64
+                        D = (wbar[q] - Xk * Wk) / (wbar[q] * (double)acc[q][kk] * pr[q]);
+                    }
+                    if (act[q]) Dmix[(int64_t)k * n + idx[q]] = D;
                 }
             }
         }
-#pragma unroll
-        for (int kk = 0; kk < kKB; ++kk) {
-            const int k = kb * kKB + kk;
-            if (k < ns) {
-                const double Xk = Yi[(int64_t)k * n] * m.sp[k].inv_W * xf;
-                double D;
-                if (acc[kk] == 0.0f) {
-                    const float f = horner<ORDER>(m.ddiag32 + k * order, u, order);
-                    D = (m.diff_kind == 0) ? (double)(f / pr) : (double)(1.0f / (f * pr));
-                } else {
-                    const double num = (wbar - Xk * m.W[k]) / wbar;
-                    D = num / (double)(acc[kk] * pr);
-                }
-                Dmix[(int64_t)k * n + i] = D;
-            }
-        }
     }
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+        if (act[q]) mu[idx[q]] = (double)visc[q];
 }
 
 // Mixture thermo (App. A.1): cp_k = Cp_k/W_k, h_k = H_k/W_k, cp = sum Y_k cp_k.
@@ -304,22 +275,29 @@ kx_status launch_transport(const kx_mech *mech, int64_t n, const double *T, cons
                            int precision, hipStream_t s)
 {
     const MechDev &m = mech->dev;
-    const int64_t nblk = (n + kBlock - 1) / kBlock;
-    if (nblk > 0x7fffffff) return fail(KX_EINVAL, "transport: n too large");
-    const bool o5 = m.fit_order == 5;
-    if (precision == KX_MIXED) {
-        auto k = o5 ? transport_mixed<5> : transport_mixed<0>;
-        hipLaunchKernelGGL(k, dim3((unsigned)nblk), dim3(kBlock), 0, s, m, n, T, p, Y, mu,
-                           lam, Dmix);
-    } else {
-        auto k = m.diff_kind == 0 ? (o5 ? transport_f64<5, 0> : transport_f64<0, 0>)
-                                  : (o5 ? transport_f64<5, 1> : transport_f64<0, 1>);
-        hipLaunchKernelGGL(k, dim3((unsigned)nblk), dim3(kBlock), 0, s, m, n, T, p, Y, mu,
-                           lam, Dmix);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "transport kernel launch");
-    return ok();
+    auto go = [&](auto fz, auto pz, auto kbz) -> kx_status {
+        using F = decltype(fz);
+        constexpr int PP = decltype(pz)::value, KB = decltype(kbz)::value;
+        const int64_t per = (int64_t)kBlock * PP;
+        const int64_t nblk = (n + per - 1) / per;
+        if (nblk > 0x7fffffff) return fail(KX_EINVAL, "transport: n too large");
+        const bool o5 = m.fit_order == 5;
+        auto k = m.diff_kind == 0
+                     ? (o5 ? transport_kernel<F, 5, 0, PP, KB> : transport_kernel<F, 0, 0, PP, KB>)
+                     : (o5 ? transport_kernel<F, 5, 1, PP, KB> : transport_kernel<F, 0, 1, PP, KB>);
+        hipLaunchKernelGGL(k, dim3((unsigned)nblk), dim3(kBlock), 0, s, m, n, T, p, Y, mu, lam,
+                           Dmix);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "transport kernel launch");
+        return ok();
+    };
+    // Points per lane and k-block size, measured on the 53-species workload:
+    // FP64 is bound by the scalar-coefficient stream, so four points share
+    // each fetched coefficient; the FP32 path carries half the registers per
+    // value and prefers wider k-blocks.
+    if (precision == KX_MIXED)
+        return go(0.0f, std::integral_constant<int, 2>{}, std::integral_constant<int, 8>{});
+    return go(0.0, std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{});
 }
 
 kx_status launch_thermo(const kx_mech *mech, int64_t n, const double *T, const double *Y,
