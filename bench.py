@@ -24,6 +24,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFLOPS = 78.6
 FP32_VALU_PEAK_TFLOPS = 157.3
+SERVE_SEED = 5
+SERVE_LOADS = (0.25, 0.5, 0.75, 0.9, 1.1)
 
 
 def log(*a):
@@ -75,6 +77,65 @@ def cpu_baseline(mech, T, p, Y, target_s=12.0):
                       f"{dt:.1f} s on {threads} threads"}
 
 
+def serve_bench(kx, args):
+    """Served workload: Poisson stream over the 9-, 53- and 200-species
+    mechanisms, n = round(10^U(3,6)), ops and precision 50/50, at fractions of
+    the measured back-to-back capacity."""
+    import numpy as np
+    import torch
+
+    from paper_2411_02640_amd import inputs as I
+    from paper_2411_02640_amd import serve_load as SL
+
+    rng = np.random.default_rng(SERVE_SEED)
+    mechs, pools = {}, {}
+    for spec in (I.MECH_9, I.MECH_53, I.MECH_200):
+        mech = I.make_mechanism(spec)
+        name = mech["name"]
+        mechs[name] = kx.Mechanism(mech, 0)
+        sizes = np.rint(10.0 ** rng.uniform(3.0, 6.0, args.serve_pool)).astype(int)
+        pools[name] = SL.make_pool(mechs[name], mech["n_species"], sizes,
+                                   SERVE_SEED * 1000 + spec.n_species)
+    srv = kx.Server(0, hbm_budget=args.serve_budget_gb << 30, max_slots=args.serve_slots)
+    try:
+        nw, nm = args.serve_warmup, args.serve_requests
+        # warm every (mechanism, precision, ops) graph on every stream
+        SL.run_stream(srv, mechs, pools, SL.make_stream(4 * nw, pools, SERVE_SEED + 1), None, 0)
+        cap_stream = SL.make_stream(nm, pools, SERVE_SEED + 2)
+        rec = SL.run_stream(srv, mechs, pools, cap_stream, None, 0)
+        cap = SL.summarize(rec)
+        capacity = cap["achieved_rps"]
+        log(f"serve capacity {capacity:.1f} req/s, {cap['achieved_Mpoints_s']:.1f} Mpoints/s")
+        seq_s = SL.direct_sequential(mechs, pools, cap_stream)
+        levels = []
+        for k, frac in enumerate(SERVE_LOADS):
+            qps = frac * capacity
+            stream = SL.make_stream(nw + nm, pools, SERVE_SEED + 10 + k)
+            rec = SL.run_stream(srv, mechs, pools, stream, qps, SERVE_SEED + 20 + k)
+            s = SL.summarize(rec, skip=nw)
+            s.update({"load": frac, "offered_rps": qps})
+            log(f"serve load {frac:.2f}: p50 {s['p50_ms']:.2f} ms p99 {s['p99_ms']:.2f} ms "
+                f"{s['achieved_rps']:.1f} req/s")
+            levels.append(s)
+        st = srv.stats()
+    finally:
+        srv.close()
+        for m in mechs.values():
+            m.close()
+    return {"workload": "Poisson arrivals; mechanism uniform over syn9/syn53/syn200, "
+                        "n = round(10^U(3,6)), rates-only vs rates+transport 50/50, "
+                        "fp64 vs mixed 50/50; inputs device-resident; latency from "
+                        "scheduled arrival to outputs ready on the device",
+            "seed": SERVE_SEED, "input_sets_per_mechanism": args.serve_pool,
+            "warmup_requests": nw, "measured_requests": nm,
+            "hbm_budget_bytes": args.serve_budget_gb << 30, "max_slots": args.serve_slots,
+            "capacity_rps": capacity, "capacity_Mpoints_s": cap["achieved_Mpoints_s"],
+            "direct_sequential_rps": nm / seq_s,
+            "direct_sequential_Mpoints_s": sum(pools[nm_][i][0] for nm_, i, _, _ in cap_stream)
+                                           / seq_s / 1e6,
+            "levels": levels, "batches": st["batches"], "graph_launches": st["graph_launches"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,10 +144,16 @@ def main():
     ap.add_argument("--points", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-warmup", type=int, default=40)
+    ap.add_argument("--serve-pool", type=int, default=24)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-budget-gb", type=int, default=48)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(points shard trivially across GPUs; see the design notes)", file=sys.stderr)
+              "(points shard trivially across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -142,6 +209,11 @@ def main():
                                 "frac": ofl * n / (oms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS,
                                 "ms": oms}
 
+    served = None
+    if not args.no_serve:
+        log("serving")
+        served = serve_bench(kx, args)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -161,7 +233,7 @@ def main():
         "grxn_per_s": value * 1e6 * nr / 1e9,
         "gdof_per_s": value * 1e6 * (ns + 2) / 1e9,
         "rates_kernel_ms": r_ms, "transport_kernel_ms": t_ms,
-        "roofline": roofline, "cpu_baseline": cpu, "mixed": mixed,
+        "roofline": roofline, "cpu_baseline": cpu, "mixed": mixed, "served": served,
     }
     print(json.dumps(line), flush=True)
     dm.close()

@@ -120,11 +120,17 @@ typedef struct kx_mech kx_mech; /* opaque device-resident mechanism */
  * sizes, out-of-range species indices, non-positive W_k or A, a species listed
  * twice on one side of a reaction, unbalanced element counts, an unknown
  * reaction type, a non-symmetric diff_fit, fit_order outside 1..8 and
- * fit_h == 0.  KX_EUNSUPPORTED: more than 4 distinct species on one side of a
- * reaction or more than 65535 species.  On success *out owns the tables until
+ * fit_h == 0.  KX_EUNSUPPORTED: more than 3 molecules (sum of nu) on one side
+ * of a reaction, or more than 256 species.  On success *out owns the tables until
  * kx_mech_destroy.  Allocates device memory (hipMalloc); blocks until the
  * upload is complete. */
 kx_status kx_mech_create(const kx_mech_desc *desc, int device, kx_mech **out);
+
+/* Validate `desc` and build the tables exactly as kx_mech_create does, without
+ * a device: the handle reports kx_mech_info and can be used with a server
+ * created with KX_SERVER_SIMULATE, but every compute call rejects it
+ * (KX_EINVAL).  For checking descriptors and serving logic on a host. */
+kx_status kx_mech_create_host(const kx_mech_desc *desc, kx_mech **out);
 
 /* Free the device tables.  The caller must have synchronised every stream on
  * which work using `mech` was enqueued.  NULL is a no-op. */
@@ -171,6 +177,102 @@ kx_status kx_transport_ex(const kx_mech *mech, int64_t n, const double *T, const
  * outputs may be NULL.  Plain FP64. */
 kx_status kx_thermo(const kx_mech *mech, int64_t n, const double *T, const double *Y,
                     double *cp_k, double *h_k, double *cp_mix, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: a continuous-batching request server (project addition; the paper
+ * notes that GPUs reach their throughput only with >~1e5 points, so small
+ * requests are batched).  A server owns an HBM arena of `hbm_budget` bytes for
+ * request outputs; a scheduler thread admits queued requests in arrival order
+ * whenever a slot and arena space are free, groups admitted requests by
+ * (mechanism, precision) into batches of up to 64, and runs each batch as
+ * work-stealing kernels over a device work list, replayed from a HIP graph,
+ * on one of several streams -- batches of different groups overlap on the
+ * device.  Every request is cut into the same tiles as a direct call, so its
+ * outputs are bit-identical alone and in a batch.
+ * ------------------------------------------------------------------------ */
+typedef struct kx_server kx_server;
+typedef int64_t kx_ticket;
+
+enum { KX_OP_RATES = 1, KX_OP_TRANSPORT = 2 };          /* request ops (bit set) */
+enum { KX_SERVER_SIMULATE = 1 };                         /* kx_server_create flags */
+enum {                                                   /* kx_result.state */
+    KX_REQ_QUEUED = 0, KX_REQ_ADMITTED = 1, KX_REQ_RUNNING = 2,
+    KX_REQ_DONE = 3, KX_REQ_CANCELLED = 4, KX_REQ_FAILED = 5
+};
+
+typedef struct {
+    const kx_mech *mech;      /* created on the server's device; must outlive the request */
+    int32_t ops;              /* KX_OP_RATES, optionally | KX_OP_TRANSPORT */
+    int32_t precision;        /* KX_FP64 or KX_MIXED */
+    int64_t n;                /* points */
+    const double *T, *p, *Y;  /* DEVICE inputs (layout as kx_production_rates); they
+                                 must stay valid and unchanged until the request is
+                                 DONE, CANCELLED or FAILED */
+    double arrival_s;         /* arrival time on kx_server_clock() for latency
+                                 accounting; < 0 means "now" */
+} kx_request;
+
+typedef struct {
+    int32_t state;                      /* KX_REQ_* */
+    int32_t pad;
+    double *wdot, *mu, *lambda, *Dmix;  /* server-owned DEVICE outputs, valid from DONE
+                                           until kx_release (NULL where not requested) */
+    double t_arrival, t_admit, t_launch, t_done;  /* kx_server_clock() seconds */
+} kx_result;
+
+typedef struct {
+    int64_t submitted, completed, cancelled, failed;
+    int64_t queued, in_flight;          /* now */
+    int64_t batches, graph_launches;
+    int64_t arena_in_use, arena_capacity;
+} kx_server_stats;
+
+/* Monotonic clock (seconds) used for all server time stamps. */
+double kx_server_clock(void);
+
+/* Create a server on `device` with an output arena of `hbm_budget` bytes and
+ * at most `max_slots` requests admitted at once.  KX_SERVER_SIMULATE runs the
+ * scheduler without a GPU (no memory, no kernels; a batch "completes" after
+ * 5 ns per point), for testing admission and queueing logic on a host.
+ * Allocates device memory, streams and pinned host buffers. */
+kx_status kx_server_create(int device, int64_t hbm_budget, int32_t max_slots, int32_t flags,
+                           kx_server **out);
+
+/* Stop the scheduler: queued and admitted requests are cancelled, batches
+ * already on the device are waited for, then every resource is freed.
+ * Pointers from kx_result become invalid. */
+kx_status kx_server_destroy(kx_server *srv);
+
+/* Queue a request.  KX_EINVAL for a bad request; KX_ENOMEM if its output
+ * footprint n * 8 * (Ns [wdot] + (Ns + 2) [transport]) exceeds the whole
+ * budget.  n == 0 completes immediately. */
+kx_status kx_submit(kx_server *srv, const kx_request *req, kx_ticket *ticket);
+
+/* Current state and outputs of a request (non-blocking). */
+kx_status kx_poll(kx_server *srv, kx_ticket ticket, kx_result *res);
+
+/* Block until the request is DONE, CANCELLED or FAILED, or `timeout_s`
+ * seconds pass (KX_EAGAIN; timeout_s < 0 waits forever). */
+kx_status kx_wait(kx_server *srv, kx_ticket ticket, double timeout_s, kx_result *res);
+
+/* Cancel a request that has not been launched (QUEUED or ADMITTED); KX_EAGAIN
+ * if it is already running or finished. */
+kx_status kx_cancel(kx_server *srv, kx_ticket ticket);
+
+/* Enqueue copies of a DONE request's outputs into caller device buffers (any
+ * may be NULL) on `stream`.  The copies must have completed before the ticket
+ * is released (its arena space is reused at once), and a ticket must not be
+ * copied and released from two threads at the same time. */
+kx_status kx_result_copy(kx_server *srv, kx_ticket ticket, double *wdot, double *mu,
+                         double *lambda, double *Dmix, hipStream_t stream);
+
+/* Forget a finished request and return its arena space; KX_EAGAIN if it is
+ * still queued or running.  A DONE request keeps its outputs (and arena
+ * space) until released, so a client that holds finished requests while it
+ * waits for queued ones can stall admission once the arena is full. */
+kx_status kx_release(kx_server *srv, kx_ticket ticket);
+
+kx_status kx_server_stats_get(kx_server *srv, kx_server_stats *stats);
 
 /* Human-readable description of the calling thread's most recent failure
  * ("" if none).  The pointer stays valid until the thread's next kx_* call. */

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libkx.so")
-SOURCES = ["kx_api.cpp", "kx_mech.cpp", "kx_rates.hip", "kx_transport.hip"]
+SOURCES = ["kx_api.cpp", "kx_mech.cpp", "kx_serve.cpp", "kx_rates.hip", "kx_transport.hip"]
 ARCH = "gfx950"
 
 
@@ -52,7 +52,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp] + objs
+    cmd = [cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

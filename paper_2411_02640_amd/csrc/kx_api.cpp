@@ -27,7 +27,7 @@ kx_status hip_fail(hipError_t e, const char *what)
     return fail(KX_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out);
+kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech **out);
 
 namespace {
 
@@ -50,6 +50,7 @@ struct DeviceGuard {
 kx_status check_common(const kx_mech *m, int64_t n, const char *who)
 {
     if (!m) return fail(KX_EINVAL, std::string(who) + ": mech is NULL");
+    if (!m->blob) return fail(KX_EINVAL, std::string(who) + ": mechanism has no device tables");
     if (n < 0) return fail(KX_EINVAL, std::string(who) + ": n < 0");
     return KX_OK;
 }
@@ -63,12 +64,21 @@ extern "C" {
 
 kx_status kx_mech_create(const kx_mech_desc *desc, int device, kx_mech **out)
 {
-    return build_mech(desc, device, out);
+    return build_mech(desc, device, false, out);
+}
+
+kx_status kx_mech_create_host(const kx_mech_desc *desc, kx_mech **out)
+{
+    return build_mech(desc, -1, true, out);
 }
 
 kx_status kx_mech_destroy(kx_mech *mech)
 {
     if (!mech) return ok();
+    if (!mech->blob) {
+        delete mech;
+        return ok();
+    }
     DeviceGuard g(mech->device);
     hipError_t e = hipFree(mech->blob);
     delete mech;

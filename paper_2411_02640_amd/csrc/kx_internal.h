@@ -114,6 +114,23 @@ struct MechDev {
     const float *visc32, *cond32, *wq32, *wilke32, *dfit32, *ddiag32;
 };
 
+// Work list of one batch of served requests (device memory, written by the
+// host before the batch launches).  start[op][r] is the first tile of item r
+// for op 0 (rates) and op 1 (transport); start[op][nitems] = ntiles[op].
+constexpr int kMaxBatch = 64;
+struct WorkItem {
+    const double *T, *p, *Y;
+    double *wdot, *mu, *lam, *Dmix;
+    int64_t n;
+};
+struct WorkList {
+    int32_t nitems;
+    int32_t ntiles[2];
+    int32_t pad;
+    int32_t start[2][kMaxBatch + 1];
+    WorkItem items[kMaxBatch];
+};
+
 }  // namespace kx
 
 struct kx_mech {
@@ -122,6 +139,7 @@ struct kx_mech {
     void *blob;          // single device allocation holding every table
     int64_t bytes;
     int32_t n_species, n_reactions;
+    uint64_t uid;        // never reused within a process (keys cached launch graphs)
 };
 
 namespace kx {
@@ -138,4 +156,19 @@ kx_status launch_transport(const kx_mech *m, int64_t n, const double *T, const d
                            int precision, hipStream_t s);
 kx_status launch_thermo(const kx_mech *m, int64_t n, const double *T, const double *Y,
                         double *cpk, double *hk, double *cpmix, hipStream_t s);
+
+// Points per tile of the two kernels for a mechanism and precision (the
+// serving work lists are cut in the same tiles as a direct call, so a request
+// gives bit-identical results alone and in a batch).
+int rates_tile_points(const MechDev &m);
+int transport_tile_points(int precision);
+// Batched (work-list) launches; `counter` must be zero at launch.
+// prepare_rates_batch sets the kernel's dynamic-LDS limit (call it before
+// capturing a launch into a graph).
+kx_status prepare_rates_batch(const MechDev &m, int precision);
+kx_status launch_rates_batch(const MechDev &m, const WorkList *wl, int *counter, int precision,
+                             int grid, hipStream_t s);
+kx_status launch_transport_batch(const MechDev &m, const WorkList *wl, int *counter,
+                                 int precision, int grid, hipStream_t s);
+kx_status launch_zero(int *p, int count, hipStream_t s);
 }  // namespace kx

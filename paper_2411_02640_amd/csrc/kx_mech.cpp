@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -141,7 +142,11 @@ kx_status validate(const kx_mech_desc *d, std::vector<double> &W)
 
 }  // namespace
 
-kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
+namespace {
+std::atomic<uint64_t> next_uid{0};
+}  // namespace
+
+kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech **out)
 {
     if (!out) return fail(KX_EINVAL, "kx_mech_create: out is NULL");
     *out = nullptr;
@@ -331,34 +336,40 @@ kx_status build_mech(const kx_mech_desc *d, int device, kx_mech **out)
     const size_t o_wil32 = add_vec(b, to32(wilke)), o_df32 = add_vec(b, to32(dfit));
     const size_t o_dd32 = add_vec(b, to32(ddiag));
 
-    int prev = 0;
-    hipError_t e = hipGetDevice(&prev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    e = hipSetDevice(device);
-    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     void *blob = nullptr;
-    e = hipMalloc(&blob, b.host.size());
-    if (e != hipSuccess) {
+    if (!host_only) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        e = hipSetDevice(device);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+        e = hipMalloc(&blob, b.host.size());
+        if (e != hipSuccess) {
+            hipSetDevice(prev);
+            return fail(KX_ENOMEM, "kx_mech_create: hipMalloc of " +
+                                       std::to_string(b.host.size()) + " bytes failed");
+        }
+        e = hipMemcpy(blob, b.host.data(), b.host.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hipFree(blob);
+            hipSetDevice(prev);
+            return hip_fail(e, "hipMemcpy (mechanism upload)");
+        }
         hipSetDevice(prev);
-        return fail(KX_ENOMEM, "kx_mech_create: hipMalloc of " +
-                                   std::to_string(b.host.size()) + " bytes failed");
     }
-    e = hipMemcpy(blob, b.host.data(), b.host.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        hipFree(blob);
-        hipSetDevice(prev);
-        return hip_fail(e, "hipMemcpy (mechanism upload)");
-    }
-    hipSetDevice(prev);
 
     kx_mech *m = new kx_mech;
-    m->device = device;
+    m->device = host_only ? -1 : device;
     m->blob = blob;
     m->bytes = (int64_t)b.host.size();
     m->n_species = ns;
+    m->uid = next_uid.fetch_add(1) + 1;
     m->n_reactions = nr;
     MechDev &v = m->dev;
-    auto at = [&](size_t off) { return (const void *)((const uint8_t *)blob + off); };
+    // device addresses of the tables (null for a host-only handle)
+    auto at = [&](size_t off) {
+        return blob ? (const void *)((const uint8_t *)blob + off) : (const void *)nullptr;
+    };
     v.ns = ns;
     v.nr = nr;
     v.chunk = chunk;

@@ -199,12 +199,14 @@ __device__ __forceinline__ double rate_of_progress(const MechDev &m, const RxnWo
 //   sq    [chunk + 1]       (rates of progress of the current chunk; the last
 //                            element is the zero the gather padding reads)
 //   Yt    [ns][tp + 1]      (Y tile in, wdot tile out)
+// One tile of `npts` (<= tp) points starting at point i0 of arrays whose
+// species rows have stride ld.  Called by the whole (one-wave) workgroup.
 template <bool MIXED, int SPL>
-__global__ __launch_bounds__(kWave) void rates_kernel(MechDev m, int64_t n,
-                                                      const double *__restrict__ T,
-                                                      const double *__restrict__ P,
-                                                      const double *__restrict__ Y,
-                                                      double *__restrict__ wdot, int tp)
+__device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t i0, int npts,
+                                           int tp, const double *__restrict__ T,
+                                           const double *__restrict__ P,
+                                           const double *__restrict__ Y,
+                                           double *__restrict__ wdot)
 {
     extern __shared__ double lds[];
     const int ns = m.ns;
@@ -216,11 +218,9 @@ __global__ __launch_bounds__(kWave) void rates_kernel(MechDev m, int64_t n,
     const char *pb = reinterpret_cast<const char *>(pairs);
     const char *qb = reinterpret_cast<const char *>(sq);
 
-    const int64_t i0 = (int64_t)blockIdx.x * tp;
-    const int npts = (int)min((int64_t)tp, n - i0);
     for (int e = lane; e < ns * tp; e += kWave) {
         const int k = e / tp, c = e - k * tp;
-        Yt[k * ys + c] = (c < npts) ? Y[(int64_t)k * n + i0 + c] : 0.0;
+        Yt[k * ys + c] = (c < npts) ? Y[(int64_t)k * ld + i0 + c] : 0.0;
     }
     if (lane == 0) {
         pairs[2 * ns] = 1.0;
@@ -330,7 +330,42 @@ __global__ __launch_bounds__(kWave) void rates_kernel(MechDev m, int64_t n,
     __syncthreads();
     for (int e = lane; e < ns * tp; e += kWave) {
         const int k = e / tp, c = e - k * tp;
-        if (c < npts) wdot[(int64_t)k * n + i0 + c] = Yt[k * ys + c];
+        if (c < npts) wdot[(int64_t)k * ld + i0 + c] = Yt[k * ys + c];
+    }
+    __syncthreads();  // the LDS tile may be reused by the next tile
+}
+
+template <bool MIXED, int SPL>
+__global__ __launch_bounds__(kWave) void rates_kernel(MechDev m, int64_t n,
+                                                      const double *__restrict__ T,
+                                                      const double *__restrict__ P,
+                                                      const double *__restrict__ Y,
+                                                      double *__restrict__ wdot, int tp)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * tp;
+    rates_tile<MIXED, SPL>(m, n, i0, (int)min((int64_t)tp, n - i0), tp, T, P, Y, wdot);
+}
+
+// Batched requests: workgroups take tiles from a shared counter until the
+// batch's tiles are exhausted (every workgroup exits once the counter passes
+// the tile count).  Tile t belongs to the last item whose first tile is <= t.
+template <bool MIXED, int SPL>
+__global__ __launch_bounds__(kWave) void rates_batch_kernel(MechDev m,
+                                                            const WorkList *__restrict__ wl,
+                                                            int *__restrict__ counter, int tp)
+{
+    const int ntiles = wl->ntiles[0];
+    for (;;) {
+        int t = 0;
+        if (threadIdx.x == 0) t = atomicAdd(counter, 1);
+        t = __shfl(t, 0, kWave);
+        if (t >= ntiles) break;
+        int r = 0;
+        while (r + 1 < wl->nitems && wl->start[0][r + 1] <= t) ++r;
+        const WorkItem it = wl->items[r];
+        const int64_t i0 = (int64_t)(t - wl->start[0][r]) * tp;
+        rates_tile<MIXED, SPL>(m, it.n, i0, (int)min((int64_t)tp, it.n - i0), tp, it.T, it.p,
+                               it.Y, it.wdot);
     }
 }
 
@@ -341,38 +376,84 @@ size_t rates_lds_bytes(const MechDev &m, int tp)
 
 }  // namespace
 
+// Largest tile (16, 8 or 4 points per wave) whose LDS leaves room for at least
+// eight waves per CU (160 KB of LDS).
+int rates_tile_points(const MechDev &m)
+{
+    for (int cand : {16, 8, 4})
+        if (rates_lds_bytes(m, cand) <= 20 * 1024) return cand;
+    return 4;
+}
+
+namespace {
+template <class K>
+kx_status set_lds(K kern, size_t lds)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute (rates)");
+    return KX_OK;
+}
+
+// species per lane of the species and gather phases
+int rates_spl(const MechDev &m) { return m.gpass <= 1 ? 1 : (m.gpass <= 2 ? 2 : 4); }
+}  // namespace
+
 kx_status launch_rates(const kx_mech *mech, int64_t n, const double *T, const double *p,
                        const double *Y, double *wdot, int precision, hipStream_t s)
 {
     const MechDev &m = mech->dev;
-    // Largest tile (16, 8 or 4 points per wave) whose LDS leaves room for
-    // at least eight waves per CU (160 KB of LDS).
-    int tp = 4;
-    for (int cand : {16, 8, 4}) {
-        if (rates_lds_bytes(m, cand) <= 20 * 1024) {
-            tp = cand;
-            break;
-        }
-    }
+    const int tp = rates_tile_points(m);
     const size_t lds = rates_lds_bytes(m, tp);
     if (lds > 160 * 1024)
         return fail(KX_EUNSUPPORTED, "production rates: mechanism too large for LDS");
     const int64_t nblk = (n + tp - 1) / tp;
     if (nblk > 0x7fffffff) return fail(KX_EINVAL, "production rates: n too large");
-    // species per lane: the gather and species phases hold SPL values per lane
-    const int spl = m.gpass <= 1 ? 1 : (m.gpass <= 2 ? 2 : 4);
+    const int spl = rates_spl(m);
     auto pick = [&](auto mixed) {
         constexpr bool M = decltype(mixed)::value;
         return spl == 1 ? rates_kernel<M, 1> : (spl == 2 ? rates_kernel<M, 2> : rates_kernel<M, 4>);
     };
     auto kern = precision == KX_MIXED ? pick(std::true_type{}) : pick(std::false_type{});
-    hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute (rates)");
+    kx_status st = set_lds(kern, lds);
+    if (st != KX_OK) return st;
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(kWave), lds, s, m, n, T, p, Y, wdot,
                        tp);
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "rates kernel launch");
+    return ok();
+}
+
+namespace {
+auto pick_batch(const MechDev &m, int precision)
+{
+    const int spl = rates_spl(m);
+    auto pick = [&](auto mixed) {
+        constexpr bool M = decltype(mixed)::value;
+        return spl == 1 ? rates_batch_kernel<M, 1>
+                        : (spl == 2 ? rates_batch_kernel<M, 2> : rates_batch_kernel<M, 4>);
+    };
+    return precision == KX_MIXED ? pick(std::true_type{}) : pick(std::false_type{});
+}
+}  // namespace
+
+kx_status prepare_rates_batch(const MechDev &m, int precision)
+{
+    const size_t lds = rates_lds_bytes(m, rates_tile_points(m));
+    if (lds > 160 * 1024)
+        return fail(KX_EUNSUPPORTED, "production rates: mechanism too large for LDS");
+    return set_lds(pick_batch(m, precision), lds);
+}
+
+kx_status launch_rates_batch(const MechDev &m, const WorkList *wl, int *counter, int precision,
+                             int grid, hipStream_t s)
+{
+    const int tp = rates_tile_points(m);
+    const size_t lds = rates_lds_bytes(m, tp);
+    hipLaunchKernelGGL(pick_batch(m, precision), dim3(grid), dim3(kWave), lds, s, m, wl,
+                       counter, tp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "rates batch kernel launch");
     return ok();
 }
 

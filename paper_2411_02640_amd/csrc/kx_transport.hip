@@ -86,14 +86,16 @@ template <> struct Tabs<float> {
     static __device__ const float *ddiag(const MechDev &m) { return m.ddiag32; }
 };
 
+// One tile of kBlock * P points starting at point `base` of arrays with n
+// points (species rows of stride n).
 template <class F, int ORDER, int KIND, int P, int KB>
-__global__ __launch_bounds__(kBlock) void transport_kernel(MechDev m, int64_t n,
-                                                           const double *__restrict__ T,
-                                                           const double *__restrict__ Pp,
-                                                           const double *__restrict__ Y,
-                                                           double *__restrict__ mu,
-                                                           double *__restrict__ lam,
-                                                           double *__restrict__ Dmix)
+__device__ __forceinline__ void transport_tile(const MechDev &m, int64_t n, int64_t base,
+                                               const double *__restrict__ T,
+                                               const double *__restrict__ Pp,
+                                               const double *__restrict__ Y,
+                                               double *__restrict__ mu,
+                                               double *__restrict__ lam,
+                                               double *__restrict__ Dmix)
 {
     using Tb = Tabs<F>;
     const int ns = m.ns, order = m.fit_order;
@@ -104,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(MechDev m, int64_t n,
     double pr[P], xf[P], wbar[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-        const int64_t ir = (int64_t)blockIdx.x * kBlock * P + threadIdx.x + (int64_t)kBlock * q;
+        const int64_t ir = base + threadIdx.x + (int64_t)kBlock * q;
         act[q] = ir < n;
         idx[q] = act[q] ? ir : n - 1;
         const double Ti = T[idx[q]];
@@ -237,6 +239,48 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(MechDev m, int64_t n,
         if (act[q]) mu[idx[q]] = (double)visc[q];
 }
 
+template <class F, int ORDER, int KIND, int P, int KB>
+__global__ __launch_bounds__(kBlock) void transport_kernel(MechDev m, int64_t n,
+                                                           const double *__restrict__ T,
+                                                           const double *__restrict__ Pp,
+                                                           const double *__restrict__ Y,
+                                                           double *__restrict__ mu,
+                                                           double *__restrict__ lam,
+                                                           double *__restrict__ Dmix)
+{
+    transport_tile<F, ORDER, KIND, P, KB>(m, n, (int64_t)blockIdx.x * kBlock * P, T, Pp, Y, mu,
+                                          lam, Dmix);
+}
+
+// Batched requests (see rates_batch_kernel): tiles of kBlock * P points.
+template <class F, int ORDER, int KIND, int P, int KB>
+__global__ __launch_bounds__(kBlock) void transport_batch_kernel(MechDev m,
+                                                                 const WorkList *__restrict__ wl,
+                                                                 int *__restrict__ counter)
+{
+    __shared__ int tile;
+    const int ntiles = wl->ntiles[1];
+    for (;;) {
+        if (threadIdx.x == 0) tile = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = tile;
+        __syncthreads();
+        if (t >= ntiles) break;
+        int r = 0;
+        while (r + 1 < wl->nitems && wl->start[1][r + 1] <= t) ++r;
+        const WorkItem it = wl->items[r];
+        transport_tile<F, ORDER, KIND, P, KB>(m, it.n,
+                                              (int64_t)(t - wl->start[1][r]) * kBlock * P, it.T,
+                                              it.p, it.Y, it.mu, it.lam, it.Dmix);
+    }
+}
+
+__global__ void zero_kernel(int *p, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
 // Mixture thermo (App. A.1): cp_k = Cp_k/W_k, h_k = H_k/W_k, cp = sum Y_k cp_k.
 __global__ __launch_bounds__(kBlock) void thermo_kernel(MechDev m, int64_t n,
                                                         const double *__restrict__ T,
@@ -268,36 +312,84 @@ __global__ __launch_bounds__(kBlock) void thermo_kernel(MechDev m, int64_t n,
     if (cpmix) cpmix[i] = cp;
 }
 
+// Points per lane and k-block size, measured on the 53-species workload:
+// FP64 is bound by the scalar-coefficient stream, so four points share each
+// fetched coefficient; the FP32 path carries half the registers per value and
+// prefers wider k-blocks.
+template <class F> struct TransportShape;
+template <> struct TransportShape<double> {
+    static constexpr int P = 4, KB = 4;
+};
+template <> struct TransportShape<float> {
+    static constexpr int P = 2, KB = 8;
+};
+
+}  // namespace
+
+int transport_tile_points(int precision)
+{
+    return kBlock * (precision == KX_MIXED ? TransportShape<float>::P : TransportShape<double>::P);
+}
+
+namespace {
+template <class F>
+kx_status go_transport(const MechDev &m, int64_t n, const double *T, const double *p,
+                       const double *Y, double *mu, double *lam, double *Dmix, hipStream_t s)
+{
+    constexpr int PP = TransportShape<F>::P, KB = TransportShape<F>::KB;
+    const int64_t per = (int64_t)kBlock * PP;
+    const int64_t nblk = (n + per - 1) / per;
+    if (nblk > 0x7fffffff) return fail(KX_EINVAL, "transport: n too large");
+    const bool o5 = m.fit_order == 5;
+    auto k = m.diff_kind == 0
+                 ? (o5 ? transport_kernel<F, 5, 0, PP, KB> : transport_kernel<F, 0, 0, PP, KB>)
+                 : (o5 ? transport_kernel<F, 5, 1, PP, KB> : transport_kernel<F, 0, 1, PP, KB>);
+    hipLaunchKernelGGL(k, dim3((unsigned)nblk), dim3(kBlock), 0, s, m, n, T, p, Y, mu, lam,
+                       Dmix);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "transport kernel launch");
+    return ok();
+}
+
+template <class F>
+kx_status go_transport_batch(const MechDev &m, const WorkList *wl, int *counter, int grid,
+                             hipStream_t s)
+{
+    constexpr int PP = TransportShape<F>::P, KB = TransportShape<F>::KB;
+    const bool o5 = m.fit_order == 5;
+    auto k = m.diff_kind == 0 ? (o5 ? transport_batch_kernel<F, 5, 0, PP, KB>
+                                    : transport_batch_kernel<F, 0, 0, PP, KB>)
+                              : (o5 ? transport_batch_kernel<F, 5, 1, PP, KB>
+                                    : transport_batch_kernel<F, 0, 1, PP, KB>);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), 0, s, m, wl, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "transport batch kernel launch");
+    return ok();
+}
 }  // namespace
 
 kx_status launch_transport(const kx_mech *mech, int64_t n, const double *T, const double *p,
                            const double *Y, double *mu, double *lam, double *Dmix,
                            int precision, hipStream_t s)
 {
-    const MechDev &m = mech->dev;
-    auto go = [&](auto fz, auto pz, auto kbz) -> kx_status {
-        using F = decltype(fz);
-        constexpr int PP = decltype(pz)::value, KB = decltype(kbz)::value;
-        const int64_t per = (int64_t)kBlock * PP;
-        const int64_t nblk = (n + per - 1) / per;
-        if (nblk > 0x7fffffff) return fail(KX_EINVAL, "transport: n too large");
-        const bool o5 = m.fit_order == 5;
-        auto k = m.diff_kind == 0
-                     ? (o5 ? transport_kernel<F, 5, 0, PP, KB> : transport_kernel<F, 0, 0, PP, KB>)
-                     : (o5 ? transport_kernel<F, 5, 1, PP, KB> : transport_kernel<F, 0, 1, PP, KB>);
-        hipLaunchKernelGGL(k, dim3((unsigned)nblk), dim3(kBlock), 0, s, m, n, T, p, Y, mu, lam,
-                           Dmix);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "transport kernel launch");
-        return ok();
-    };
-    // Points per lane and k-block size, measured on the 53-species workload:
-    // FP64 is bound by the scalar-coefficient stream, so four points share
-    // each fetched coefficient; the FP32 path carries half the registers per
-    // value and prefers wider k-blocks.
     if (precision == KX_MIXED)
-        return go(0.0f, std::integral_constant<int, 2>{}, std::integral_constant<int, 8>{});
-    return go(0.0, std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{});
+        return go_transport<float>(mech->dev, n, T, p, Y, mu, lam, Dmix, s);
+    return go_transport<double>(mech->dev, n, T, p, Y, mu, lam, Dmix, s);
+}
+
+kx_status launch_transport_batch(const MechDev &m, const WorkList *wl, int *counter,
+                                 int precision, int grid, hipStream_t s)
+{
+    if (precision == KX_MIXED) return go_transport_batch<float>(m, wl, counter, grid, s);
+    return go_transport_batch<double>(m, wl, counter, grid, s);
+}
+
+kx_status launch_zero(int *p, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_kernel, dim3((count + 63) / 64), dim3(64), 0, s, p, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "zero kernel launch");
+    return ok();
 }
 
 kx_status launch_thermo(const kx_mech *mech, int64_t n, const double *T, const double *Y,

@@ -207,3 +207,170 @@ def thermo(mech: Mechanism, T, Y, stream=None):
                           C.c_void_p(hk.data_ptr()), C.c_void_p(cp.data_ptr()),
                           _stream_ptr(stream, dev)))
     return cpk, hk, cp
+
+
+# --------------------------------------------------------------------------
+# host-only mechanisms and the request server
+# --------------------------------------------------------------------------
+KX_OP_RATES, KX_OP_TRANSPORT = 1, 2
+KX_SERVER_SIMULATE = 1
+REQ_STATES = {0: "queued", 1: "admitted", 2: "running", 3: "done", 4: "cancelled", 5: "failed"}
+
+
+class _Request(C.Structure):
+    _fields_ = [("mech", C.c_void_p), ("ops", C.c_int32), ("precision", C.c_int32),
+                ("n", C.c_int64), ("T", C.c_void_p), ("p", C.c_void_p), ("Y", C.c_void_p),
+                ("arrival_s", C.c_double)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("state", C.c_int32), ("pad", C.c_int32), ("wdot", C.c_void_p),
+                ("mu", C.c_void_p), ("lam", C.c_void_p), ("Dmix", C.c_void_p),
+                ("t_arrival", C.c_double), ("t_admit", C.c_double), ("t_launch", C.c_double),
+                ("t_done", C.c_double)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("submitted", "completed", "cancelled", "failed",
+                                         "queued", "in_flight", "batches", "graph_launches",
+                                         "arena_in_use", "arena_capacity")]
+
+
+def _serve_lib():
+    L = lib()
+    if not getattr(L, "_serve_ready", False):
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        L.kx_mech_create_host.argtypes = [C.POINTER(_Desc), C.POINTER(vp)]
+        L.kx_server_clock.restype = C.c_double
+        L.kx_server_create.argtypes = [C.c_int, i64, i32, i32, C.POINTER(vp)]
+        L.kx_server_destroy.argtypes = [vp]
+        L.kx_submit.argtypes = [vp, C.POINTER(_Request), C.POINTER(i64)]
+        L.kx_poll.argtypes = [vp, i64, C.POINTER(_Result)]
+        L.kx_wait.argtypes = [vp, i64, C.c_double, C.POINTER(_Result)]
+        L.kx_cancel.argtypes = [vp, i64]
+        L.kx_result_copy.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        L.kx_release.argtypes = [vp, i64]
+        L.kx_server_stats_get.argtypes = [vp, C.POINTER(_Stats)]
+        for name in ("kx_mech_create_host", "kx_server_create", "kx_server_destroy",
+                     "kx_submit", "kx_poll", "kx_wait", "kx_cancel", "kx_result_copy",
+                     "kx_release", "kx_server_stats_get"):
+            getattr(L, name).restype = C.c_int32
+        L._serve_ready = True
+    return L
+
+
+class HostMechanism(Mechanism):
+    """Mechanism tables built without a device (kx_mech_create_host)."""
+
+    def __init__(self, mech: dict):  # noqa: D401 - mirrors Mechanism
+        L = _serve_lib()
+        d, keep = make_desc(mech)
+        h = C.c_void_p()
+        check(L.kx_mech_create_host(C.byref(d), C.byref(h)))
+        del keep
+        self.handle = h
+        self.device = -1
+        ns, nr, nb = C.c_int32(), C.c_int32(), C.c_int64()
+        check(L.kx_mech_info(h, C.byref(ns), C.byref(nr), C.byref(nb)))
+        self.n_species, self.n_reactions, self.device_bytes = ns.value, nr.value, nb.value
+        self.name = mech.get("name", "")
+
+
+def clock() -> float:
+    """The server's monotonic clock (seconds)."""
+    return _serve_lib().kx_server_clock()
+
+
+def _result_dict(r: _Result) -> dict:
+    return {"state": REQ_STATES.get(r.state, r.state), "t_arrival": r.t_arrival,
+            "t_admit": r.t_admit, "t_launch": r.t_launch, "t_done": r.t_done,
+            "wdot": r.wdot, "mu": r.mu, "lambda": r.lam, "Dmix": r.Dmix}
+
+
+class Server:
+    """Continuous-batching request server (kx_server_*)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 8 << 30, max_slots: int = 64,
+                 simulate: bool = False):
+        L = _serve_lib()
+        h = C.c_void_p()
+        flags = KX_SERVER_SIMULATE if simulate else 0
+        check(L.kx_server_create(int(device), int(hbm_budget), int(max_slots), flags,
+                                 C.byref(h)))
+        self.handle = h
+        self.device = device
+        self.simulate = simulate
+        self._inputs = {}   # ticket -> (mech, tensors) kept alive until release
+        self._meta = {}
+
+    def submit(self, mech: Mechanism, T=None, p=None, Y=None, n: int | None = None,
+               transport: bool = False, precision: str = "fp64",
+               arrival: float | None = None) -> int:
+        L = _serve_lib()
+        r = _Request()
+        r.mech = mech.handle.value
+        r.ops = KX_OP_RATES | (KX_OP_TRANSPORT if transport else 0)
+        r.precision = PRECISION[precision]
+        if T is not None:
+            n = T.shape[0]
+            r.T = _dev_tensor(T, self.device, (n,), "T").value
+            r.p = _dev_tensor(p, self.device, (n,), "p").value
+            r.Y = _dev_tensor(Y, self.device, (mech.n_species, n), "Y").value
+        r.n = int(n)
+        r.arrival_s = -1.0 if arrival is None else float(arrival)
+        t = C.c_int64()
+        check(L.kx_submit(self.handle, C.byref(r), C.byref(t)))
+        self._inputs[t.value] = (mech, T, p, Y)
+        self._meta[t.value] = (mech.n_species, int(n), transport)
+        return t.value
+
+    def poll(self, ticket: int) -> dict:
+        res = _Result()
+        check(_serve_lib().kx_poll(self.handle, ticket, C.byref(res)))
+        return _result_dict(res)
+
+    def wait(self, ticket: int, timeout: float = -1.0) -> dict:
+        res = _Result()
+        check(_serve_lib().kx_wait(self.handle, ticket, float(timeout), C.byref(res)))
+        return _result_dict(res)
+
+    def cancel(self, ticket: int) -> None:
+        check(_serve_lib().kx_cancel(self.handle, ticket))
+
+    def outputs(self, ticket: int, stream=None):
+        """Copies of a done request's outputs: (wdot, mu, lambda, Dmix) tensors
+        (the transport ones are None when not requested)."""
+        ns, n, transport = self._meta[ticket]
+        kw = dict(dtype=torch.float64, device=f"cuda:{self.device}")
+        w = torch.empty((ns, n), **kw)
+        mu = lam = Dm = None
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+        if transport:
+            mu, lam, Dm = torch.empty(n, **kw), torch.empty(n, **kw), torch.empty((ns, n), **kw)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        check(_serve_lib().kx_result_copy(self.handle, ticket, ptr(w), ptr(mu), ptr(lam),
+                                          ptr(Dm), C.c_void_p(st.cuda_stream)))
+        st.synchronize()  # the arena space may be reused as soon as it is released
+        return w, mu, lam, Dm
+
+    def release(self, ticket: int) -> None:
+        check(_serve_lib().kx_release(self.handle, ticket))
+        self._inputs.pop(ticket, None)
+        self._meta.pop(ticket, None)
+
+    def stats(self) -> dict:
+        st = _Stats()
+        check(_serve_lib().kx_server_stats_get(self.handle, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in _Stats._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            check(_serve_lib().kx_server_destroy(self.handle))
+            self.handle = None
+            self._inputs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

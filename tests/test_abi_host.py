@@ -1,0 +1,161 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function that include/kx.h declares, and kx_mech_create_host enforces the
+descriptor contract (error codes) without touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2411_02640_amd import kx
+from tests import tiny_mechs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "kx.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w ]+?\**\s*(kx_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_api():
+    names = declared_functions()
+    for must in ("kx_mech_create", "kx_mech_create_host", "kx_production_rates",
+                 "kx_transport", "kx_thermo", "kx_submit", "kx_server_create"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported():
+    L = kx.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version():
+    assert "gfx950" in kx.version()
+
+
+@pytest.mark.parametrize("name", ["mech9", "mech53", "mech200"])
+def test_host_create(name, request):
+    mech = request.getfixturevalue(name)
+    m = kx.HostMechanism(mech)
+    assert m.n_species == mech["n_species"]
+    assert m.n_reactions == mech["n_reactions"]
+    assert m.device_bytes > 0
+    m.close()
+
+
+def _tiny():
+    return tiny_mechs.abx_mechanism()
+
+
+def _expect(mech, code, words):
+    with pytest.raises(kx.KxError) as ei:
+        kx.HostMechanism(mech)
+    assert ei.value.code == code, str(ei.value)
+    assert words in str(ei.value)
+
+
+def _mod(**kw):
+    m = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in _tiny().items()}
+    m.update(kw)
+    return m
+
+
+def test_tiny_is_valid():
+    kx.HostMechanism(_tiny()).close()
+
+
+def test_reject_bad_counts():
+    _expect(_mod(n_species=0), kx.KX_EINVAL, "n_species")
+    _expect(_mod(n_elements=0), kx.KX_EINVAL, "n_species")
+
+
+def test_reject_too_many_species(mech9):
+    m = dict(mech9)
+    m["n_species"] = 257
+    _expect(m, kx.KX_EUNSUPPORTED, "256 species")
+
+
+def test_reject_fit_parameters():
+    _expect(_mod(fit_order=0), kx.KX_EINVAL, "fit_order")
+    _expect(_mod(fit_order=9), kx.KX_EINVAL, "fit_order")
+    _expect(_mod(fit_h=0.0), kx.KX_EINVAL, "fit_h")
+    _expect(_mod(fit_L0=float("nan")), kx.KX_EINVAL, "fit_h")
+    _expect(_mod(diff_fit_kind=2), kx.KX_EINVAL, "diff_fit_kind")
+
+
+def test_reject_asymmetric_diffusion_fit():
+    m = _mod()
+    d = m["diff_fit"].copy()
+    d[0, 1, 0] += 1e-3
+    m["diff_fit"] = d
+    _expect(m, kx.KX_EINVAL, "symmetric")
+
+
+def test_reject_negative_atoms():
+    m = _mod()
+    c = m["composition"].copy()
+    c[0, 0] = -1
+    m["composition"] = c
+    _expect(m, kx.KX_EINVAL, "negative atom")
+
+
+def test_reject_bad_reaction_fields():
+    m = _mod()
+    m["A"] = m["A"].copy()
+    m["A"][0] = 0.0
+    _expect(m, kx.KX_EINVAL, "A must be > 0")
+    m = _mod()
+    m["rxn_type"] = m["rxn_type"].copy()
+    m["rxn_type"][0] = 7
+    _expect(m, kx.KX_EINVAL, "unknown reaction type")
+    m = _mod()
+    m["reac_sp"] = m["reac_sp"].copy()
+    m["reac_sp"][0] = m["n_species"]
+    _expect(m, kx.KX_EINVAL, "out of range")
+
+
+def test_reject_unbalanced_reaction():
+    comp = [[2, 0], [0, 2], [1, 1]]  # H2, O2, HO
+    nasa = np.tile([3.5, 0, 0, 0, 0, -1000.0, 3.0], (3, 1))
+    rx = [{"type": 0, "reac": [(0, 1), (1, 1)], "prod": [(2, 1)], "A": 1e10, "beta": 0.0,
+           "Ea": 0.0}]
+    _expect(tiny_mechs.build(comp, nasa, rx), kx.KX_EINVAL, "element-balanced")
+
+
+def test_reject_four_molecules_on_a_side():
+    comp = [[2, 0], [1, 0]]  # H2, H
+    nasa = np.tile([3.5, 0, 0, 0, 0, -1000.0, 3.0], (2, 1))
+    rx = [{"type": 0, "reac": [(1, 4)], "prod": [(0, 2)], "A": 1e10, "beta": 0.0, "Ea": 0.0}]
+    _expect(tiny_mechs.build(comp, nasa, rx), kx.KX_EUNSUPPORTED, "more than 3 molecules")
+
+
+def test_reject_duplicate_species_on_a_side():
+    comp = [[2, 0], [1, 0]]
+    nasa = np.tile([3.5, 0, 0, 0, 0, -1000.0, 3.0], (2, 1))
+    rx = [{"type": 0, "reac": [(1, 1), (1, 1)], "prod": [(0, 1)], "A": 1e10, "beta": 0.0,
+           "Ea": 0.0}]
+    _expect(tiny_mechs.build(comp, nasa, rx), kx.KX_EINVAL, "listed twice")
+
+
+def test_direct_calls_reject_host_mechanism():
+    L = kx.lib()
+    m = kx.HostMechanism(_tiny())
+    rc = L.kx_production_rates(m.handle, 1, None, None, None, None, None)
+    assert rc == kx.KX_EINVAL and b"device tables" in L.kx_last_error()
+    rc = L.kx_transport(m.handle, 1, None, None, None, None, None, None, None)
+    assert rc == kx.KX_EINVAL
+    m.close()
+
+
+def test_null_arguments():
+    L = kx.lib()
+    assert L.kx_production_rates(None, 1, None, None, None, None, None) == kx.KX_EINVAL
+    assert b"NULL" in L.kx_last_error()
+    d, keep = kx.make_desc(_tiny())
+    L2 = kx._serve_lib()
+    assert L2.kx_mech_create_host(C.byref(d), None) == kx.KX_EINVAL
+    assert L.kx_mech_destroy(None) == kx.KX_OK

@@ -1,0 +1,190 @@
+"""The request server on the GPU: every served request is bit-identical to a
+direct call on the same inputs, whatever it was batched with, and one served
+request is checked against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2411_02640_amd import inputs as I
+
+from . import parity as PM
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+WAIT_S = 60.0
+
+
+def _say(*a):
+    print("[gpu-serve]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kx():
+    from paper_2411_02640_amd import kx as K
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    K.lib()
+    return K
+
+
+@pytest.fixture(scope="module")
+def mechs(kx, mech9, mech53):
+    ms = {"syn9": (kx.Mechanism(mech9, 0), mech9), "syn53": (kx.Mechanism(mech53, 0), mech53)}
+    yield ms
+    for dm, _ in ms.values():
+        dm.close()
+
+
+def _inputs(ns, n, seed):
+    spec = I.StateSpec(n_points=n, seed=seed, T_range=(300.0, 2800.0), p_atm_range=(1.0, 40.0),
+                       dirichlet_alpha=0.3)
+    T, p, Y = I.make_states(ns, spec)
+    return [torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (T, p, Y)], (T, p, Y)
+
+
+def _direct(kx, dm, Td, pd, Yd, transport, precision):
+    w = kx.production_rates(dm, Td, pd, Yd, precision=precision)
+    tr = kx.transport(dm, Td, pd, Yd, precision=precision) if transport else (None,) * 3
+    torch.cuda.synchronize()
+    return (w,) + tuple(tr)
+
+
+def _same(a, b):
+    return (a is None and b is None) or torch.equal(a, b)
+
+
+def _footprint(ns, n, transport):
+    d = ns + ((ns + 2) if transport else 0)
+    return (n * 8 * d + 255) // 256 * 256
+
+
+def test_served_equals_direct_mixed_batches(kx, mechs):
+    """24 requests over two mechanisms, both precisions, both op sets and
+    ragged sizes are queued behind a finished request that holds the arena;
+    releasing it admits them all in one pass, so they run as a few mixed
+    batches.  Each output must equal the direct call bit for bit."""
+    rng = np.random.default_rng(11)
+    cases = []
+    sizes = [1, 63, 64, 65, 1000, 4097, 20000, 70001]
+    for i in range(24):
+        name = "syn9" if i % 3 == 0 else "syn53"
+        n = int(sizes[i % len(sizes)])
+        tr = bool(rng.integers(2))
+        prec = "fp64" if rng.integers(2) else "mixed"
+        dm, mech = mechs[name]
+        (Td, pd, Yd), _ = _inputs(mech["n_species"], n, 100 + i)
+        cases.append((name, n, tr, prec, Td, pd, Yd))
+    ns53 = mechs["syn53"][1]["n_species"]
+    total = sum(_footprint(mechs[c[0]][1]["n_species"], c[1], c[2]) for c in cases)
+    first = _footprint(mechs[cases[0][0]][1]["n_species"], cases[0][1], cases[0][2])
+    n_blk = -(-(total - first + 256) // (8 * ns53))
+    budget = max(total, _footprint(ns53, n_blk, False))
+    assert budget - _footprint(ns53, n_blk, False) < first
+    (Tb, pb, Yb), _ = _inputs(ns53, n_blk, 99)
+    srv = kx.Server(0, hbm_budget=budget, max_slots=64)
+    try:
+        blocker = srv.submit(mechs["syn53"][0], Tb, pb, Yb)
+        assert srv.wait(blocker, WAIT_S)["state"] == "done"
+        reqs = [(srv.submit(mechs[c[0]][0], *c[4:], transport=c[2], precision=c[3]), c)
+                for c in cases]
+        assert srv.stats()["queued"] == len(cases)
+        srv.release(blocker)
+        for t, (name, n, tr, prec, Td, pd, Yd) in reqs:
+            _say("request", t, name, "n =", n, "transport" if tr else "rates", prec)
+            r = srv.wait(t, WAIT_S)
+            assert r["state"] == "done", r
+            got = srv.outputs(t)
+            ref = _direct(kx, mechs[name][0], Td, pd, Yd, tr, prec)
+            for g, e, what in zip(got, ref, ("wdot", "mu", "lambda", "Dmix")):
+                assert _same(g, e), (name, n, prec, what)
+            srv.release(t)
+        st = srv.stats()
+        _say(st)
+        assert st["completed"] == len(cases) + 1 and st["failed"] == 0
+        # one batch per (mechanism, precision) group after the blocker
+        assert st["batches"] <= 1 + 4
+        assert st["arena_in_use"] == 0
+    finally:
+        srv.close()
+
+
+def test_served_matches_oracle(kx, mechs):
+    dm, mech = mechs["syn53"]
+    (Td, pd, Yd), (T, p, Y) = _inputs(mech["n_species"], 3001, 7)
+    srv = kx.Server(0, hbm_budget=256 << 20, max_slots=8)
+    try:
+        t = srv.submit(dm, Td, pd, Yd, transport=True)
+        assert srv.wait(t, WAIT_S)["state"] == "done"
+        w, mu, lam, Dm = [x.cpu().numpy() for x in srv.outputs(t)]
+        srv.release(t)
+    finally:
+        srv.close()
+    om = O.OracleMech(mech)
+    ref, s = om.production_rates(T, p, Y)
+    rep = PM.wdot_report(w, ref, s)
+    _say(rep)
+    assert rep["ok"], rep
+    rmu, rlam, rDm = om.transport(T, p, Y)
+    for name, g, r in (("mu", mu, rmu), ("lambda", lam, rlam), ("Dmix", Dm, rDm)):
+        rep = PM.rel_report(g, r, PM.REL_FP64)
+        assert rep["ok"], (name, rep)
+
+
+def test_budget_pressure_and_cancel(kx, mechs):
+    dm, mech = mechs["syn53"]
+    ns, n = mech["n_species"], 30000
+    fp = (n * 8 * ns + 255) // 256 * 256
+    srv = kx.Server(0, hbm_budget=2 * fp, max_slots=16)
+    try:
+        (Td, pd, Yd), _ = _inputs(ns, n, 21)
+        ref = _direct(kx, dm, Td, pd, Yd, False, "fp64")[0]
+        a = srv.submit(dm, Td, pd, Yd)
+        b = srv.submit(dm, Td, pd, Yd)
+        assert srv.wait(a, WAIT_S)["state"] == "done"
+        assert srv.wait(b, WAIT_S)["state"] == "done"
+        c = srv.submit(dm, Td, pd, Yd)            # arena full: stays queued
+        d = srv.submit(dm, Td, pd, Yd)
+        with pytest.raises(kx.KxError):
+            srv.wait(c, 0.2)
+        srv.cancel(c)
+        assert srv.poll(c)["state"] == "cancelled"
+        for t in (a, b):
+            assert torch.equal(srv.outputs(t)[0], ref)
+            srv.release(t)
+        assert srv.wait(d, WAIT_S)["state"] == "done"
+        assert torch.equal(srv.outputs(d)[0], ref)
+        srv.release(d)
+        srv.release(c)
+        st = srv.stats()
+        assert st["cancelled"] == 1 and st["completed"] == 3 and st["arena_in_use"] == 0
+    finally:
+        srv.close()
+
+
+def test_graph_replay_across_batches(kx, mechs):
+    """Many batches of one group replay the same graph; every replay stays
+    equal to the direct result."""
+    dm, mech = mechs["syn9"]
+    ns = mech["n_species"]
+    srv = kx.Server(0, hbm_budget=512 << 20, max_slots=4)
+    try:
+        for rep in range(6):
+            n = 5000 + 977 * rep
+            (Td, pd, Yd), _ = _inputs(ns, n, 300 + rep)
+            ts = [srv.submit(dm, Td, pd, Yd, transport=True) for _ in range(3)]
+            ref = _direct(kx, dm, Td, pd, Yd, True, "fp64")
+            for t in ts:
+                assert srv.wait(t, WAIT_S)["state"] == "done"
+                got = srv.outputs(t)
+                for g, e in zip(got, ref):
+                    assert torch.equal(g, e)
+                srv.release(t)
+        st = srv.stats()
+        _say(st)
+        assert st["graph_launches"] == st["batches"] >= 2
+    finally:
+        srv.close()
