@@ -90,18 +90,20 @@ constexpr int kKB = 8;
 struct MechDev {
     int32_t ns, nr, nchunks;   // species, reactions, reaction chunks for the gather
     int32_t chunk;             // reactions per chunk (multiple of 64)
-    int32_t gpass;             // species passes of the gather (ceil(ns / 64))
+    int32_t gpass;             // species per lane in the species phases (1, 2 or 4)
     int32_t fit_order, diff_kind;
     double fit_L0, inv_fit_h;
     const DevRxn *rxn;         // [nr] kernel order
     const DevAux *aux;         // [naux]
     const DevEff *eff;         // [neff]
     const DevSpecies *sp;      // [ns]
-    const int32_t *glen;       // [nchunks] uniform trip count of the gather
-    const int32_t *goff;       // [nchunks] first entry of each chunk
-    const int32_t *gent;       // [chunk][it][64 * gpass] entries, lane-interleaved:
-                               // (8 * slot_in_chunk) << 8 | (uint8_t)(int8_t) nu; padding
-                               // entries read the zero element after the chunk
+    const int32_t *gpos;       // [nchunks] groups of eight +q entries of the gather
+    const int32_t *gneg;       // [nchunks] groups of eight -q entries
+    const int32_t *goff;       // [nchunks] first group of each chunk
+    const uint4 *gent;         // [group][64 * gpass]: eight 16-bit LDS byte offsets
+                               // 16 * slot_in_chunk per lane and group (a species with
+                               // |nu''-nu'| = 2 or 3 lists the slot that many times);
+                               // padding entries read the zero slot after the chunk
     // transport (FP64)
     const double *W;           // [ns]
     const double *visc;        // [ns][order]

@@ -11,22 +11,20 @@
 //  krcp(d):  v_rcp_f64 (about 24 correct bits on gfx950) followed by two
 //            Newton-Raphson steps r <- r + r (1 - d r).
 //  krsqrt(x): v_rsq_f64 followed by two Newton steps r <- r (3 - x r^2) / 2.
+//  kln(x):   x = 2^e m with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s),
+//            s = (m - 1) / (m + 1), |s| <= 0.1716, from the odd series
+//            2 (s + s^3/3 + ... + s^21/21) (truncation below 1e-18 relative),
+//            plus e ln 2 with ln 2 in two parts.  Positive normal x only.
 //
-// The polynomial steps are written as VOP3 v_fma_f64 so that the compiler keeps
-// each coefficient in a register that is never overwritten (the two-address
-// v_fmac form otherwise copies every coefficient before each use).
+// The polynomial steps are written as VOP3 v_fma_f64 whose constant operand is
+// a scalar register pair: the coefficients then live in SGPRs (materialised by
+// cheap scalar moves) instead of occupying vector registers for the whole
+// kernel, and the two-address v_fmac form's per-use copies are avoided.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace kx {
-
-__device__ __forceinline__ double fma3(double a, double b, double c)
-{
-    double d;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-    return d;
-}
 
 // a * b + c with a wave-uniform addend c read straight from scalar registers.
 __device__ __forceinline__ double fma_s(double a, double b, double c)
@@ -49,29 +47,20 @@ __device__ __forceinline__ double kexp(double x)
     double r = __builtin_fma(-n, 6.93147180559945286227e-01, x);
     r = __builtin_fma(-n, 2.31904681384629955842e-17, r);
     double p = 1.0 / 6227020800.0;      // 1/13!
-    p = fma3(p, r, 1.0 / 479001600.0);  // 1/12!
-    p = fma3(p, r, 1.0 / 39916800.0);
-    p = fma3(p, r, 1.0 / 3628800.0);
-    p = fma3(p, r, 1.0 / 362880.0);
-    p = fma3(p, r, 1.0 / 40320.0);
-    p = fma3(p, r, 1.0 / 5040.0);
-    p = fma3(p, r, 1.0 / 720.0);
-    p = fma3(p, r, 1.0 / 120.0);
-    p = fma3(p, r, 1.0 / 24.0);
-    p = fma3(p, r, 1.0 / 6.0);
+    p = fma_s(p, r, 1.0 / 479001600.0);  // 1/12!
+    p = fma_s(p, r, 1.0 / 39916800.0);
+    p = fma_s(p, r, 1.0 / 3628800.0);
+    p = fma_s(p, r, 1.0 / 362880.0);
+    p = fma_s(p, r, 1.0 / 40320.0);
+    p = fma_s(p, r, 1.0 / 5040.0);
+    p = fma_s(p, r, 1.0 / 720.0);
+    p = fma_s(p, r, 1.0 / 120.0);
+    p = fma_s(p, r, 1.0 / 24.0);
+    p = fma_s(p, r, 1.0 / 6.0);
     p = __builtin_fma(p, r, 0.5);
     p = __builtin_fma(p, r, 1.0);
     p = __builtin_fma(p, r, 1.0);
     return __builtin_ldexp(p, (int)n);
-}
-
-// 10^x = e^(x ln 10) with ln 10 split in two parts.
-__device__ __forceinline__ double kexp10(double x)
-{
-    const double hi = x * 2.30258509299404568402;
-    const double lo = __builtin_fma(x, 2.30258509299404568402, -hi) +
-                      x * -2.17075622338224935e-16;
-    return kexp(hi) * (1.0 + lo);
 }
 
 __device__ __forceinline__ double krcp(double d)
@@ -89,6 +78,34 @@ __device__ __forceinline__ double krcp1(double d)
 {
     const double r = __builtin_amdgcn_rcp(d);
     return __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+}
+
+__device__ __forceinline__ double kln(double x)
+{
+    int e;
+    double m = __builtin_frexp(x, &e);  // m in [0.5, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double f = m - 1.0;  // exact
+    const double s = f * krcp(m + 1.0);
+    const double z = s * s;
+    double q = 1.0 / 21.0;
+    q = fma_s(q, z, 1.0 / 19.0);
+    q = fma_s(q, z, 1.0 / 17.0);
+    q = fma_s(q, z, 1.0 / 15.0);
+    q = fma_s(q, z, 1.0 / 13.0);
+    q = fma_s(q, z, 1.0 / 11.0);
+    q = fma_s(q, z, 1.0 / 9.0);
+    q = fma_s(q, z, 1.0 / 7.0);
+    q = fma_s(q, z, 1.0 / 5.0);
+    q = __builtin_fma(q, z, 1.0 / 3.0);
+    const double s2 = s + s;
+    const double lnm = __builtin_fma(s2 * z, q, s2);
+    const double de = (double)e;
+    return __builtin_fma(de, 6.93147180559945286227e-01,
+                         __builtin_fma(de, 2.31904681384629955842e-17, lnm));
 }
 
 __device__ __forceinline__ double krsqrt(double x)

@@ -233,15 +233,24 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     if (eff.empty()) eff.resize(1);
     if (aux.empty()) aux.resize(1);
 
-    // ---- species-major gather lists per reaction chunk, padded to a uniform
-    // trip count and interleaved so that lane k reads entry (it, k) coalesced
+    // ---- species-major gather lists per reaction chunk.  Each species lists
+    // the chunk slots of the reactions that produce it (+q, once per unit of
+    // net nu) and of those that consume it (-q); both lists are padded to a
+    // whole number of eight-entry groups common to all lanes, and a group is
+    // eight 16-bit LDS offsets (16 bytes per lane, so lane k reads it with one
+    // coalesced 16-byte load).  The rates of progress of two points sit side by
+    // side in LDS, so one offset addresses both.
     const int chunk = std::max(kWave, std::min(512, (nr + kWave - 1) / kWave * kWave));
     const int nchunks = std::max(1, (nr + chunk - 1) / chunk);
-    const int gpass = (ns + kWave - 1) / kWave;
+    // species per lane of the species phases: 1, 2 or 4 (the kernels are
+    // instantiated for these), so lists are laid out for 64 * gpass lanes
+    const int gpass = ns <= kWave ? 1 : (ns <= 2 * kWave ? 2 : 4);
     const int gw = kWave * gpass;
-    std::vector<int32_t> glen(nchunks), goff(nchunks), gent;
+    std::vector<int32_t> gpos(nchunks), gneg(nchunks), goff(nchunks);
+    std::vector<uint16_t> gent;  // 8 per (group, lane)
+    size_t ngroups = 0;
     for (int c = 0; c < nchunks; ++c) {
-        std::vector<std::vector<int32_t>> per(gw);
+        std::vector<std::vector<uint16_t>> pos(gw), neg(gw);
         for (int s = c * chunk; s < std::min(nr, (c + 1) * chunk); ++s) {
             const int i = perm[s];
             std::vector<std::pair<int, int>> net;  // (species, nu'' - nu')
@@ -254,22 +263,33 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
                 addnu(d->reac_sp[e], -d->reac_nu[e]);
             for (int e = d->prod_ptr[i]; e < d->prod_ptr[i + 1]; ++e)
                 addnu(d->prod_sp[e], d->prod_nu[e]);
-            for (auto &pr : net) {
-                if (pr.second == 0) continue;
-                per[pr.first].push_back(((8 * (s - c * chunk)) << 8) |
-                                        (int32_t)(uint8_t)(int8_t)pr.second);
-            }
+            const uint16_t slot = (uint16_t)(16 * (s - c * chunk));
+            for (auto &pr : net)
+                for (int u = 0; u < std::abs(pr.second); ++u)
+                    (pr.second > 0 ? pos : neg)[pr.first].push_back(slot);
         }
-        size_t len = 0;
-        for (auto &v : per) len = std::max(len, v.size());
-        len = (len + 7) / 8 * 8;  // the kernel consumes entries eight at a time
-        glen[c] = (int32_t)len;
-        goff[c] = (int32_t)gent.size();
-        const int32_t pad = (8 * chunk) << 8;  // zero element, nu = 0
-        for (size_t it = 0; it < len; ++it)
-            for (int k = 0; k < gw; ++k) gent.push_back(it < per[k].size() ? per[k][it] : pad);
+        size_t lp = 0, ln = 0;
+        for (int k = 0; k < gw; ++k) {
+            lp = std::max(lp, pos[k].size());
+            ln = std::max(ln, neg[k].size());
+        }
+        gpos[c] = (int32_t)((lp + 7) / 8);
+        gneg[c] = (int32_t)((ln + 7) / 8);
+        goff[c] = (int32_t)ngroups;
+        const uint16_t pad = (uint16_t)(16 * chunk);  // the zero slot
+        for (int side = 0; side < 2; ++side) {
+            const auto &lists = side ? neg : pos;
+            const int groups = side ? gneg[c] : gpos[c];
+            for (int g = 0; g < groups; ++g)
+                for (int k = 0; k < gw; ++k)
+                    for (int u = 0; u < 8; ++u) {
+                        const size_t e = (size_t)g * 8 + u;
+                        gent.push_back(e < lists[k].size() ? lists[k][e] : pad);
+                    }
+            ngroups += groups;
+        }
     }
-    if (gent.empty()) gent.push_back(0);
+    if (gent.empty()) gent.resize(8, 0);
 
     // ---- species thermo
     std::vector<DevSpecies> spv(ns);
@@ -327,7 +347,8 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
 
     Blob b;
     const size_t o_rxn = add_vec(b, rx), o_aux = add_vec(b, aux), o_eff = add_vec(b, eff);
-    const size_t o_sp = add_vec(b, spv), o_glen = add_vec(b, glen), o_goff = add_vec(b, goff);
+    const size_t o_sp = add_vec(b, spv), o_gpos = add_vec(b, gpos), o_gneg = add_vec(b, gneg);
+    const size_t o_goff = add_vec(b, goff);
     const size_t o_gent = add_vec(b, gent);
     const size_t o_W = add_vec(b, W), o_visc = add_vec(b, visc), o_cond = add_vec(b, cond);
     const size_t o_wil = add_vec(b, wilke), o_df = add_vec(b, dfit), o_dd = add_vec(b, ddiag);
@@ -383,9 +404,10 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     v.aux = (const DevAux *)at(o_aux);
     v.eff = (const DevEff *)at(o_eff);
     v.sp = (const DevSpecies *)at(o_sp);
-    v.glen = (const int32_t *)at(o_glen);
+    v.gpos = (const int32_t *)at(o_gpos);
+    v.gneg = (const int32_t *)at(o_gneg);
     v.goff = (const int32_t *)at(o_goff);
-    v.gent = (const int32_t *)at(o_gent);
+    v.gent = (const uint4 *)at(o_gent);
     v.W = (const double *)at(o_W);
     v.visc = (const double *)at(o_visc);
     v.cond = (const double *)at(o_cond);

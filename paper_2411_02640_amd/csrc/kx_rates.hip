@@ -1,29 +1,34 @@
 // kx_rates.hip -- species net production rates on gfx950.
 //
-// Work decomposition (one wave per grid point at a time).  A workgroup is one
-// wave that owns a tile of `tp` consecutive points: the tile of Y is staged
-// through LDS with coalesced row loads, and the same LDS tile later receives
-// wdot and is written back with coalesced row stores.  For each of its points
-// the wave runs three phases, with lanes spread over species, then reactions,
-// then species again:
+// Work decomposition.  A workgroup is one wave that owns a tile of `tp`
+// consecutive points: the tile of Y is staged through LDS with coalesced row
+// loads, and the same LDS tile later receives wdot and is written back with
+// coalesced row stores.  The wave takes the tile's points two at a time and
+// runs three phases, with lanes spread over species, then (reaction, point)
+// pairs, then species again:
 //
-//  1. species (lane = k): C_k, the Gibbs energy g_k = G_k/RT of eq:Ck (range by
-//     T_mid), a_k = (p_atm/RT) exp(-g_k) and b_k = C_k / a_k into LDS as one
-//     16-byte pair per species.  With these, prod_k C_k^nu' = A' B' and prod_k C_k^nu'' / K_c = A' B''
+//  1. species (lane = k, both points): C_k, the Gibbs energy g_k = G_k/RT of
+//     eq:Ck (range by T_mid), a_k = (p_atm/RT) exp(-g_k) and b_k = C_k / a_k
+//     into LDS as one 16-byte pair per species and point.  With these,
+//     prod_k C_k^nu' = A' B' and prod_k C_k^nu'' / K_c = A' B''
 //     (A' = prod_reac a^nu', B' = prod_reac b^nu', B'' = prod_prod b^nu''), since
 //     K_c = prod_k a_k^(nu''-nu') by eq:K_p and K_c = K_p (p_atm/RT)^(sum nu).
 //     So K_c needs one exponential per species instead of one per reaction and
 //     the rate of progress needs no division:
 //         R_i = c_i k_f A' (B' - B'')                   (eq:r_i, eq:c_i)
 //     and B' - B'' is the near-equilibrium difference, formed in FP64.
-//  2. reactions (lane = reaction): k_f (eq:arrhenius, with the beta = E_R = 0
-//     shortcut of eq:k_f), [X]_i, the Lindemann / Troe factor (eq:blend) and
-//     R_i into an LDS array, one chunk of reactions at a time.  Each reaction
-//     side is three molecule slots (unused ones hit a dummy species with
-//     a = b = 1), so the products A', B', B'' are branch-free.
-//  3. species (lane = k): wdot_k = sum_i nu_ki R_i gathered from a species-major
-//     list of (reaction, nu) pairs -- a fixed summation order, so results are
-//     deterministic; the mixed path accumulates with Neumaier compensation.
+//  2. reactions (lanes 2r, 2r+1 = reaction r at the two points): k_f
+//     (eq:arrhenius, with the beta = E_R = 0 shortcut of eq:k_f), [X]_i, the
+//     Lindemann / Troe factor (eq:blend) and R_i into LDS, one chunk of
+//     reactions at a time.  Reactions are sorted heaviest type first, so the
+//     falloff code runs for 32 reactions x 2 points per 64-lane iteration.
+//     Each reaction side is three molecule slots (unused ones hit a dummy
+//     species with a = b = 1), so the products A', B', B'' are branch-free.
+//  3. species (lane = k, both points): wdot_k = sum_i nu_ki R_i gathered from
+//     species-major lists of +R and -R entries (a net |nu| of 2 or 3 is listed
+//     that many times); one 16-byte LDS read returns R_i at both points.  The
+//     summation order is fixed, so results are deterministic; the mixed path
+//     accumulates with Neumaier compensation.
 #include <float.h>
 
 #include <type_traits>
@@ -42,15 +47,6 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-    // xor butterfly: every lane forms the same sums (a + b == b + a), so all
-    // lanes end with the bit-identical total.
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
-
 // exp(x) for the mixed path: the argument stays in FP64, is reduced by n ln 2
 // in FP64 and only exp(r), |r| <= ln2/2, is evaluated in FP32.
 __device__ __forceinline__ double exp_mixed(double x)
@@ -61,26 +57,22 @@ __device__ __forceinline__ double exp_mixed(double x)
     return ldexp((double)er, (int)nd);
 }
 
-template <bool MIXED>
-__device__ __forceinline__ double arrhenius(double lnA, double beta, double ER, double lnT,
-                                            double invT)
+// Troe blending factor (eq:blend).  The base-10 logarithms of the paper are
+// formed from natural ones: log10 F_cent = ln F_cent / ln 10, and
+// F = 10^(log10 F_cent / (1 + f1^2)) = exp(ln F_cent / (1 + f1^2)).
+__device__ __forceinline__ double troe_F64(const DevAux &ax, double T, double invT, double lnPr)
 {
-    const double x = fma(beta, lnT, fma(-ER, invT, lnA));
-    return MIXED ? exp_mixed(x) : kexp(x);
-}
-
-// Troe blending factor (eq:blend, base-10 logarithms).
-__device__ __forceinline__ double troe_F64(const DevAux &ax, double T, double invT, double Pr)
-{
+    constexpr double kInvLn10 = 0.43429448190325182765;
     double Fc = (1.0 - ax.troe_alpha) * kexp(-T * ax.troe_inv_T3) +
                 ax.troe_alpha * kexp(-T * ax.troe_inv_T1);
     if (ax.has_T2) Fc += kexp(-ax.troe_T2 * invT);
-    const double lFc = log10(Fc);
+    const double lnFc = kln(Fc);
+    const double lFc = lnFc * kInvLn10;
     const double c = -0.4 - 0.67 * lFc;
     const double nn = 0.75 - 1.27 * lFc;
-    const double x = log10(fmax(Pr, DBL_MIN)) + c;
+    const double x = fma(lnPr, kInvLn10, c);
     const double f1 = x * krcp(nn - 0.14 * x);
-    return kexp10(lFc * krcp(1.0 + f1 * f1));
+    return kexp(lnFc * krcp(fma(f1, f1, 1.0)));
 }
 
 // FP32 Troe blend from log10 P_r (computed by the caller without overflow).
@@ -163,11 +155,9 @@ __device__ __forceinline__ double rate_of_progress(const MechDev &m, const RxnWo
     const unsigned flags = (w.w2.w >> 8) & 0xFFu;
     const unsigned aux = w.w2.w >> 16;
 
-    double kf;
-    if (flags & kFlagKfConst)
-        kf = A;
-    else
-        kf = arrhenius<MIXED>(lnA, beta, ER, lnT, invT);
+    // exponent of k_f (eq:k_f); k_f = A without an exponential when beta = E_R = 0
+    const double xf = (flags & kFlagKfConst) ? lnA : fma(beta, lnT, fma(-ER, invT, lnA));
+    const double kf = (flags & kFlagKfConst) ? A : (MIXED ? exp_mixed(xf) : kexp(xf));
     const Pair r0 = load_pair(pb, w.w2.x & 0xFFFFu);
     const Pair r1 = load_pair(pb, w.w2.x >> 16);
     const Pair r2 = load_pair(pb, w.w2.y & 0xFFFFu);
@@ -177,16 +167,23 @@ __device__ __forceinline__ double rate_of_progress(const MechDev &m, const RxnWo
                        load_b(pb, w.w2.z >> 16);
     double c = 1.0;
     if (type != KX_RXN_ELEMENTARY) {
-        const DevAux ax = m.aux[aux];
+        const DevAux &ax = m.aux[aux];
         const double X = third_body(m, ax, pb, Mconc);
         c = X;
         if (type != KX_RXN_THREEBODY) {
-            const double k0 = arrhenius<MIXED>(ax.lnA0, ax.beta0, ax.ER0, lnT, invT);
-            const double Pr = k0 * X * krcp(kf);
+            // P_r = k_0 [X] / k_inf = exp(x_0 - x_inf) [X] (no division)
+            const double d0 = fma(ax.beta0, lnT, fma(-ax.ER0, invT, ax.lnA0)) - xf;
+            const double Pr = (MIXED ? exp_mixed(d0) : kexp(d0)) * X;
             double F = 1.0;
-            if (type == KX_RXN_TROE)
-                F = MIXED ? (double)troe_F32(ax, (float)Ti, (float)invT, log10_wide(Pr))
-                          : troe_F64(ax, Ti, invT, Pr);
+            if (type == KX_RXN_TROE) {
+                if (MIXED) {
+                    F = (double)troe_F32(ax, (float)Ti, (float)invT, log10_wide(Pr));
+                } else {
+                    // ln max(P_r, DBL_MIN) without forming the logarithm of P_r
+                    const double lnPr = fmax(d0 + kln(fmax(X, DBL_MIN)), -708.39641853226410622);
+                    F = troe_F64(ax, Ti, invT, lnPr);
+                }
+            }
             c = Pr * krcp(1.0 + Pr) * F;
         }
     }
@@ -194,13 +191,50 @@ __device__ __forceinline__ double rate_of_progress(const MechDev &m, const RxnWo
     return c * kf * Ap * fma(-rev, Bpp, Bp);
 }
 
+// Gibbs energy g = G/RT of one species at one temperature (eq:Ck with the
+// coefficients pre-scaled: g = c0 (1 - ln T) + c1 T + ... + c4 T^4 + c5 / T + c6).
+__device__ __forceinline__ double gibbs(const DevSpecies &S, double T, double lnT, double invT)
+{
+    const double *g = (T < S.t_mid) ? S.g_lo : S.g_hi;
+    const double poly = T * fma(T, fma(T, fma(T, g[4], g[3]), g[2]), g[1]);
+    return fma(g[0], 1.0 - lnT, poly) + fma(g[5], invT, g[6]);
+}
+
+template <bool MIXED>
+__device__ __forceinline__ void accumulate(double &acc, double &cmp, double t)
+{
+    if (MIXED) {
+        const double sum = acc + t;
+        cmp += (fabs(acc) >= fabs(t)) ? (acc - sum) + t : (t - sum) + acc;
+        acc = sum;
+    } else {
+        acc += t;
+    }
+}
+
+// Per-point constants of a tile, computed once per point (lane = point).
+struct PointConst {
+    double T, lnT, invT, M;  // temperature, ln T, 1/T, [M] = p / RT
+    double P0, cf;           // p_atm / RT; C_k = Y_k / W_k * cf with cf = [M] W-bar
+    double pad[2];
+};
+
 // LDS layout of one workgroup (one wave):
-//   pairs [ns + 1] {a, b}   (entry ns is the dummy species, {1, 1})
-//   sq    [chunk + 1]       (rates of progress of the current chunk; the last
-//                            element is the zero the gather padding reads)
-//   Yt    [ns][tp + 1]      (Y tile in, wdot tile out)
-// One tile of `npts` (<= tp) points starting at point i0 of arrays whose
-// species rows have stride ld.  Called by the whole (one-wave) workgroup.
+//   sq    [chunk + 1][2]    rates of progress of the current chunk for the two
+//                           points of a step, side by side (slot `chunk` is zero
+//                           and absorbs the gather padding); at byte 0 so that
+//                           the gather offsets are LDS addresses
+//   pairs [2][ns + 1] {a, b} per point (entry ns is the dummy species, {1, 1})
+//   pc    [tp]              PointConst of the tile's points
+//   Yt    [ns][tp + 1]      Y tile in, wdot tile out (coalesced row loads/stores)
+// One tile of `npts` (<= tp, tp even) points starting at point i0 of arrays
+// whose species rows have stride ld, two points per step:
+//   phase 1 -- lane = species, both points;
+//   phase 2 -- lane = (reaction, point): lanes 2r and 2r+1 take reaction r for
+//              the two points, so a group of 32 falloff reactions fills a whole
+//              64-lane iteration;
+//   phase 3 -- lane = species, both points: one 16-byte LDS read per list entry
+//              returns the rate of progress of the reaction at both points.
 template <bool MIXED, int SPL>
 __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t i0, int npts,
                                            int tp, const double *__restrict__ T,
@@ -212,65 +246,73 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
     const int ns = m.ns;
     const int ys = tp + 1;
     const int lane = threadIdx.x;
-    double *pairs = lds;
-    double *sq = lds + 2 * (ns + 1);
-    double *Yt = sq + (m.chunk + 1);
-    const char *pb = reinterpret_cast<const char *>(pairs);
+    double *sq = lds;
+    double *pairs = sq + 2 * (m.chunk + 1);
+    PointConst *pc = reinterpret_cast<PointConst *>(pairs + 4 * (ns + 1));
+    double *Yt = reinterpret_cast<double *>(pc + tp);
     const char *qb = reinterpret_cast<const char *>(sq);
 
     for (int e = lane; e < ns * tp; e += kWave) {
         const int k = e / tp, c = e - k * tp;
         Yt[k * ys + c] = (c < npts) ? Y[(int64_t)k * ld + i0 + c] : 0.0;
     }
-    if (lane == 0) {
-        pairs[2 * ns] = 1.0;
-        pairs[2 * ns + 1] = 1.0;
-        sq[m.chunk] = 0.0;
+    if (lane < 2) {
+        pairs[2 * ns + 2 * (ns + 1) * lane] = 1.0;
+        pairs[2 * ns + 2 * (ns + 1) * lane + 1] = 1.0;
+        sq[2 * m.chunk + lane] = 0.0;
+    }
+    __syncthreads();
+    if (lane < tp) {
+        // lane = point; the padding points of a partial tile repeat its last one
+        const int c = min(lane, npts - 1);
+        const int64_t i = i0 + c;
+        PointConst q;
+        q.T = T[i];
+        q.lnT = kln(q.T);
+        q.invT = krcp(q.T);
+        const double invRT = krcp(kRu * q.T);
+        q.M = P[i] * invRT;
+        q.P0 = kPatm * invRT;
+        double wsum = 0.0;  // sum_k Y_k / W_k = 1 / W-bar
+        for (int k = 0; k < ns; ++k) wsum = fma(Yt[k * ys + c], m.sp[k].inv_W, wsum);
+        q.cf = q.M * krcp(wsum);
+        q.pad[0] = q.pad[1] = 0.0;
+        pc[lane] = q;
     }
     __syncthreads();
 
+    const int jl = lane & 1;   // point of this lane in phase 2
+    const int rl = lane >> 1;  // reaction slot of this lane in phase 2
+    const char *pbl = reinterpret_cast<const char *>(pairs + 2 * (ns + 1) * jl);
     const int gw = kWave * m.gpass;
-    for (int pl = 0; pl < npts; ++pl) {
-        const int64_t i = i0 + pl;
-        const double Ti = T[i], pi = P[i];
-        const double lnT = log(Ti), invT = 1.0 / Ti;
-        const double RT = kRu * Ti;
-        const double P0 = kPatm / RT;
-        const double Mconc = pi / RT;
-
-        // ---- phase 1: species
-        double yk[SPL];
-        double part = 0.0;
-#pragma unroll
-        for (int s = 0; s < SPL; ++s) {
-            const int k = lane + kWave * s;
-            yk[s] = 0.0;
-            if (k < ns) {
-                yk[s] = Yt[k * ys + pl];
-                part = fma(yk[s], m.sp[k].inv_W, part);
-            }
-        }
-        const double cfac = Mconc / wave_sum(part);
+    for (int pl = 0; pl < npts; pl += 2) {
+        // ---- phase 1: species (both points per lane)
+        const PointConst p2[2] = {pc[pl], pc[pl + 1]};
 #pragma unroll
         for (int s = 0; s < SPL; ++s) {
             const int k = lane + kWave * s;
             if (k < ns) {
                 const DevSpecies &S = m.sp[k];
-                const double *g = (Ti < S.t_mid) ? S.g_lo : S.g_hi;
-                const double poly = Ti * fma(Ti, fma(Ti, fma(Ti, g[4], g[3]), g[2]), g[1]);
-                const double gk = fma(g[0], 1.0 - lnT, poly) + fma(g[5], invT, g[6]);
-                const double ak = P0 * kexp(-gk);
-                const double Ck = yk[s] * S.inv_W * cfac;
-                pairs[2 * k] = ak;
-                pairs[2 * k + 1] = Ck * krcp(ak);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const PointConst &q = p2[j];
+                    const double ak = q.P0 * kexp(-gibbs(S, q.T, q.lnT, q.invT));
+                    const double Ck = Yt[k * ys + pl + j] * S.inv_W * q.cf;
+                    double *pr = pairs + 2 * (ns + 1) * j + 2 * k;
+                    pr[0] = ak;
+                    pr[1] = Ck * krcp(ak);
+                }
             }
         }
         wave_sync();
+        // the point of this lane in phase 2
+        const PointConst &ql = pc[pl + jl];
+        const double Tl = ql.T, lnTl = ql.lnT, invTl = ql.invT, Ml = ql.M;
 
         // ---- phases 2 and 3, one chunk of reactions at a time
-        double acc[SPL], cmp[SPL];
+        double acc[SPL][2], cmp[SPL][2];
 #pragma unroll
-        for (int s = 0; s < SPL; ++s) acc[s] = cmp[s] = 0.0;
+        for (int s = 0; s < SPL; ++s) acc[s][0] = acc[s][1] = cmp[s][0] = cmp[s][1] = 0.0;
         for (int c = 0; c < m.nchunks; ++c) {
             const int base = c * m.chunk;
             const int cnt = min(m.chunk, m.nr - base);
@@ -279,44 +321,48 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
             const uint4 *rsrc = reinterpret_cast<const uint4 *>(m.rxn + base);
             RxnWords w;
             w.w0 = w.w1 = w.w2 = make_uint4(0, 0, 0, 0);
-            if (lane < cnt) {
-                w.w0 = rsrc[3 * lane];
-                w.w1 = rsrc[3 * lane + 1];
-                w.w2 = rsrc[3 * lane + 2];
+            if (rl < cnt) {
+                w.w0 = rsrc[3 * rl];
+                w.w1 = rsrc[3 * rl + 1];
+                w.w2 = rsrc[3 * rl + 2];
             }
-            for (int r = lane; r < cnt; r += kWave) {
+            for (int r = rl; r < cnt; r += kWave / 2) {
                 const RxnWords cur = w;
-                const int rn = r + kWave;
+                const int rn = r + kWave / 2;
                 if (rn < cnt) {
                     w.w0 = rsrc[3 * rn];
                     w.w1 = rsrc[3 * rn + 1];
                     w.w2 = rsrc[3 * rn + 2];
                 }
-                sq[r] = rate_of_progress<MIXED>(m, cur, pb, Ti, lnT, invT, Mconc);
+                sq[2 * r + jl] = rate_of_progress<MIXED>(m, cur, pbl, Tl, lnTl, invTl, Ml);
             }
             wave_sync();
-            const int len = m.glen[c];  // a multiple of 8
-            const int32_t *ge = m.gent + m.goff[c] + lane;
+            const int npos = m.gpos[c], ngrp = npos + m.gneg[c];
+            const uint4 *ge = m.gent + (size_t)m.goff[c] * gw + lane;
 #pragma unroll
             for (int s = 0; s < SPL; ++s) {
-                const int32_t *g = ge + kWave * s;
-                for (int it = 0; it < len; it += 8) {
-                    int32_t v[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) v[u] = g[(size_t)(it + u) * gw];
+                const uint4 *g = ge + kWave * s;
+                uint4 nxt = ngrp > 0 ? g[0] : make_uint4(0, 0, 0, 0);
+                for (int it = 0; it < ngrp; ++it) {
+                    const uint4 v = nxt;
+                    if (it + 1 < ngrp) nxt = g[(size_t)(it + 1) * gw];
+                    const unsigned off[8] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16,
+                                             v.z & 0xFFFFu, v.z >> 16, v.w & 0xFFFFu, v.w >> 16};
+                    // the eight entries of a group are summed plainly; the
+                    // mixed path compensates the running sum across groups
+                    double g0 = 0.0, g1 = 0.0;
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
-                        const double q = *reinterpret_cast<const double *>(qb + (v[u] >> 8));
-                        const double t = (double)(int8_t)(v[u] & 0xFF) * q;
-                        if (MIXED) {
-                            const double sum = acc[s] + t;
-                            cmp[s] += (fabs(acc[s]) >= fabs(t)) ? (acc[s] - sum) + t
-                                                                : (t - sum) + acc[s];
-                            acc[s] = sum;
-                        } else {
-                            acc[s] += t;
-                        }
+                        const double2 q2 = *reinterpret_cast<const double2 *>(qb + off[u]);
+                        g0 += q2.x;
+                        g1 += q2.y;
                     }
+                    if (it >= npos) {
+                        g0 = -g0;
+                        g1 = -g1;
+                    }
+                    accumulate<MIXED>(acc[s][0], cmp[s][0], g0);
+                    accumulate<MIXED>(acc[s][1], cmp[s][1], g1);
                 }
             }
             wave_sync();
@@ -324,7 +370,10 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
 #pragma unroll
         for (int s = 0; s < SPL; ++s) {
             const int k = lane + kWave * s;
-            if (k < ns) Yt[k * ys + pl] = MIXED ? acc[s] + cmp[s] : acc[s];
+            if (k < ns) {
+                Yt[k * ys + pl] = MIXED ? acc[s][0] + cmp[s][0] : acc[s][0];
+                Yt[k * ys + pl + 1] = MIXED ? acc[s][1] + cmp[s][1] : acc[s][1];
+            }
         }
     }
     __syncthreads();
@@ -335,14 +384,25 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
     __syncthreads();  // the LDS tile may be reused by the next tile
 }
 
+// Workgroups are dispatched to the eight XCDs round-robin (workgroup b runs on
+// XCD b mod 8).  This bijection gives each XCD one contiguous range of tiles,
+// so neighbouring tiles -- which share cache lines of Y and wdot -- meet in the
+// same L2.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nblk)
+{
+    constexpr unsigned kXcd = 8;
+    const unsigned x = b % kXcd, q = nblk / kXcd, r = nblk % kXcd;
+    return x * q + min(x, r) + b / kXcd;
+}
+
 template <bool MIXED, int SPL>
-__global__ __launch_bounds__(kWave) void rates_kernel(MechDev m, int64_t n,
+__global__ __launch_bounds__(kWave, SPL == 1 ? 4 : (SPL == 2 ? 3 : 2)) void rates_kernel(MechDev m, int64_t n,
                                                       const double *__restrict__ T,
                                                       const double *__restrict__ P,
                                                       const double *__restrict__ Y,
                                                       double *__restrict__ wdot, int tp)
 {
-    const int64_t i0 = (int64_t)blockIdx.x * tp;
+    const int64_t i0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * tp;
     rates_tile<MIXED, SPL>(m, n, i0, (int)min((int64_t)tp, n - i0), tp, T, P, Y, wdot);
 }
 
@@ -350,7 +410,7 @@ __global__ __launch_bounds__(kWave) void rates_kernel(MechDev m, int64_t n,
 // batch's tiles are exhausted (every workgroup exits once the counter passes
 // the tile count).  Tile t belongs to the last item whose first tile is <= t.
 template <bool MIXED, int SPL>
-__global__ __launch_bounds__(kWave) void rates_batch_kernel(MechDev m,
+__global__ __launch_bounds__(kWave, SPL == 1 ? 4 : (SPL == 2 ? 3 : 2)) void rates_batch_kernel(MechDev m,
                                                             const WorkList *__restrict__ wl,
                                                             int *__restrict__ counter, int tp)
 {
@@ -371,18 +431,21 @@ __global__ __launch_bounds__(kWave) void rates_batch_kernel(MechDev m,
 
 size_t rates_lds_bytes(const MechDev &m, int tp)
 {
-    return sizeof(double) * (2 * (size_t)(m.ns + 1) + (m.chunk + 1) + (size_t)m.ns * (tp + 1));
+    return sizeof(double) * (2 * (size_t)(m.chunk + 1) + 4 * (size_t)(m.ns + 1) +
+                             8 * (size_t)tp + (size_t)m.ns * (tp + 1));
 }
 
 }  // namespace
 
-// Largest tile (16, 8 or 4 points per wave) whose LDS leaves room for at least
-// eight waves per CU (160 KB of LDS).
+// Points per workgroup tile: 8 (64-byte row segments of Y and wdot; tiles that
+// share a 128-byte line run on the same XCD, see xcd_tile), or fewer when the
+// Y tile of a large mechanism would leave room for fewer than eight waves
+// per CU.
 int rates_tile_points(const MechDev &m)
 {
-    for (int cand : {16, 8, 4})
+    for (int cand : {8, 4})
         if (rates_lds_bytes(m, cand) <= 20 * 1024) return cand;
-    return 4;
+    return 2;
 }
 
 namespace {
