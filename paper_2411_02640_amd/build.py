@@ -29,8 +29,12 @@ def hipcc() -> str:
 
 
 def common_flags():
+    # -amdgpu-mfma-vgpr-form: MFMA accumulators stay in ordinary VGPRs (the
+    # accumulation registers would otherwise be copied to and from VGPRs in
+    # every iteration of the transport K-loop)
     return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-mllvm", "-amdgpu-mfma-vgpr-form",
             "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result"]
 
 

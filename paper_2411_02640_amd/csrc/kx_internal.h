@@ -114,6 +114,18 @@ struct MechDev {
     const double *ddiag;       // [ns][order] diagonal fits for the fallback
     // transport (FP32 copies for the mixed path)
     const float *visc32, *cond32, *wq32, *wilke32, *dfit32, *ddiag32;
+    // Matrix-core form of the quadratic transport sums (tables holding fits of
+    // 1/D_kj only; null otherwise).  mblk = ceil(ns / 16) row blocks of 16
+    // species k, kstep = ceil(ns / 4) steps of 4 species j.  Fragments are
+    // stored in the lane order of a 16x16x4 MFMA A operand: lane l holds row
+    // k = 16 mb + l % 16, column j = 4 ks + l / 16, so each is one coalesced
+    // 64-element load.
+    //   gfrag  [fit_order][mblk][kstep][64]: d_kjn, the n-th coefficient of the
+    //          fit of 1/D_kj (zero on the diagonal j = k and in the padding)
+    //   c1frag [mblk][kstep][64]: Wilke c1_kj (zero in the padding)
+    int32_t mblk, kstep;
+    const double *gfrag, *c1frag;
+    const float *gfrag32, *c1frag32;
 };
 
 // Work list of one batch of served requests (device memory, written by the
@@ -163,7 +175,7 @@ kx_status launch_thermo(const kx_mech *m, int64_t n, const double *T, const doub
 // serving work lists are cut in the same tiles as a direct call, so a request
 // gives bit-identical results alone and in a batch).
 int rates_tile_points(const MechDev &m);
-int transport_tile_points(int precision);
+int transport_tile_points(const MechDev &m, int precision);
 // Batched (work-list) launches; `counter` must be zero at launch.
 // prepare_rates_batch sets the kernel's dynamic-LDS limit (call it before
 // capturing a launch into a graph).
@@ -172,5 +184,7 @@ kx_status launch_rates_batch(const MechDev &m, const WorkList *wl, int *counter,
                              int grid, hipStream_t s);
 kx_status launch_transport_batch(const MechDev &m, const WorkList *wl, int *counter,
                                  int precision, int grid, hipStream_t s);
+// Sets the transport batch kernel's dynamic-LDS limit (before graph capture).
+kx_status prepare_transport_batch(const MechDev &m, int precision);
 kx_status launch_zero(int *p, int count, hipStream_t s);
 }  // namespace kx

@@ -345,6 +345,30 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
         return std::vector<float>(v.begin(), v.end());
     };
 
+    // ---- MFMA fragments of the quadratic sums (fits of 1/D_kj only)
+    const int mblk = (ns + 15) / 16, kstep = (ns + 3) / 4;
+    const bool mfma = d->diff_fit_kind == 1;
+    std::vector<double> gfrag, c1frag;
+    if (mfma) {
+        gfrag.assign((size_t)order * mblk * kstep * 64, 0.0);
+        c1frag.assign((size_t)mblk * kstep * 64, 0.0);
+        for (int mb = 0; mb < mblk; ++mb)
+            for (int ks = 0; ks < kstep; ++ks)
+                for (int l = 0; l < 64; ++l) {
+                    const int k = 16 * mb + l % 16, j = 4 * ks + l / 16;
+                    if (k >= ns || j >= ns) continue;
+                    c1frag[((size_t)mb * kstep + ks) * 64 + l] =
+                        1.0 / std::sqrt(8.0 * (1.0 + W[k] / W[j]));
+                    if (j == k) continue;
+                    for (int o = 0; o < order; ++o)
+                        gfrag[(((size_t)o * mblk + mb) * kstep + ks) * 64 + l] =
+                            d->diff_fit[((size_t)k * ns + j) * order + o];
+                }
+    } else {
+        gfrag.resize(1);
+        c1frag.resize(1);
+    }
+
     Blob b;
     const size_t o_rxn = add_vec(b, rx), o_aux = add_vec(b, aux), o_eff = add_vec(b, eff);
     const size_t o_sp = add_vec(b, spv), o_gpos = add_vec(b, gpos), o_gneg = add_vec(b, gneg);
@@ -356,6 +380,8 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     const size_t o_visc32 = add_vec(b, to32(visc)), o_cond32 = add_vec(b, to32(cond));
     const size_t o_wil32 = add_vec(b, to32(wilke)), o_df32 = add_vec(b, to32(dfit));
     const size_t o_dd32 = add_vec(b, to32(ddiag));
+    const size_t o_gf = add_vec(b, gfrag), o_c1f = add_vec(b, c1frag);
+    const size_t o_gf32 = add_vec(b, to32(gfrag)), o_c1f32 = add_vec(b, to32(c1frag));
 
     void *blob = nullptr;
     if (!host_only) {
@@ -421,6 +447,12 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     v.wilke32 = (const float *)at(o_wil32);
     v.dfit32 = (const float *)at(o_df32);
     v.ddiag32 = (const float *)at(o_dd32);
+    v.mblk = mblk;
+    v.kstep = kstep;
+    v.gfrag = mfma ? (const double *)at(o_gf) : nullptr;
+    v.c1frag = mfma ? (const double *)at(o_c1f) : nullptr;
+    v.gfrag32 = mfma ? (const float *)at(o_gf32) : nullptr;
+    v.c1frag32 = mfma ? (const float *)at(o_c1f32) : nullptr;
     *out = m;
     return ok();
 }

@@ -171,6 +171,7 @@ kx_status build_graph(kx_server *s, Slot &sl, const kx_mech *m, int prec, int op
 {
     // kernel attributes are set outside the capture
     kx_status pst = prepare_rates_batch(m->dev, prec);
+    if (pst == KX_OK && (ops & KX_OP_TRANSPORT)) pst = prepare_transport_batch(m->dev, prec);
     if (pst != KX_OK) return pst;
     hipError_t e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
@@ -219,7 +220,7 @@ void launch_batch(kx_server *s, Slot &sl, std::vector<Req *> &batch)
     std::memset(&w, 0, sizeof w);
     w.nitems = (int)batch.size();
     const int tpr = rates_tile_points(m->dev);
-    const int tpt = transport_tile_points(prec);
+    const int tpt = transport_tile_points(m->dev, prec);
     int tr = 0, tt = 0;
     for (size_t r = 0; r < batch.size(); ++r) {
         const Req *q = batch[r];
@@ -256,6 +257,7 @@ void launch_batch(kx_server *s, Slot &sl, std::vector<Req *> &batch)
         } else {
             // direct launches (graph capture unavailable)
             ok_launch = prepare_rates_batch(m->dev, prec) == KX_OK &&
+                        prepare_transport_batch(m->dev, prec) == KX_OK &&
                         launch_zero(sl.d_counter, 2, sl.stream) == KX_OK &&
                         launch_rates_batch(m->dev, sl.d_wl, sl.d_counter, prec, kRatesGrid,
                                            sl.stream) == KX_OK &&

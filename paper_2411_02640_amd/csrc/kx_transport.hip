@@ -49,6 +49,16 @@ __device__ __forceinline__ F horner(const F *__restrict__ c, F u, int order)
     return r;
 }
 
+// The same with per-lane coefficients (vector registers).
+template <int ORDER, class F>
+__device__ __forceinline__ F horner_v(const F *__restrict__ c, F u, int order)
+{
+    const int o = ORDER > 0 ? ORDER : order;
+    F r = c[o - 1];
+    for (int q = o - 2; q >= 0; --q) r = fma(r, u, c[q]);
+    return r;
+}
+
 // Mixture-averaged transport for P points per lane.  F is the arithmetic
 // type of the fits and mixing sums (double: FP64 path; float: mixed path);
 // KIND is the diffusion fit kind (0: D_kj, 1: 1/D_kj); KB species k are held
@@ -239,6 +249,283 @@ __device__ __forceinline__ void transport_tile(const MechDev &m, int64_t n, int6
         if (act[q]) mu[idx[q]] = (double)visc[q];
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core form (tables holding fits of 1/D_kj, the form the paper's
+// generated code evaluates).  With g_kj(u) = 1/D_kj(1 atm) = sum_n d_kjn u^n,
+//     S_k = sum_{j != k} X_j g_kj = sum_n sum_j d_kjn (u^n X_j),
+// a product of the fixed matrix [G_0 | ... | G_{N-1}] (G_n[k][j] = d_kjn, zero
+// diagonal) with the per-point stack (u^n X_j).  The Wilke denominator, with
+// t_kj = 1 + sigma_k rho_j and sigma_k = 1 / rho_k,
+//     sum_j c1_kj X_j t_kj^2 = A_k + 2 sigma_k B_k + sigma_k^2 C_k,
+// needs the products of the fixed matrix c1 with X, X rho and X rho^2 (all
+// terms positive, so the expansion loses nothing).  A workgroup of four waves
+// takes NP points: X and rho go to LDS, each wave runs 16x16x4 MFMAs for its
+// blocks of 16 species k, and the epilogue forms mu, D_km per (k, point).
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <class F> struct Mfma;
+template <> struct Mfma<double> {
+    using V = v4d;
+    static __device__ __forceinline__ V op(double a, double b, V c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // row of the 16x16 result held by lane l in element r
+    static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
+    static __device__ const double *gfrag(const MechDev &m) { return m.gfrag; }
+    static __device__ const double *c1frag(const MechDev &m) { return m.c1frag; }
+};
+template <> struct Mfma<float> {
+    using V = v4f;
+    static __device__ __forceinline__ V op(float a, float b, V c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+    static __device__ const float *gfrag(const MechDev &m) { return m.gfrag32; }
+    static __device__ const float *c1frag(const MechDev &m) { return m.c1frag32; }
+};
+
+constexpr int kMfmaPad = 2;  // LDS row padding of the X / rho tiles (elements)
+
+// Per-point values shared by the phases of a tile.
+struct MfmaPoint {
+    double u, xf, wbar, pr;
+};
+
+template <class F, int NP>
+__host__ __device__ constexpr size_t mfma_lds_bytes_np(int kstep)
+{
+    // X and rho tiles, point table, partial sums (4 per (group, point) in the
+    // prologue, 16 per point for mu)
+    return 2 * (size_t)(4 * kstep) * (NP + kMfmaPad) * sizeof(F) + NP * sizeof(MfmaPoint) +
+           (size_t)((kBlock / NP) * 3 > 16 ? (kBlock / NP) * 3 : 16) * NP * sizeof(double);
+}
+
+template <class F, int NP, int ORDER>
+__device__ __forceinline__ void transport_mfma_tile(const MechDev &m, int64_t n, int64_t base,
+                                                    const double *__restrict__ T,
+                                                    const double *__restrict__ Pp,
+                                                    const double *__restrict__ Y,
+                                                    double *__restrict__ mu,
+                                                    double *__restrict__ lam,
+                                                    double *__restrict__ Dmix)
+{
+    using Tb = Tabs<F>;
+    using MF = Mfma<F>;
+    using V = typename MF::V;
+    constexpr int NB = NP / 16;          // 16-point column blocks
+    constexpr int NG = kBlock / NP;      // species groups of the prologue
+    constexpr int LD = NP + kMfmaPad;    // LDS row stride of the tiles
+    const int ns = m.ns, order = ORDER > 0 ? ORDER : m.fit_order;
+    const int KS = m.kstep, MB = m.mblk, Kp = 4 * KS;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+
+    extern __shared__ double smem_d[];
+    F *Xs = reinterpret_cast<F *>(smem_d);
+    F *Rs = Xs + (size_t)Kp * LD;
+    MfmaPoint *pt = reinterpret_cast<MfmaPoint *>(Rs + (size_t)Kp * LD);
+    double *part = reinterpret_cast<double *>(pt + NP);
+
+    // ---- prologue: thread = (point p, species group g)
+    const int p = t % NP;
+    // with 64-point tiles the species group is the wave: uniform, so the
+    // per-species coefficients below come from scalar loads
+    const int g = NP == 64 ? __builtin_amdgcn_readfirstlane(t / NP) : t / NP;
+    const int64_t ip = min(base + p, n - 1);  // points past n repeat the last one
+    const double Tp = T[ip];
+    const double up = (kln(Tp) - m.fit_L0) * m.inv_fit_h;
+    double s = 0.0;
+    for (int j = g; j < ns; j += NG) s = fma(Y[(int64_t)j * n + ip], m.sp[j].inv_W, s);
+    part[g * NP + p] = s;
+    __syncthreads();
+    double sYW = 0.0;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) sYW += part[q * NP + p];
+    const double xf = krcp(sYW);
+    __syncthreads();  // partials are reused below
+    double wb = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int j = g; j < Kp; j += NG) {
+        if (j < ns) {
+            const double X = Y[(int64_t)j * n + ip] * m.sp[j].inv_W * xf;
+            wb = fma(X, m.W[j], wb);
+            const F lj = NP == 64 ? horner<ORDER>(Tb::cond(m) + j * order, (F)up, order)
+                                  : horner_v<ORDER>(Tb::cond(m) + j * order, (F)up, order);
+            s1 = fma(X, (double)lj, s1);
+            s2 = fma(X, (double)rcp_acc(lj), s2);
+            const F ej = NP == 64 ? horner<ORDER>(Tb::visc(m) + j * order, (F)up, order)
+                                  : horner_v<ORDER>(Tb::visc(m) + j * order, (F)up, order);
+            Xs[(size_t)j * LD + p] = (F)X;
+            Rs[(size_t)j * LD + p] = Tb::wq(m)[j] * rsqrt_acc(ej);  // rho_j
+        } else {
+            Xs[(size_t)j * LD + p] = (F)0;
+            Rs[(size_t)j * LD + p] = (F)1;
+        }
+    }
+    part[(g * 3 + 0) * NP + p] = wb;
+    part[(g * 3 + 1) * NP + p] = s1;
+    part[(g * 3 + 2) * NP + p] = s2;
+    __syncthreads();
+    if (t < NP) {
+        double W = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            W += part[(q * 3 + 0) * NP + p];
+            a1 += part[(q * 3 + 1) * NP + p];
+            a2 += part[(q * 3 + 2) * NP + p];
+        }
+        MfmaPoint P;
+        P.u = up;
+        P.xf = xf;
+        P.wbar = W;
+        P.pr = Pp[ip] * (1.0 / kPatm);
+        pt[p] = P;
+        if (base + p < n) lam[base + p] = 0.5 * (a1 + krcp(a2));  // Mathur
+    }
+    __syncthreads();
+
+    // ---- products on the matrix cores: wave w takes row blocks w, w + 4, ...
+    const int col = lane & 15, jr = lane >> 4;
+    F uc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) uc[nb] = (F)pt[16 * nb + col].u;
+    double mup[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) mup[nb] = 0.0;
+    const F *gf = MF::gfrag(m), *cf = MF::c1frag(m);
+    constexpr int MO = ORDER > 0 ? ORDER : kMaxFitOrder;  // A fragments per K-step
+    const size_t ostride = (size_t)MB * KS * 64;           // between fit orders
+    for (int mb = w; mb < MB; mb += 4) {
+        V S[NB], A[NB], B[NB], C[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) S[nb] = A[nb] = B[nb] = C[nb] = V{0, 0, 0, 0};
+        // A fragments of the next K-step are in flight during this one
+        const F *cfb = cf + (size_t)mb * KS * 64 + lane;
+        const F *gfb = gf + (size_t)mb * KS * 64 + lane;
+        F a1n = cfb[0], ggn[MO];
+#pragma unroll
+        for (int o = 0; o < MO; ++o)
+            if (o < order) ggn[o] = gfb[o * ostride];
+        for (int ks = 0; ks < KS; ++ks) {
+            const F a1 = a1n;
+            F gg[MO];
+#pragma unroll
+            for (int o = 0; o < MO; ++o) gg[o] = ggn[o];
+            if (ks + 1 < KS) {
+                a1n = cfb[(ks + 1) * 64];
+#pragma unroll
+                for (int o = 0; o < MO; ++o)
+                    if (o < order) ggn[o] = gfb[o * ostride + (ks + 1) * 64];
+            }
+            const int j = 4 * ks + jr;
+            F x[NB], r[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                x[nb] = Xs[(size_t)j * LD + 16 * nb + col];
+                r[nb] = Rs[(size_t)j * LD + 16 * nb + col];
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const F xr = x[nb] * r[nb];
+                A[nb] = MF::op(a1, x[nb], A[nb]);
+                B[nb] = MF::op(a1, xr, B[nb]);
+                C[nb] = MF::op(a1, xr * r[nb], C[nb]);
+            }
+            F bb[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) bb[nb] = x[nb];
+#pragma unroll
+            for (int o = 0; o < MO; ++o) {
+                if (o < order) {
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        S[nb] = MF::op(gg[o], bb[nb], S[nb]);
+                        bb[nb] *= uc[nb];
+                    }
+                }
+            }
+        }
+        // ---- epilogue of this row block: element r of lane l is (k, point)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int pp = 16 * nb + col;
+            const int64_t i = base + pp;
+            const MfmaPoint P = pt[pp];
+            const int64_t ic = min(i, n - 1);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = 16 * mb + MF::row(lane, e);
+                if (k >= ns) continue;
+                const F rho = Rs[(size_t)k * LD + pp];
+                const F sig = rcp_acc(rho);
+                const F wsig = Tb::wq(m)[k] * sig;  // sqrt(eta_k)
+                const F den = A[nb][e] + sig * ((F)2 * B[nb][e] + sig * C[nb][e]);
+                // X_k in FP64 for the D_km numerator (W-bar - X_k W_k) / W-bar (the
+                // FP64 tile holds it already; the mixed path recomputes it)
+                const double Xk = std::is_same<F, double>::value
+                                      ? (double)Xs[(size_t)k * LD + pp]
+                                      : Y[(int64_t)k * n + ic] * m.sp[k].inv_W * P.xf;
+                mup[nb] = fma(Xk, (double)(wsig * wsig * rcp_acc(den)), mup[nb]);
+                double D;
+                if (S[nb][e] == (F)0) {
+                    // no other species present: D_km -> D_kk
+                    const F gk = horner_v<ORDER>(Tb::ddiag(m) + k * order, (F)P.u, order);
+                    D = 1.0 / ((double)gk * P.pr);
+                } else {
+                    D = (P.wbar - Xk * m.W[k]) / (P.wbar * (double)S[nb][e] * P.pr);
+                }
+                if (i < n) Dmix[(int64_t)k * n + i] = D;
+            }
+        }
+    }
+    // mu: 16 partial sums per point (4 waves x 4 row groups), fixed order
+    __syncthreads();
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) part[(w * 4 + jr) * NP + 16 * nb + col] = mup[nb];
+    __syncthreads();
+    if (t < NP && base + t < n) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v += part[q * NP + t];
+        mu[base + t] = v;
+    }
+    __syncthreads();  // LDS reused by the next tile
+}
+
+template <class F, int NP, int ORDER>
+__global__ __launch_bounds__(kBlock) void transport_mfma_kernel(MechDev m, int64_t n,
+                                                                const double *__restrict__ T,
+                                                                const double *__restrict__ Pp,
+                                                                const double *__restrict__ Y,
+                                                                double *__restrict__ mu,
+                                                                double *__restrict__ lam,
+                                                                double *__restrict__ Dmix)
+{
+    transport_mfma_tile<F, NP, ORDER>(m, n, (int64_t)blockIdx.x * NP, T, Pp, Y, mu, lam, Dmix);
+}
+
+template <class F, int NP, int ORDER>
+__global__ __launch_bounds__(kBlock) void transport_mfma_batch_kernel(
+    MechDev m, const WorkList *__restrict__ wl, int *__restrict__ counter)
+{
+    __shared__ int tile;
+    const int ntiles = wl->ntiles[1];
+    for (;;) {
+        if (threadIdx.x == 0) tile = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = tile;
+        __syncthreads();
+        if (t >= ntiles) break;
+        int r = 0;
+        while (r + 1 < wl->nitems && wl->start[1][r + 1] <= t) ++r;
+        const WorkItem it = wl->items[r];
+        transport_mfma_tile<F, NP, ORDER>(m, it.n, (int64_t)(t - wl->start[1][r]) * NP, it.T,
+                                          it.p, it.Y, it.mu, it.lam, it.Dmix);
+    }
+}
+
 template <class F, int ORDER, int KIND, int P, int KB>
 __global__ __launch_bounds__(kBlock) void transport_kernel(MechDev m, int64_t n,
                                                            const double *__restrict__ T,
@@ -324,11 +611,68 @@ template <> struct TransportShape<float> {
     static constexpr int P = 2, KB = 8;
 };
 
+// Points per matrix-core tile: the largest of 64, 32, 16 whose LDS (X and rho
+// tiles) stays within 80 KB, i.e. two workgroups per CU.
+template <class F> int mfma_np(const MechDev &m)
+{
+    if (mfma_lds_bytes_np<F, 64>(m.kstep) <= 80 * 1024) return 64;
+    if (mfma_lds_bytes_np<F, 32>(m.kstep) <= 80 * 1024) return 32;
+    return 16;
+}
+
+template <class F> size_t mfma_lds(const MechDev &m, int np)
+{
+    return np == 64 ? mfma_lds_bytes_np<F, 64>(m.kstep)
+                    : (np == 32 ? mfma_lds_bytes_np<F, 32>(m.kstep)
+                                : mfma_lds_bytes_np<F, 16>(m.kstep));
+}
+
+// Below about two dozen species the padded 16 x 4 MFMA tiles are mostly empty
+// and the vector-ALU kernel is faster.
+constexpr int kMfmaMinSpecies = 24;
+bool use_mfma(const MechDev &m)
+{
+    return m.diff_kind == 1 && m.gfrag != nullptr && m.ns >= kMfmaMinSpecies;
+}
+
+template <class F, bool BATCH> const void *mfma_kernel(const MechDev &m, int np)
+{
+    const bool o5 = m.fit_order == 5;
+#define KX_PICK(NPV)                                                                        \
+    (BATCH ? (o5 ? (const void *)transport_mfma_batch_kernel<F, NPV, 5>                     \
+                 : (const void *)transport_mfma_batch_kernel<F, NPV, 0>)                    \
+           : (o5 ? (const void *)transport_mfma_kernel<F, NPV, 5>                           \
+                 : (const void *)transport_mfma_kernel<F, NPV, 0>))
+    return np == 64 ? KX_PICK(64) : (np == 32 ? KX_PICK(32) : KX_PICK(16));
+#undef KX_PICK
+}
+
+template <class F, bool BATCH> kx_status mfma_prepare(const MechDev &m, size_t *lds)
+{
+    const int np = mfma_np<F>(m);
+    *lds = mfma_lds<F>(m, np);
+    if (*lds > 160 * 1024)
+        return fail(KX_EUNSUPPORTED, "transport: mechanism too large for the LDS tiles");
+    hipError_t e = hipFuncSetAttribute(mfma_kernel<F, BATCH>(m, np),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)*lds);
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute (transport)");
+    return KX_OK;
+}
+
 }  // namespace
 
-int transport_tile_points(int precision)
+int transport_tile_points(const MechDev &m, int precision)
 {
+    if (use_mfma(m)) return precision == KX_MIXED ? mfma_np<float>(m) : mfma_np<double>(m);
     return kBlock * (precision == KX_MIXED ? TransportShape<float>::P : TransportShape<double>::P);
+}
+
+kx_status prepare_transport_batch(const MechDev &m, int precision)
+{
+    if (!use_mfma(m)) return KX_OK;
+    size_t lds = 0;
+    return precision == KX_MIXED ? mfma_prepare<float, true>(m, &lds)
+                                 : mfma_prepare<double, true>(m, &lds);
 }
 
 namespace {
@@ -336,6 +680,20 @@ template <class F>
 kx_status go_transport(const MechDev &m, int64_t n, const double *T, const double *p,
                        const double *Y, double *mu, double *lam, double *Dmix, hipStream_t s)
 {
+    if (use_mfma(m)) {
+        size_t lds = 0;
+        kx_status st = mfma_prepare<F, false>(m, &lds);
+        if (st != KX_OK) return st;
+        const int np = mfma_np<F>(m);
+        const int64_t nblk = (n + np - 1) / np;
+        if (nblk > 0x7fffffff) return fail(KX_EINVAL, "transport: n too large");
+        void *args[] = {(void *)&m, (void *)&n, (void *)&T, (void *)&p, (void *)&Y,
+                        (void *)&mu, (void *)&lam, (void *)&Dmix};
+        hipError_t e = hipLaunchKernel(mfma_kernel<F, false>(m, np), dim3((unsigned)nblk),
+                                       dim3(kBlock), args, lds, s);
+        if (e != hipSuccess) return hip_fail(e, "transport kernel launch");
+        return ok();
+    }
     constexpr int PP = TransportShape<F>::P, KB = TransportShape<F>::KB;
     const int64_t per = (int64_t)kBlock * PP;
     const int64_t nblk = (n + per - 1) / per;
@@ -355,6 +713,15 @@ template <class F>
 kx_status go_transport_batch(const MechDev &m, const WorkList *wl, int *counter, int grid,
                              hipStream_t s)
 {
+    if (use_mfma(m)) {
+        const int np = mfma_np<F>(m);
+        const size_t lds = mfma_lds<F>(m, np);
+        void *args[] = {(void *)&m, (void *)&wl, (void *)&counter};
+        hipError_t e = hipLaunchKernel(mfma_kernel<F, true>(m, np), dim3(grid), dim3(kBlock),
+                                       args, lds, s);
+        if (e != hipSuccess) return hip_fail(e, "transport batch kernel launch");
+        return ok();
+    }
     constexpr int PP = TransportShape<F>::P, KB = TransportShape<F>::KB;
     const bool o5 = m.fit_order == 5;
     auto k = m.diff_kind == 0 ? (o5 ? transport_batch_kernel<F, 5, 0, PP, KB>

@@ -309,7 +309,9 @@ class MechSpec:
     n_troe: int
     seed: int
     special_cases: bool = False
-    diff_fit_kind: int = 0
+    # 1: tables hold fits of 1/D_kj, the polynomial the paper's generated
+    # routines evaluate directly; 0: fits of D_kj itself (eq:Dkj)
+    diff_fit_kind: int = 1
     name: str = ""
     extra: dict = field(default_factory=dict)
 

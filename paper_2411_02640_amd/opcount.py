@@ -95,11 +95,16 @@ def transport_ops(mech: dict) -> dict:
     c["fma"] += 2 * ns
     c["div"] += ns
     c["fma"] += ns
-    # D_kj fits for k != j (full matrix), 1/D, accumulation, D_km
+    # fits for k != j (full matrix) and the accumulation of X_j / D_kj: with
+    # fits of 1/D_kj (kind 1, the paper's form) the fit value multiplies X_j
+    # directly; with fits of D_kj (kind 0) a division per pair is needed
     npair = ns * (ns - 1)
     c["fma"] += npair * (order - 1)
-    c["div"] += npair
-    c["add"] += npair
+    if int(mech.get("diff_fit_kind", 0)) == 1:
+        c["fma"] += npair
+    else:
+        c["div"] += npair
+        c["add"] += npair
     c["div"] += 2 * ns
     c["fma"] += 2 * ns
     c["mul"] += ns

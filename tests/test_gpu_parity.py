@@ -151,12 +151,20 @@ def test_special_case_mechanism(kx):
     check_rates(kx, m, T, p, Y, "special cases")
 
 
-def test_diffusion_fit_kind_inverse(kx):
-    """Tables holding fits of 1/D_kj (diff_fit_kind = 1)."""
-    spec = I.MechSpec(53, 266, 30, 0, 29, seed=53325, diff_fit_kind=1, name="syn53inv")
+def test_diffusion_fit_kind_direct(kx):
+    """Tables holding fits of D_kj itself (diff_fit_kind = 0): the vector-ALU
+    transport kernel with a reciprocal per pair, FP64 and mixed."""
+    spec = I.MechSpec(53, 266, 30, 0, 29, seed=53325, diff_fit_kind=0, name="syn53d")
     m = I.make_mechanism(spec)
-    T, p, Y = I.make_states(53, I.STATES_53, n_points=4096)
-    check_transport(kx, m, T, p, Y, "1/D fits")
+    T, p, Y = I.make_states(53, I.STATES_53, n_points=4133)
+    check_transport(kx, m, T, p, Y, "D fits")
+    dm = dev_mech(kx, m)
+    mu, lam, Dm = run_transport(kx, dm, T, p, Y, precision="mixed")
+    rmu, rlam, rDm = O.OracleMech(m).transport(T, p, Y)
+    for name, g, r in (("mu", mu, rmu), ("lambda", lam, rlam), ("Dmix", Dm, rDm)):
+        rep = PM.rel_report(g, r, PM.REL_MIXED)
+        _say("  mixed", name, rep)
+        assert rep["ok"], (name, rep)
 
 
 def test_near_equilibrium_states_fp64(kx, mech53):
