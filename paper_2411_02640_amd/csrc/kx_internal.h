@@ -100,7 +100,7 @@ struct MechDev {
     const int32_t *gpos;       // [nchunks] groups of eight +q entries of the gather
     const int32_t *gneg;       // [nchunks] groups of eight -q entries
     const int32_t *goff;       // [nchunks] first group of each chunk
-    const uint4 *gent;         // [group][64 * gpass]: eight 16-bit LDS byte offsets
+    const uint4 *gent;         // [group][64 * gpass][2]: eight 32-bit LDS byte offsets
                                // 16 * slot_in_chunk per lane and group (a species with
                                // |nu''-nu'| = 2 or 3 lists the slot that many times);
                                // padding entries read the zero slot after the chunk

@@ -237,9 +237,9 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     // the chunk slots of the reactions that produce it (+q, once per unit of
     // net nu) and of those that consume it (-q); both lists are padded to a
     // whole number of eight-entry groups common to all lanes, and a group is
-    // eight 16-bit LDS offsets (16 bytes per lane, so lane k reads it with one
-    // coalesced 16-byte load).  The rates of progress of two points sit side by
-    // side in LDS, so one offset addresses both.
+    // eight 32-bit LDS offsets (32 bytes per lane, so lane k reads it with a
+    // pair of coalesced 16-byte loads).  The rates of progress of two points sit
+    // side by side in LDS, so one offset addresses both.
     const int chunk = std::max(kWave, std::min(192, (nr + kWave - 1) / kWave * kWave));
     const int nchunks = std::max(1, (nr + chunk - 1) / chunk);
     // species per lane of the species phases: 1, 2 or 4 (the kernels are
@@ -247,10 +247,10 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     const int gpass = ns <= kWave ? 1 : (ns <= 2 * kWave ? 2 : 4);
     const int gw = kWave * gpass;
     std::vector<int32_t> gpos(nchunks), gneg(nchunks), goff(nchunks);
-    std::vector<uint16_t> gent;  // 8 per (group, lane)
+    std::vector<uint32_t> gent;  // 8 per (group, lane)
     size_t ngroups = 0;
     for (int c = 0; c < nchunks; ++c) {
-        std::vector<std::vector<uint16_t>> pos(gw), neg(gw);
+        std::vector<std::vector<uint32_t>> pos(gw), neg(gw);
         for (int s = c * chunk; s < std::min(nr, (c + 1) * chunk); ++s) {
             const int i = perm[s];
             std::vector<std::pair<int, int>> net;  // (species, nu'' - nu')
@@ -263,7 +263,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
                 addnu(d->reac_sp[e], -d->reac_nu[e]);
             for (int e = d->prod_ptr[i]; e < d->prod_ptr[i + 1]; ++e)
                 addnu(d->prod_sp[e], d->prod_nu[e]);
-            const uint16_t slot = (uint16_t)(16 * (s - c * chunk));
+            const uint32_t slot = (uint32_t)(16 * (s - c * chunk));
             for (auto &pr : net)
                 for (int u = 0; u < std::abs(pr.second); ++u)
                     (pr.second > 0 ? pos : neg)[pr.first].push_back(slot);
@@ -276,7 +276,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
         gpos[c] = (int32_t)((lp + 7) / 8);
         gneg[c] = (int32_t)((ln + 7) / 8);
         goff[c] = (int32_t)ngroups;
-        const uint16_t pad = (uint16_t)(16 * chunk);  // the zero slot
+        const uint32_t pad = (uint32_t)(16 * chunk);  // the zero slot
         for (int side = 0; side < 2; ++side) {
             const auto &lists = side ? neg : pos;
             const int groups = side ? gneg[c] : gpos[c];

@@ -156,15 +156,26 @@ __device__ __forceinline__ double rate_of_progress(const MechDev &m, const RxnWo
     const unsigned aux = w.w2.w >> 16;
 
     // exponent of k_f (eq:k_f); k_f = A without an exponential when beta = E_R = 0
-    const double xf = (flags & kFlagKfConst) ? lnA : fma(beta, lnT, fma(-ER, invT, lnA));
-    const double kf = (flags & kFlagKfConst) ? A : (MIXED ? exp_mixed(xf) : kexp(xf));
+    // (such reactions are sorted together, so the branch is mostly wave-uniform)
+    const bool kconst = (flags & kFlagKfConst) != 0;
+    const double xf = kconst ? lnA : fma(beta, lnT, fma(-ER, invT, lnA));
+    double kf = A;
+    if (!kconst) kf = MIXED ? exp_mixed(xf) : kexp(xf);
     const Pair r0 = load_pair(pb, w.w2.x & 0xFFFFu);
     const Pair r1 = load_pair(pb, w.w2.x >> 16);
-    const Pair r2 = load_pair(pb, w.w2.y & 0xFFFFu);
-    const double Ap = r0.a * r1.a * r2.a;
-    const double Bp = r0.b * r1.b * r2.b;
-    const double Bpp = load_b(pb, w.w2.y >> 16) * load_b(pb, w.w2.z & 0xFFFFu) *
-                       load_b(pb, w.w2.z >> 16);
+    double Ap = r0.a * r1.a;
+    double Bp = r0.b * r1.b;
+    double Bpp = load_b(pb, w.w2.y >> 16) * load_b(pb, w.w2.z & 0xFFFFu);
+    // third molecule slots: skipped by the whole wave when none of its
+    // reactions has three molecules on a side (the dummy species gives 1)
+    const unsigned o2 = w.w2.y & 0xFFFFu, o5 = w.w2.z >> 16;
+    const unsigned dummy = 16u * (unsigned)m.ns;
+    if (__builtin_amdgcn_ballot_w64(o2 != dummy || o5 != dummy) != 0) {
+        const Pair r2 = load_pair(pb, o2);
+        Ap *= r2.a;
+        Bp *= r2.b;
+        Bpp *= load_b(pb, o5);
+    }
     double c = 1.0;
     if (type != KX_RXN_ELEMENTARY) {
         const DevAux &ax = m.aux[aux];
@@ -212,6 +223,11 @@ __device__ __forceinline__ void accumulate(double &acc, double &cmp, double t)
     }
 }
 
+// Points per workgroup tile: 8 (64-byte row segments of Y and wdot; tiles that
+// share a 128-byte line run on the same XCD, see xcd_tile); 2 for mechanisms
+// of more than 128 species, whose Y tile would otherwise crowd the LDS.
+__host__ __device__ constexpr int rates_tile_points_for(int spl) { return spl == 4 ? 2 : 8; }
+
 // Per-point constants of a tile, computed once per point (lane = point).
 struct PointConst {
     double T, lnT, invT, M;  // temperature, ln T, 1/T, [M] = p / RT
@@ -243,29 +259,39 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
                                            double *__restrict__ wdot)
 {
     extern __shared__ double lds[];
+    constexpr int TP = rates_tile_points_for(SPL);  // == tp
+    constexpr int NGW = kWave / TP;                 // species groups of the W-bar pass
     const int ns = m.ns;
-    const int ys = tp + 1;
+    const int ys = TP + 1;
     const int lane = threadIdx.x;
     double *sq = lds;
     double *pairs = sq + 2 * (m.chunk + 1);
     PointConst *pc = reinterpret_cast<PointConst *>(pairs + 4 * (ns + 1));
-    double *Yt = reinterpret_cast<double *>(pc + tp);
+    double *Yt = reinterpret_cast<double *>(pc + TP);
     const char *qb = reinterpret_cast<const char *>(sq);
+    (void)tp;
 
-    for (int e = lane; e < ns * tp; e += kWave) {
-        const int k = e / tp, c = e - k * tp;
+    for (int e = lane; e < ns * TP; e += kWave) {
+        const int k = e / TP, c = e % TP;
         Yt[k * ys + c] = (c < npts) ? Y[(int64_t)k * ld + i0 + c] : 0.0;
     }
-    if (lane < 2) {
-        pairs[2 * ns + 2 * (ns + 1) * lane] = 1.0;
-        pairs[2 * ns + 2 * (ns + 1) * lane + 1] = 1.0;
-        sq[2 * m.chunk + lane] = 0.0;
+    __syncthreads();
+    {
+        // sum_k Y_k / W_k = 1 / W-bar: lane = (point, species group); the
+        // group partials meet in the (still unused) rate-of-progress array
+        const int c = lane % TP, g = lane / TP;
+        const int cc = min(c, npts - 1);  // padding points repeat the last one
+        double part = 0.0;
+        for (int k = g; k < ns; k += NGW) part = fma(Yt[k * ys + cc], m.sp[k].inv_W, part);
+        sq[g * TP + c] = part;
     }
     __syncthreads();
-    if (lane < tp) {
-        // lane = point; the padding points of a partial tile repeat its last one
+    if (lane < TP) {
         const int c = min(lane, npts - 1);
         const int64_t i = i0 + c;
+        double wsum = 0.0;
+#pragma unroll
+        for (int g = 0; g < NGW; ++g) wsum += sq[g * TP + lane];
         PointConst q;
         q.T = T[i];
         q.lnT = kln(q.T);
@@ -273,13 +299,16 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
         const double invRT = krcp(kRu * q.T);
         q.M = P[i] * invRT;
         q.P0 = kPatm * invRT;
-        double wsum = 0.0;  // sum_k Y_k / W_k = 1 / W-bar
-        for (int k = 0; k < ns; ++k) wsum = fma(Yt[k * ys + c], m.sp[k].inv_W, wsum);
         q.cf = q.M * krcp(wsum);
         q.pad[0] = q.pad[1] = 0.0;
         pc[lane] = q;
     }
     __syncthreads();
+    if (lane < 2) {
+        pairs[2 * ns + 2 * (ns + 1) * lane] = 1.0;
+        pairs[2 * ns + 2 * (ns + 1) * lane + 1] = 1.0;
+        sq[2 * m.chunk + lane] = 0.0;
+    }
 
     const int jl = lane & 1;   // point of this lane in phase 2
     const int rl = lane >> 1;  // reaction slot of this lane in phase 2
@@ -338,16 +367,22 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
             }
             wave_sync();
             const int npos = m.gpos[c], ngrp = npos + m.gneg[c];
-            const uint4 *ge = m.gent + (size_t)m.goff[c] * gw + lane;
+            const uint4 *ge = m.gent + ((size_t)m.goff[c] * gw + lane) * 2;
 #pragma unroll
             for (int s = 0; s < SPL; ++s) {
-                const uint4 *g = ge + kWave * s;
-                uint4 nxt = ngrp > 0 ? g[0] : make_uint4(0, 0, 0, 0);
+                const uint4 *g = ge + 2 * kWave * s;
+                uint4 nx0 = make_uint4(0, 0, 0, 0), nx1 = nx0;
+                if (ngrp > 0) {
+                    nx0 = g[0];
+                    nx1 = g[1];
+                }
                 for (int it = 0; it < ngrp; ++it) {
-                    const uint4 v = nxt;
-                    if (it + 1 < ngrp) nxt = g[(size_t)(it + 1) * gw];
-                    const unsigned off[8] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16,
-                                             v.z & 0xFFFFu, v.z >> 16, v.w & 0xFFFFu, v.w >> 16};
+                    const uint4 v0 = nx0, v1 = nx1;
+                    if (it + 1 < ngrp) {
+                        nx0 = g[(size_t)(it + 1) * 2 * gw];
+                        nx1 = g[(size_t)(it + 1) * 2 * gw + 1];
+                    }
+                    const unsigned off[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
                     // the eight entries of a group are summed plainly; the
                     // mixed path compensates the running sum across groups
                     double g0 = 0.0, g1 = 0.0;
@@ -377,8 +412,8 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
         }
     }
     __syncthreads();
-    for (int e = lane; e < ns * tp; e += kWave) {
-        const int k = e / tp, c = e - k * tp;
+    for (int e = lane; e < ns * TP; e += kWave) {
+        const int k = e / TP, c = e % TP;
         if (c < npts) wdot[(int64_t)k * ld + i0 + c] = Yt[k * ys + c];
     }
     __syncthreads();  // the LDS tile may be reused by the next tile
@@ -437,16 +472,7 @@ size_t rates_lds_bytes(const MechDev &m, int tp)
 
 }  // namespace
 
-// Points per workgroup tile: 8 (64-byte row segments of Y and wdot; tiles that
-// share a 128-byte line run on the same XCD, see xcd_tile), or fewer when the
-// Y tile of a large mechanism would leave room for fewer than eight waves
-// per CU.
-int rates_tile_points(const MechDev &m)
-{
-    for (int cand : {8, 4})
-        if (rates_lds_bytes(m, cand) <= 20 * 1024) return cand;
-    return 2;
-}
+int rates_tile_points(const MechDev &m) { return rates_tile_points_for(m.gpass); }
 
 namespace {
 template <class K>
