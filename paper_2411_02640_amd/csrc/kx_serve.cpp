@@ -35,7 +35,7 @@ namespace kx {
 namespace {
 
 constexpr int kStreams = 4;
-constexpr int kRatesGrid = 2048;      // one-wave workgroups of the rates batch kernel
+constexpr int kRatesGrid = 4096;      // one-wave workgroups of the rates batch kernel (16 per CU)
 constexpr int kTransportGrid = 1024;  // 256-lane workgroups of the transport batch kernel
 constexpr double kSimSecondsPerPoint = 5e-9;
 

@@ -279,3 +279,44 @@ def test_mixed_precision_error_report(kx, mech53):
             rep = PM.rel_report(g, rr, PM.REL_MIXED)
             _say("  ", name, part, rep)
             assert rep["ok"], (name, part, rep)
+
+
+def test_mixed_full_size_sampled(kx, mech53):
+    """The mixed-precision workload at its full size (2^22 points, a quarter of
+    them within 1e-6 of constructed equilibrium states -- 4096 distinct ones,
+    each used 256 times), both kernels in the benchmark's launch
+    configuration; the oracle checks a sample split into bulk and
+    near-equilibrium points."""
+    n = I.STATES_53_MIXED.n_points
+    nq = n // 4
+    om = O.OracleMech(mech53)
+    T1, p1, Y1 = I.make_states(53, I.STATES_53_MIXED, n_points=n - nq)
+    Te, pe, Ye = O.equilibrium_states(om, 1 << 12, seed=1003, perturb=1e-6)
+    reps = nq // Te.size
+    T = np.concatenate([T1, np.tile(Te, reps)])
+    p = np.concatenate([p1, np.tile(pe, reps)])
+    Y = np.ascontiguousarray(np.concatenate([Y1, np.tile(Ye, (1, reps))], axis=1))
+    del Y1
+    near = np.zeros(n, bool)
+    near[n - nq:] = True
+    _say("mixed full size n =", n)
+    dm = dev_mech(kx, mech53)
+    w = run_rates(kx, dm, T, p, Y, precision="mixed")
+    mu, lam, Dm = run_transport(kx, dm, T, p, Y, precision="mixed")
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([rng.choice(n - nq, 1000, replace=False),
+                                    n - nq + rng.choice(nq, 1000, replace=False),
+                                    [0, 7, 8, 63, 64, n - nq - 1, n - nq, n - 1]]))
+    Ts, ps, Ys = T[idx], p[idx], np.ascontiguousarray(Y[:, idx])
+    ref, sc = om.production_rates(Ts, ps, Ys)
+    rmu, rlam, rDm = om.transport(Ts, ps, Ys)
+    sel_near = near[idx]
+    for part, sel in (("bulk", ~sel_near), ("near-equilibrium", sel_near)):
+        r = PM.mixed_wdot_report(w[:, idx][:, sel], ref[:, sel], sc[:, sel])
+        _say("  wdot", part, r)
+        assert r["ok"], (part, r)
+        for name, g, rr in (("mu", mu[idx][sel], rmu[sel]), ("lambda", lam[idx][sel], rlam[sel]),
+                            ("Dmix", Dm[:, idx][:, sel], rDm[:, sel])):
+            rep = PM.rel_report(g, rr, PM.REL_MIXED)
+            _say("  ", name, part, rep)
+            assert rep["ok"], (name, part, rep)
