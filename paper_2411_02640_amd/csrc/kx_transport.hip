@@ -337,8 +337,24 @@ __device__ __forceinline__ void transport_mfma_tile(const MechDev &m, int64_t n,
     const int64_t ip = min(base + p, n - 1);  // points past n repeat the last one
     const double Tp = T[ip];
     const double up = (kln(Tp) - m.fit_L0) * m.inv_fit_h;
+    // every Y load of this thread is issued before the first is used (a
+    // thread covers at most kJmax species: ns <= 4 NP for the chosen NP)
+    constexpr int kJmax = 16;
+    double yw[kJmax];
+#pragma unroll
+    for (int q = 0; q < kJmax; ++q) {
+        const int j = g + NG * q;
+        yw[q] = j < ns ? Y[(int64_t)j * n + ip] : 0.0;
+    }
     double s = 0.0;
-    for (int j = g; j < ns; j += NG) s = fma(Y[(int64_t)j * n + ip], m.sp[j].inv_W, s);
+#pragma unroll
+    for (int q = 0; q < kJmax; ++q) {
+        const int j = g + NG * q;
+        if (j < ns) {
+            yw[q] *= m.sp[j].inv_W;  // Y_j / W_j
+            s += yw[q];
+        }
+    }
     part[g * NP + p] = s;
     __syncthreads();
     double sYW = 0.0;
@@ -347,9 +363,12 @@ __device__ __forceinline__ void transport_mfma_tile(const MechDev &m, int64_t n,
     const double xf = krcp(sYW);
     __syncthreads();  // partials are reused below
     double wb = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int j = g; j < Kp; j += NG) {
+#pragma unroll
+    for (int q = 0; q < kJmax; ++q) {
+        const int j = g + NG * q;
+        if (j >= Kp) break;
         if (j < ns) {
-            const double X = Y[(int64_t)j * n + ip] * m.sp[j].inv_W * xf;
+            const double X = yw[q] * xf;  // FP64 X_j for W-bar and the Mathur sums
             wb = fma(X, m.W[j], wb);
             const F lj = NP == 64 ? horner<ORDER>(Tb::cond(m) + j * order, (F)up, order)
                                   : horner_v<ORDER>(Tb::cond(m) + j * order, (F)up, order);
@@ -474,7 +493,7 @@ __device__ __forceinline__ void transport_mfma_tile(const MechDev &m, int64_t n,
                     const F gk = horner_v<ORDER>(Tb::ddiag(m) + k * order, (F)P.u, order);
                     D = 1.0 / ((double)gk * P.pr);
                 } else {
-                    D = (P.wbar - Xk * m.W[k]) / (P.wbar * (double)S[nb][e] * P.pr);
+                    D = (P.wbar - Xk * m.W[k]) * krcp(P.wbar * (double)S[nb][e] * P.pr);
                 }
                 if (i < n) Dmix[(int64_t)k * n + i] = D;
             }
@@ -613,10 +632,13 @@ template <> struct TransportShape<float> {
 
 // Points per matrix-core tile: the largest of 64, 32, 16 whose LDS (X and rho
 // tiles) stays within 80 KB, i.e. two workgroups per CU.
+// The prologue gives each thread at most 16 species (256 / NP groups), so NP
+// also bounds the species count: NP = 64 up to 64 species, 32 up to 128.
 template <class F> int mfma_np(const MechDev &m)
 {
-    if (mfma_lds_bytes_np<F, 64>(m.kstep) <= 80 * 1024) return 64;
-    if (mfma_lds_bytes_np<F, 32>(m.kstep) <= 80 * 1024) return 32;
+    const int kp = 4 * m.kstep;
+    if (kp <= 64 && mfma_lds_bytes_np<F, 64>(m.kstep) <= 80 * 1024) return 64;
+    if (kp <= 128 && mfma_lds_bytes_np<F, 32>(m.kstep) <= 80 * 1024) return 32;
     return 16;
 }
 
