@@ -95,21 +95,25 @@ def time_path(kx, dm, Td, pd, Yd, outs, steps, warmup, precision):
         ev[k][2].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    rates_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
-    trans_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
-    return wall, rates_ms, trans_ms
+    r = sorted(e[0].elapsed_time(e[1]) for e in ev)
+    t = sorted(e[1].elapsed_time(e[2]) for e in ev)
+    time_path.medians = (r[len(r) // 2], t[len(t) // 2])
+    return wall, sum(r) / steps, sum(t) / steps
 
 
-def cpu_baseline(mech, T, p, Y, target_s=12.0):
-    """The oracle as it stands, on a bounded sample of the same states."""
+def cpu_baseline(mech, T, p, Y, target_s=12.0, single_s=3.0):
+    """The oracle as it stands, on a bounded sample of the same states, on all
+    host threads and on one.  Returns the baseline and the oracle's outputs on
+    the first 4096 points (for the error report)."""
     import numpy as np
     from oracle import oracle as O
     om = O.OracleMech(mech)
     threads = O.max_threads()
-    n0 = 2048
+    n0 = 4096
+    Y0 = np.ascontiguousarray(Y[:, :n0])
     t0 = time.perf_counter()
-    om.production_rates(T[:n0], p[:n0], np.ascontiguousarray(Y[:, :n0]), with_scale=False)
-    om.transport(T[:n0], p[:n0], np.ascontiguousarray(Y[:, :n0]))
+    ref_w, ref_s = om.production_rates(T[:n0], p[:n0], Y0)
+    ref_t = om.transport(T[:n0], p[:n0], Y0)
     est = (time.perf_counter() - t0) / n0
     n = int(min(T.size, max(n0, target_s / max(est, 1e-9))))
     Ys = np.ascontiguousarray(Y[:, :n])
@@ -117,9 +121,40 @@ def cpu_baseline(mech, T, p, Y, target_s=12.0):
     om.production_rates(T[:n], p[:n], Ys, with_scale=False)
     om.transport(T[:n], p[:n], Ys)
     dt = time.perf_counter() - t0
-    return {"value": n / dt / 1e6, "unit": "Mpoints/s", "cores": threads, "kind": "oracle",
+    # single thread, the paper's per-core comparison basis
+    n1 = int(max(256, min(n, single_s * n / dt / max(threads, 1))))
+    O.set_threads(1)
+    Y1 = np.ascontiguousarray(Y[:, :n1])
+    t1 = time.perf_counter()
+    om.production_rates(T[:n1], p[:n1], Y1, with_scale=False)
+    om.transport(T[:n1], p[:n1], Y1)
+    dt1 = time.perf_counter() - t1
+    O.set_threads(threads)
+    base = {"value": n / dt / 1e6, "unit": "Mpoints/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} points of the same workload, production rates + transport, "
-                      f"{dt:.1f} s on {threads} threads"}
+                      f"{dt:.1f} s on {threads} threads",
+            "single_thread": {"value": n1 / dt1 / 1e6, "unit": "Mpoints/s", "cores": 1,
+                              "sample": f"first {n1} points, {dt1:.1f} s"}}
+    return base, (ref_w, ref_s) + tuple(ref_t)
+
+
+def error_report(gpu, ref):
+    """Per-output error of GPU outputs against the oracle on a sample: wdot by
+    the strict relative error and the conditioned error |d| / s_k on entries
+    above 1e-10 max|entry| of their point; transport by the relative error."""
+    import numpy as np
+    w, mu, lam, Dm = gpu
+    rw, rs, rmu, rlam, rDm = ref
+    mask = np.abs(rw) > 1e-10 * np.abs(rw).max(axis=0, keepdims=True)
+    d = np.abs(w - rw)[mask]
+    out = {"points": int(rw.shape[1]),
+           "wdot": {"max_rel": float((d / np.abs(rw)[mask]).max()),
+                    "median_rel": float(np.median(d / np.abs(rw)[mask])),
+                    "max_conditioned": float((d / rs[mask]).max())}}
+    for name, g, r in (("mu", mu, rmu), ("lambda", lam, rlam), ("Dmix", Dm, rDm)):
+        e = np.abs(g - r) / np.abs(r)
+        out[name] = {"max_rel": float(e.max()), "median_rel": float(np.median(e))}
+    return out
 
 
 def serve_bench(kx, args):
@@ -225,6 +260,14 @@ def main():
 
     log(f"fp64: {args.warmup} warmup + {args.steps} timed steps, n = {n}")
     wall, r_ms, t_ms = time_path(kx, dm, Td, pd, Yd, outs, args.steps, args.warmup, "fp64")
+    r_med, t_med = time_path.medians
+    sample = 4096
+
+    def head(o):  # first `sample` points of the outputs, on the host
+        w_, (mu_, lam_, Dm_) = o
+        return (w_[:, :sample].cpu().numpy(), mu_[:sample].cpu().numpy(),
+                lam_[:sample].cpu().numpy(), Dm_[:, :sample].cpu().numpy())
+    gpu64 = head(outs)
     ms_step = wall / args.steps * 1e3
     value = n * args.steps / wall / 1e6
     log(f"fp64 {value:.1f} Mpoints/s (rates {r_ms:.3f} ms, transport {t_ms:.3f} ms)")
@@ -233,9 +276,12 @@ def main():
     if not args.no_mixed:
         log("mixed precision")
         mwall, mr, mt = time_path(kx, dm, Td, pd, Yd, outs, args.steps, args.warmup, "mixed")
+        gpumx = head(outs)
         mixed = {"value": n * args.steps / mwall / 1e6, "unit": "Mpoints/s",
                  "ms_per_step": mwall / args.steps * 1e3,
                  "rates_kernel_ms": mr, "transport_kernel_ms": mt,
+                 "rates_kernel_ms_median": time_path.medians[0],
+                 "transport_kernel_ms_median": time_path.medians[1],
                  "speedup_vs_fp64": (n * args.steps / mwall) / (n * args.steps / wall)}
         log(f"mixed {mixed['value']:.1f} Mpoints/s")
 
@@ -270,11 +316,16 @@ def main():
         log("serving")
         served = serve_bench(kx, args)
 
-    cpu = None
+    cpu = errors = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(mech, T, p, Y)
-        log(f"oracle {cpu['value']:.4f} Mpoints/s on {cpu['cores']} threads")
+        cpu, ref = cpu_baseline(mech, T, p, Y)
+        log(f"oracle {cpu['value']:.4f} Mpoints/s on {cpu['cores']} threads, "
+            f"{cpu['single_thread']['value']:.5f} on one")
+        errors = {"fp64": error_report(gpu64, ref)}
+        if mixed is not None:
+            errors["mixed"] = error_report(gpumx, ref)
+        log("errors vs oracle", json.dumps(errors))
 
     line = {
         "metric": "Mpoints/s wdot+transport (53 sp) FP64 vs mixed; served p50/p99 latency",
@@ -289,6 +340,8 @@ def main():
         "grxn_per_s": value * 1e6 * nr / 1e9,
         "gdof_per_s": value * 1e6 * (ns + 2) / 1e9,
         "rates_kernel_ms": r_ms, "transport_kernel_ms": t_ms,
+        "rates_kernel_ms_median": r_med, "transport_kernel_ms_median": t_med,
+        "error_vs_oracle": errors,
         "roofline": roofline, "cpu_baseline": cpu, "mixed": mixed, "served": served,
     }
     print(json.dumps(line), flush=True)
