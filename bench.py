@@ -101,6 +101,59 @@ def time_path(kx, dm, Td, pd, Yd, outs, steps, warmup, precision):
     return wall, sum(r) / steps, sum(t) / steps
 
 
+def other_workloads(kx, I, torch, steps, warmup):
+    """Kernel times of the other workload sizes, on device-generated states of
+    the same distributions (T ~ U[300, 2800] K, p ~ U[1, 40] atm, Y ~
+    Dirichlet(0.3)): syn53 at 2^22 points; syn200 at 2^20 points with 1/D_kj fit
+    tables (matrix-core transport) and with D_kj fit tables (vector-ALU
+    transport); and a sweep of the point count for syn53.  No kernel branches
+    on state values other than the NASA temperature range, so the work per
+    point does not depend on how the states are drawn."""
+    import dataclasses
+    from paper_2411_02640_amd import serve_load
+
+    def run(mech, n, seed, nsteps):
+        dm = kx.Mechanism(mech, 0)
+        ns = int(mech["n_species"])
+        (_, T, p, Y), = serve_load.make_pool(dm, ns, [n], seed)
+        kw = dict(dtype=torch.float64, device="cuda:0")
+        outs = (torch.empty((ns, n), **kw),
+                (torch.empty(n, **kw), torch.empty(n, **kw), torch.empty((ns, n), **kw)))
+        entry = {"n_points": n, "n_species": ns, "n_reactions": int(mech["n_reactions"]),
+                 "steps": nsteps}
+        for prec in ("fp64", "mixed"):
+            wall, r, t = time_path(kx, dm, T, p, Y, outs, nsteps, warmup, prec)
+            entry[prec] = {"Mpoints_s": n * nsteps / wall / 1e6, "rates_ms": r,
+                           "transport_ms": t, "rates_ms_median": time_path.medians[0],
+                           "transport_ms_median": time_path.medians[1]}
+        del outs, T, p, Y
+        dm.close()
+        torch.cuda.empty_cache()
+        return entry
+
+    m53 = I.make_mechanism(I.MECH_53)
+    res = {"states": "device-generated (torch generator), seeds 11-13 and 20+"}
+    log("syn53 at 2^22 points")
+    res["syn53_2p22"] = run(m53, 1 << 22, 11, steps)
+    m200 = I.make_mechanism(I.MECH_200)
+    log("syn200 at 2^20 points (1/D_kj fits)")
+    res["syn200_2p20"] = run(m200, 1 << 20, 12, steps)
+    log("syn200 at 2^20 points (D_kj fits)")
+    m200d = I.make_mechanism(dataclasses.replace(I.MECH_200, diff_fit_kind=0))
+    res["syn200_2p20_dfit"] = run(m200d, 1 << 20, 13, steps)
+    sweep = []
+    for e in range(10, 25, 2):
+        n = 1 << e
+        log(f"sweep n = 2^{e}")
+        r = run(m53, n, 20 + e, max(steps, min(400, (1 << 22) // n)))
+        sweep.append({"n_points": n, "fp64_Mpoints_s": r["fp64"]["Mpoints_s"],
+                      "mixed_Mpoints_s": r["mixed"]["Mpoints_s"],
+                      "fp64_rates_ms": r["fp64"]["rates_ms"],
+                      "fp64_transport_ms": r["fp64"]["transport_ms"]})
+    res["sweep_syn53"] = sweep
+    return res
+
+
 def cpu_baseline(mech, T, p, Y, target_s=12.0, single_s=3.0):
     """The oracle as it stands, on a bounded sample of the same states, on all
     host threads and on one.  Returns the baseline and the oracle's outputs on
@@ -225,6 +278,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 2^22, syn200 and point-count sweep timings")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB elementwise copy first (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=400)
@@ -311,6 +366,10 @@ def main():
                                 "frac": ofl * n / (oms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS,
                                 "ms": oms, "traffic": profiled_traffic(other)}
 
+    extra = None
+    if not args.no_extra:
+        extra = other_workloads(kx, I, torch, args.steps, args.warmup)
+
     served = None
     if not args.no_serve:
         log("serving")
@@ -343,6 +402,7 @@ def main():
         "rates_kernel_ms_median": r_med, "transport_kernel_ms_median": t_med,
         "error_vs_oracle": errors,
         "roofline": roofline, "cpu_baseline": cpu, "mixed": mixed, "served": served,
+        "other_workloads": extra,
     }
     print(json.dumps(line), flush=True)
     dm.close()
