@@ -130,10 +130,16 @@ __device__ __forceinline__ double third_body(const MechDev &m, const DevAux &ax,
                                              const char *__restrict__ pb, double Mconc)
 {
     double X = ax.eff_default * Mconc;
+    // the reads are issued four at a time (left to itself the scheduler waits
+    // for each read in turn; eight in flight would cost registers)
 #pragma unroll
-    for (int e = 0; e < kInlineEff; ++e) {
-        const Pair s = load_pair(pb, ax.eoff[e]);
-        X = fma(ax.dalpha[e], s.a * s.b, X);
+    for (int e0 = 0; e0 < kInlineEff; e0 += 4) {
+        Pair s[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s[e] = load_pair(pb, ax.eoff[e0 + e]);
+        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) X = fma(ax.dalpha[e0 + e], s[e].a * s[e].b, X);
     }
     for (int e = 0; e < ax.ext_cnt; ++e) {
         const DevEff f = m.eff[ax.ext_off + e];
@@ -157,17 +163,19 @@ __device__ __forceinline__ double rate_of_progress(const MechDev &m, const RxnWo
     const unsigned flags = (w.w2.w >> 8) & 0xFFu;
     const unsigned aux = w.w2.w >> 16;
 
+    // the LDS reads go first so that their latency hides behind the exponential
+    const Pair r0 = load_pair(pb, w.w2.x & 0xFFFFu);
+    const Pair r1 = load_pair(pb, w.w2.x >> 16);
+    const double bp0 = load_b(pb, w.w2.y >> 16), bp1 = load_b(pb, w.w2.z & 0xFFFFu);
     // exponent of k_f (eq:k_f); k_f = A without an exponential when beta = E_R = 0
     // (such reactions are sorted together, so the branch is mostly wave-uniform)
     const bool kconst = (flags & kFlagKfConst) != 0;
     const double xf = kconst ? lnA : fma(beta, lnT, fma(-ER, invT, lnA));
     double kf = A;
     if (!kconst) kf = MIXED ? exp_mixed(xf) : kexp(xf);
-    const Pair r0 = load_pair(pb, w.w2.x & 0xFFFFu);
-    const Pair r1 = load_pair(pb, w.w2.x >> 16);
     double Ap = r0.a * r1.a;
     double Bp = r0.b * r1.b;
-    double Bpp = load_b(pb, w.w2.y >> 16) * load_b(pb, w.w2.z & 0xFFFFu);
+    double Bpp = bp0 * bp1;
     // third molecule slots: skipped by the whole wave when none of its
     // reactions has three molecules on a side (the dummy species gives 1)
     const unsigned o2 = w.w2.y & 0xFFFFu, o5 = w.w2.z >> 16;
@@ -387,12 +395,19 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
                     const unsigned off[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
                     // the eight entries of a group are summed plainly; the
                     // mixed path compensates the running sum across groups
-                    double g0 = 0.0, g1 = 0.0;
+                    // all eight reads are issued before the first sum (left to
+                    // itself the scheduler waits for each read in turn)
+                    double2 q2[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const double2 q2 = *reinterpret_cast<const double2 *>(qb + off[u]);
-                        g0 += q2.x;
-                        g1 += q2.y;
+                    for (int u = 0; u < 8; ++u)
+                        q2[u] = *reinterpret_cast<const double2 *>(qb + off[u]);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // DS reads
+                    __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);  // VALU
+                    double g0 = q2[0].x, g1 = q2[0].y;
+#pragma unroll
+                    for (int u = 1; u < 8; ++u) {
+                        g0 += q2[u].x;
+                        g1 += q2[u].y;
                     }
                     if (it >= npos) {
                         g0 = -g0;
