@@ -250,6 +250,30 @@ def serve_bench(kx, args):
             log(f"serve load {frac:.2f}: p50 {s['p50_ms']:.2f} ms p99 {s['p99_ms']:.2f} ms "
                 f"{s['achieved_rps']:.1f} req/s")
             levels.append(s)
+        # the same service for a client whose data live in pinned host memory:
+        # inputs copied in at arrival, outputs copied out before the request
+        # counts as finished (latency to outputs on the host)
+        log("serving with host staging")
+        hpools = {name: SL.make_host_pool(pools[name][:args.serve_staged_pool],
+                                          mechs[name].n_species) for name in pools}
+        ns_, nw_ = args.serve_staged_requests, max(1, args.serve_staged_requests // 10)
+        cap_s = SL.make_stream(ns_, hpools, SERVE_SEED + 40)
+        rec = SL.run_stream_staged(srv, mechs, hpools, cap_s, None, 0)
+        scap = SL.summarize(rec, end="t_host")
+        staged = {"capacity_rps": scap["achieved_rps"],
+                  "capacity_Mpoints_s": scap["achieved_Mpoints_s"],
+                  "input_sets_per_mechanism": args.serve_staged_pool,
+                  "measured_requests": ns_, "warmup_requests": nw_, "levels": []}
+        log(f"staged capacity {scap['achieved_rps']:.1f} req/s")
+        for k, frac in enumerate((0.5, 0.9)):
+            qps = frac * scap["achieved_rps"]
+            stream = SL.make_stream(nw_ + ns_, hpools, SERVE_SEED + 50 + k)
+            rec = SL.run_stream_staged(srv, mechs, hpools, stream, qps, SERVE_SEED + 60 + k)
+            sm = SL.summarize(rec, skip=nw_, end="t_host")
+            sm.update({"load": frac, "offered_rps": qps})
+            log(f"staged load {frac:.2f}: p50 {sm['p50_ms']:.2f} ms p99 {sm['p99_ms']:.2f} ms")
+            staged["levels"].append(sm)
+        del hpools
         st = srv.stats()
     finally:
         srv.close()
@@ -266,7 +290,10 @@ def serve_bench(kx, args):
             "direct_sequential_rps": nm / seq_s,
             "direct_sequential_Mpoints_s": sum(pools[nm_][i][0] for nm_, i, _, _ in cap_stream)
                                            / seq_s / 1e6,
-            "levels": levels, "batches": st["batches"], "graph_launches": st["graph_launches"]}
+            "levels": levels, "batches": st["batches"], "graph_launches": st["graph_launches"],
+            "host_staged": dict(staged, workload="the same mix with inputs and outputs in "
+                                "pinned host memory: inputs copied to the device at arrival, "
+                                "latency to outputs copied back to the host")}
 
 
 def main():
@@ -287,6 +314,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=int, default=48)
+    ap.add_argument("--serve-staged-requests", type=int, default=200)
+    ap.add_argument("--serve-staged-pool", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

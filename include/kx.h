@@ -259,10 +259,12 @@ kx_status kx_wait(kx_server *srv, kx_ticket ticket, double timeout_s, kx_result 
  * if it is already running or finished. */
 kx_status kx_cancel(kx_server *srv, kx_ticket ticket);
 
-/* Enqueue copies of a DONE request's outputs into caller device buffers (any
- * may be NULL) on `stream`.  The copies must have completed before the ticket
- * is released (its arena space is reused at once), and a ticket must not be
- * copied and released from two threads at the same time. */
+/* Enqueue copies of a DONE request's outputs into caller buffers (any may be
+ * NULL) on `stream`; each buffer is device memory or pinned host memory
+ * (hipHostMalloc), in which case the copy goes over the host link.  The copies
+ * must have completed before the ticket is released (its arena space is reused
+ * at once), and a ticket must not be copied and released from two threads at
+ * the same time. */
 kx_status kx_result_copy(kx_server *srv, kx_ticket ticket, double *wdot, double *mu,
                          double *lambda, double *Dmix, hipStream_t stream);
 

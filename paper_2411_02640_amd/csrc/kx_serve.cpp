@@ -605,13 +605,13 @@ kx_status kx_result_copy(kx_server *s, kx_ticket t, double *wdot, double *mu, do
     const bool tr = (q->r.ops & KX_OP_TRANSPORT) != 0;
     hipError_t e = hipSuccess;
     if (wdot && e == hipSuccess)
-        e = hipMemcpyAsync(wdot, q->wdot, ns * n * 8, hipMemcpyDeviceToDevice, stream);
+        e = hipMemcpyAsync(wdot, q->wdot, ns * n * 8, hipMemcpyDefault, stream);
     if (tr && mu && e == hipSuccess)
-        e = hipMemcpyAsync(mu, q->mu, n * 8, hipMemcpyDeviceToDevice, stream);
+        e = hipMemcpyAsync(mu, q->mu, n * 8, hipMemcpyDefault, stream);
     if (tr && lam && e == hipSuccess)
-        e = hipMemcpyAsync(lam, q->lam, n * 8, hipMemcpyDeviceToDevice, stream);
+        e = hipMemcpyAsync(lam, q->lam, n * 8, hipMemcpyDefault, stream);
     if (tr && Dmix && e == hipSuccess)
-        e = hipMemcpyAsync(Dmix, q->Dmix, ns * n * 8, hipMemcpyDeviceToDevice, stream);
+        e = hipMemcpyAsync(Dmix, q->Dmix, ns * n * 8, hipMemcpyDefault, stream);
     if (e != hipSuccess) return hip_fail(e, "kx_result_copy");
     return ok();
 }

@@ -353,6 +353,31 @@ class Server:
         st.synchronize()  # the arena space may be reused as soon as it is released
         return w, mu, lam, Dm
 
+    def copy_outputs(self, ticket: int, wdot, mu=None, lam=None, Dmix=None, stream=None):
+        """Copy a done request's outputs into caller tensors (float64, contiguous,
+        on this server's device or in pinned host memory; any may be None) and
+        wait for the copies."""
+        ns, n, transport = self._meta[ticket]
+        shapes = ((wdot, (ns, n)), (mu, (n,)), (lam, (n,)), (Dmix, (ns, n)))
+        for t, shape in shapes:
+            if t is None:
+                continue
+            if t.dtype != torch.float64 or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"output tensor must be contiguous float64 of shape {shape}")
+            if t.is_cuda:
+                if t.device.index != self.device:
+                    raise ValueError("output tensor on another device")
+            elif not t.is_pinned():
+                raise ValueError("host output tensors must be in pinned memory")
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        check(_serve_lib().kx_result_copy(self.handle, ticket, ptr(wdot),
+                                          ptr(mu if transport else None),
+                                          ptr(lam if transport else None),
+                                          ptr(Dmix if transport else None),
+                                          C.c_void_p(st.cuda_stream)))
+        st.synchronize()
+
     def release(self, ticket: int) -> None:
         check(_serve_lib().kx_release(self.handle, ticket))
         self._inputs.pop(ticket, None)

@@ -51,11 +51,28 @@ def make_stream(n_req: int, pools: dict, seed: int):
     return out
 
 
-class _Collector(threading.Thread):
-    """Waits for tickets in submission order, records timings, releases."""
+def make_host_pool(pool, ns: int):
+    """Pinned host copies of device input sets, with pinned output buffers:
+    per entry (n, (T, p, Y), (wdot, mu, lambda, Dmix))."""
+    out = []
+    for n, T, p, Y in pool:
+        hin = tuple(torch.empty(t.shape, dtype=t.dtype, pin_memory=True).copy_(t)
+                    for t in (T, p, Y))
+        kw = dict(dtype=torch.float64, pin_memory=True)
+        hout = (torch.empty((ns, n), **kw), torch.empty(n, **kw), torch.empty(n, **kw),
+                torch.empty((ns, n), **kw))
+        out.append((n, hin, hout))
+    return out
 
-    def __init__(self, srv: kx.Server):
+
+class _Collector(threading.Thread):
+    """Waits for tickets in submission order, records timings, releases.
+    `finish(ticket, meta, result)`, if given, runs before the release (the
+    host-staged client copies the outputs out there)."""
+
+    def __init__(self, srv: kx.Server, finish=None):
         super().__init__(daemon=True)
+        self.finish = finish
         self.srv = srv
         self.q = []
         self.cv = threading.Condition()
@@ -85,6 +102,8 @@ class _Collector(threading.Thread):
                 r = self.srv.wait(ticket, 120.0)
                 if r["state"] != "done":
                     raise RuntimeError(f"request {ticket} ended {r['state']}")
+                if self.finish is not None:
+                    self.finish(ticket, meta, r)
                 self.records.append((meta, r))
                 self.srv.release(ticket)
         except Exception as e:  # surfaced by the caller
@@ -121,14 +140,63 @@ def run_stream(srv: kx.Server, mechs: dict, pools: dict, stream, qps: float | No
     return col.records
 
 
-def summarize(records, skip: int = 0):
+def run_stream_staged(srv: kx.Server, mechs: dict, hpools: dict, stream, qps: float | None,
+                      seed: int):
+    """As run_stream, for a client whose data live in pinned host memory: at
+    its scheduled arrival a request's inputs are copied into fresh device
+    buffers (on a client stream, waited for) and it is submitted; once it is
+    done its outputs are copied back into pinned host buffers.  The request's
+    "t_host" is when that copy has completed (the server's clock)."""
+    rng = np.random.default_rng(seed)
+    dev = torch.device(f"cuda:{srv.device}")
+    cin = torch.cuda.Stream(dev)
+    cout = torch.cuda.Stream(dev)
+
+    def finish(ticket, meta, r):
+        _, _, tr, _, idx = meta
+        _, _, (w, mu, lam, Dm) = hpools[meta[0]][idx]
+        srv.copy_outputs(ticket, w, mu if tr else None, lam if tr else None,
+                         Dm if tr else None, stream=cout)
+        r["t_host"] = kx.clock()
+
+    col = _Collector(srv, finish)
+    col.start()
+    t0 = kx.clock() + 0.01
+    gaps = rng.exponential(1.0 / qps, len(stream)) if qps else np.zeros(len(stream))
+    sched = t0 + np.cumsum(gaps)
+    for (name, idx, tr, prec), ts in zip(stream, sched):
+        if qps:
+            while True:
+                d = ts - kx.clock()
+                if d <= 0:
+                    break
+                time.sleep(d if d > 2e-4 else 0)
+        n, (hT, hp, hY), _ = hpools[name][idx]
+        with torch.cuda.stream(cin):
+            T, p, Y = (h.to(dev, non_blocking=True) for h in (hT, hp, hY))
+        cin.synchronize()
+        t = srv.submit(mechs[name], T, p, Y, transport=tr, precision=prec,
+                       arrival=float(ts) if qps else None)
+        col.push((t, (name, n, tr, prec, idx)))
+        if col.error:
+            break
+    col.close()
+    col.join()
+    if col.error:
+        raise col.error
+    return col.records
+
+
+def summarize(records, skip: int = 0, end: str = "t_done"):
+    """Latency percentiles from the scheduled arrival to `end` ("t_done":
+    outputs ready on the device; "t_host": copied to the host)."""
     recs = records[skip:]
-    lat = np.array([r["t_done"] - r["t_arrival"] for _, r in recs])
+    lat = np.array([r[end] - r["t_arrival"] for _, r in recs])
     queue = np.array([r["t_launch"] - r["t_arrival"] for _, r in recs])
     service = np.array([r["t_done"] - r["t_launch"] for _, r in recs])
     pts = sum(m[1] for m, _ in recs)
     t_first = min(r["t_arrival"] for _, r in recs)
-    t_last = max(r["t_done"] for _, r in recs)
+    t_last = max(r[end] for _, r in recs)
     span = max(t_last - t_first, 1e-9)
     return {"requests": len(recs), "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3),

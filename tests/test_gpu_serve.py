@@ -188,3 +188,41 @@ def test_graph_replay_across_batches(kx, mechs):
         assert st["graph_launches"] == st["batches"] >= 2
     finally:
         srv.close()
+
+
+def test_host_staged_client(kx, mechs):
+    """A client whose data live in pinned host memory: inputs are copied in at
+    arrival and outputs copied back into pinned host buffers (kx_result_copy
+    with host destinations).  Every host output equals the direct call bit for
+    bit, and a pageable host buffer is refused."""
+    from paper_2411_02640_amd import serve_load as SL
+    devs = {name: dm for name, (dm, _) in mechs.items()}
+    pools, hpools = {}, {}
+    for k, (name, (dm, mech)) in enumerate(sorted(mechs.items())):
+        pools[name] = SL.make_pool(dm, mech["n_species"], [1000 + 777 * i for i in range(3)],
+                                   40 + k)
+        hpools[name] = SL.make_host_pool(pools[name], mech["n_species"])
+    stream = [(name, i, i % 2 == 0, "mixed" if i == 1 else "fp64")
+              for name in sorted(hpools) for i in range(3)]
+    _say("host-staged stream of", len(stream), "requests")
+    srv = kx.Server(0, hbm_budget=1 << 30, max_slots=8)
+    try:
+        rec = SL.run_stream_staged(srv, devs, hpools, stream, None, 0)
+        assert len(rec) == len(stream)
+        assert all(r["t_host"] >= r["t_done"] for _, r in rec)
+        dm, mech = mechs["syn9"]
+        n, (hT, hp, hY), _ = hpools["syn9"][0]
+        t = srv.submit(dm, hT.to(DEV), hp.to(DEV), hY.to(DEV))
+        assert srv.wait(t, WAIT_S)["state"] == "done"
+        with pytest.raises(ValueError):
+            srv.copy_outputs(t, torch.empty((mech["n_species"], n), dtype=torch.float64))
+        srv.release(t)
+    finally:
+        srv.close()
+    for name, i, tr, prec in stream:
+        n, (hT, hp, hY), (w, mu, lam, Dm) = hpools[name][i]
+        ref = _direct(kx, devs[name], hT.to(DEV), hp.to(DEV), hY.to(DEV), tr, prec)
+        assert torch.equal(w, ref[0].cpu()), (name, i)
+        if tr:
+            for got, want in zip((mu, lam, Dm), ref[1:]):
+                assert torch.equal(got, want.cpu()), (name, i)
