@@ -72,7 +72,10 @@ enum {
     KX_RXN_ELEMENTARY = 0, /* c_i = 1 */
     KX_RXN_THREEBODY = 1,  /* c_i = [X]_i */
     KX_RXN_LINDEMANN = 2,  /* c_i = P_r/(1+P_r), F = 1 */
-    KX_RXN_TROE = 3        /* c_i = P_r/(1+P_r) F_Troe (eq:blend) */
+    KX_RXN_TROE = 3,       /* c_i = P_r/(1+P_r) F_Troe (eq:blend) */
+    KX_RXN_SRI = 4,        /* c_i = P_r/(1+P_r) F_SRI (eq:blend, SRI form) */
+    KX_RXN_PLOG = 5        /* c_i = 1, k_f interpolated in ln p between reference
+                              pressures (App. A.2, pressure-dependent reactions) */
 };
 
 /* Mechanism descriptor.  Every array is HOST memory owned by the caller and
@@ -110,6 +113,25 @@ typedef struct {
     const double *cond_fit;       /* [Ns][order] lambda_k(u) */
     const double *diff_fit;       /* [Ns][Ns][order], symmetric in (k, j); the diagonal
                                      is used only when sum_{j!=k} X_j/D_kj == 0 */
+    /* Further reaction forms (App. A.2).  Each pointer may be NULL when no
+     * reaction uses it. */
+    const double *sri;            /* [Nr][5] a, b, c, d, e of KX_RXN_SRI reactions:
+                                     F = d T^e [a exp(-b/T) + exp(-T/c)]^X with
+                                     X = 1 / (1 + log10(P_r)^2); a >= 0, c != 0,
+                                     d > 0 (d = 1, e = 0 when a mechanism gives three) */
+    const int32_t *chem_act;      /* [Nr] nonzero marks a chemically activated falloff
+                                     reaction (types LINDEMANN, TROE, SRI): c_i =
+                                     F/(1+P_r) (eq:c_i) and r_i uses k_0 in place of
+                                     k_inf, i.e. k_f = k_0 F/(1+P_r) */
+    const int32_t *plog_ptr;      /* [Nr+1] CSR of the reference pressures of KX_RXN_PLOG
+                                     reactions (at least one each; empty for the other
+                                     types, whose entries are not read) */
+    const double *plog_p;         /*   reference pressure p_j > 0, dyn/cm^2, strictly
+                                     increasing within a reaction */
+    const double *plog_A, *plog_beta, *plog_Ea;  /* Arrhenius k_j(T) at p_j.  ln k_f is
+                                     linear in ln p between neighbouring p_j; below the
+                                     first (above the last) pressure k_f is that point's
+                                     k_j.  A, beta, Ea of a PLOG reaction are not read. */
 } kx_mech_desc;
 
 typedef struct kx_mech kx_mech; /* opaque device-resident mechanism */
@@ -119,8 +141,10 @@ typedef struct kx_mech kx_mech; /* opaque device-resident mechanism */
  * tables) and upload them to `device`.  Rejects (KX_EINVAL) negative or zero
  * sizes, out-of-range species indices, non-positive W_k or A, a species listed
  * twice on one side of a reaction, unbalanced element counts, an unknown
- * reaction type, a non-symmetric diff_fit, fit_order outside 1..8 and
- * fit_h == 0.  KX_EUNSUPPORTED: more than 3 molecules (sum of nu) on one side
+ * reaction type, a non-symmetric diff_fit, fit_order outside 1..8,
+ * fit_h == 0, SRI parameters outside their ranges, chem_act set on a reaction
+ * that is not a falloff reaction, and PLOG tables that are empty, not
+ * increasing in pressure or with A <= 0.  KX_EUNSUPPORTED: more than 3 molecules (sum of nu) on one side
  * of a reaction, or more than 256 species.  On success *out owns the tables until
  * kx_mech_destroy.  Allocates device memory (hipMalloc); blocks until the
  * upload is complete. */

@@ -22,6 +22,12 @@
  *    p/p_atm; kind 1 tables hold fits of 1/D_kj instead.
  *  - D_km falls back to D_kk when sum_{j!=k} X_j/D_kj is exactly zero.
  *  - P_r is clamped below at the smallest normal double before log10.
+ *  - SRI: log in X = 1/(1 + log^2 P_r) is base 10, like Troe.
+ *  - Chemically activated falloff: c_i = F/(1+P_r) (eq:c_i) and the rate of
+ *    progress r_i uses k_0 where other reactions use k_f, so that the forward
+ *    rate constant is k_0 F/(1+P_r).
+ *  - Pressure tables (PLOG): ln k_f linear in ln p between the two neighbouring
+ *    reference pressures; outside the table the nearest end point's k_j.
  *  - Units: cgs, concentrations in mol/cm^3, Ea in cal/mol.
  */
 #include <float.h>
@@ -39,7 +45,8 @@
 #define KXO_RCAL (8.31446261815324 / 4.184)        /* cal / (mol K) */
 #define KXO_PATM 1013250.0                         /* dyn / cm^2 */
 
-enum { KXO_ELEMENTARY = 0, KXO_THREEBODY = 1, KXO_LINDEMANN = 2, KXO_TROE = 3 };
+enum { KXO_ELEMENTARY = 0, KXO_THREEBODY = 1, KXO_LINDEMANN = 2, KXO_TROE = 3, KXO_SRI = 4,
+       KXO_PLOG = 5 };
 
 /* The oracle's own view of a mechanism: plain host arrays, row-major. */
 typedef struct {
@@ -64,6 +71,10 @@ typedef struct {
     const double *visc_fit;      /* [ns][order] */
     const double *cond_fit;      /* [ns][order] */
     const double *diff_fit;      /* [ns][ns][order] */
+    const double *sri;           /* [nr][5] a, b, c, d, e (or NULL) */
+    const int32_t *chem_act;     /* [nr] (or NULL) */
+    const int32_t *plog_ptr;     /* [nr+1] (or NULL) */
+    const double *plog_p, *plog_A, *plog_beta, *plog_Ea;
 } kxo_mech;
 
 static int g_threads = 0;
@@ -191,6 +202,35 @@ static double troe_F(const double *p4, double T, double Pr)
     return pow(10.0, lF);
 }
 
+/* SRI blending factor F = d T^e [a exp(-b/T) + exp(-T/c)]^X with
+ * X = 1/(1 + log10(P_r)^2) (eq:blend). */
+static double sri_F(const double *p5, double T, double Pr)
+{
+    const double a = p5[0], b = p5[1], c = p5[2], d = p5[3], e = p5[4];
+    const double lPr = log10(Pr > DBL_MIN ? Pr : DBL_MIN);
+    const double X = 1.0 / (1.0 + lPr * lPr);
+    return d * pow(T, e) * pow(a * exp(-b / T) + exp(-T / c), X);
+}
+
+/* Forward rate constant of a pressure-table reaction at (T, p): the
+ * logarithmic interpolation of App. A.2 between the reference pressures that
+ * bracket p; the end point's rate outside the table. */
+static double plog_kf(const kxo_mech *m, int i, double T, double p)
+{
+    const int b = m->plog_ptr[i], e = m->plog_ptr[i + 1];
+    const double *P = m->plog_p;
+    if (p <= P[b]) return arrhenius(m->plog_A[b], m->plog_beta[b], m->plog_Ea[b], T);
+    if (p >= P[e - 1])
+        return arrhenius(m->plog_A[e - 1], m->plog_beta[e - 1], m->plog_Ea[e - 1], T);
+    int j = b;
+    while (!(p < P[j + 1])) ++j;
+    const double k1 = arrhenius(m->plog_A[j], m->plog_beta[j], m->plog_Ea[j], T);
+    const double k2 = arrhenius(m->plog_A[j + 1], m->plog_beta[j + 1], m->plog_Ea[j + 1], T);
+    const double lk = log(k1) + (log(k2) - log(k1)) * (log(p) - log(P[j])) /
+                                    (log(P[j + 1]) - log(P[j]));
+    return exp(lk);
+}
+
 /* Net stoichiometric coefficient nu''_ki - nu'_ki. */
 static int net_nu(const kxo_mech *m, int i, int k)
 {
@@ -242,15 +282,23 @@ static void rates_point(const kxo_mech *m, double T, double p, const double *Y,
 
     for (int i = 0; i < nr; ++i) {
         const int type = m->rtype[i];
-        double kf = arrhenius(m->A[i], m->beta[i], m->Ea[i], T);
+        double kf = (type == KXO_PLOG) ? plog_kf(m, i, T, p)
+                                       : arrhenius(m->A[i], m->beta[i], m->Ea[i], T);
         double c = 1.0;
         if (type == KXO_THREEBODY) {
             c = third_body(m, i, C);
-        } else if (type == KXO_LINDEMANN || type == KXO_TROE) {
+        } else if (type == KXO_LINDEMANN || type == KXO_TROE || type == KXO_SRI) {
             const double k0 = arrhenius(m->A0[i], m->beta0[i], m->Ea0[i], T);
             const double Pr = k0 * third_body(m, i, C) / kf;
-            const double F = (type == KXO_TROE) ? troe_F(m->troe + 4 * i, T, Pr) : 1.0;
-            c = Pr / (1.0 + Pr) * F;
+            double F = 1.0;
+            if (type == KXO_TROE) F = troe_F(m->troe + 4 * i, T, Pr);
+            if (type == KXO_SRI) F = sri_F(m->sri + 5 * i, T, Pr);
+            if (m->chem_act && m->chem_act[i]) {
+                c = F / (1.0 + Pr);
+                kf = k0;
+            } else {
+                c = Pr / (1.0 + Pr) * F;
+            }
         }
         double kr = 0.0;
         if (m->rev[i]) {
@@ -334,18 +382,21 @@ void kxo_rates_detail(const kxo_mech *m, double T, double p, const double *Y,
 
 /* Forward rate constants k_f (k_inf for falloff) and, for falloff reactions,
  * k_0, at temperature T (for closed-form tests). */
-void kxo_rate_constants(const kxo_mech *m, double T, double *kf, double *k0)
+void kxo_rate_constants(const kxo_mech *m, double T, double p, double *kf, double *k0)
 {
     for (int i = 0; i < m->nr; ++i) {
-        kf[i] = arrhenius(m->A[i], m->beta[i], m->Ea[i], T);
-        k0[i] = (m->rtype[i] == KXO_LINDEMANN || m->rtype[i] == KXO_TROE)
+        const int t = m->rtype[i];
+        kf[i] = (t == KXO_PLOG) ? plog_kf(m, i, T, p) : arrhenius(m->A[i], m->beta[i], m->Ea[i], T);
+        k0[i] = (t == KXO_LINDEMANN || t == KXO_TROE || t == KXO_SRI)
                     ? arrhenius(m->A0[i], m->beta0[i], m->Ea0[i], T)
                     : 0.0;
     }
 }
 
-/* The Troe blend for parameters p4 at (T, Pr), for closed-form tests. */
+/* The Troe and SRI blends for parameters p4 / p5 at (T, Pr), for closed-form
+ * tests. */
 double kxo_troe_F(const double *p4, double T, double Pr) { return troe_F(p4, T, Pr); }
+double kxo_sri_F(const double *p5, double T, double Pr) { return sri_F(p5, T, Pr); }
 
 /* --------------------------------------------------------------- transport */
 

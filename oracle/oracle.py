@@ -49,6 +49,8 @@ class _Mech(C.Structure):
         ("fit_order", C.c_int32), ("fit_L0", C.c_double), ("fit_h", C.c_double),
         ("diff_kind", C.c_int32),
         ("visc_fit", _dp), ("cond_fit", _dp), ("diff_fit", _dp),
+        ("sri", _dp), ("chem_act", _ip), ("plog_ptr", _ip), ("plog_p", _dp),
+        ("plog_A", _dp), ("plog_beta", _dp), ("plog_Ea", _dp),
     ]
 
 
@@ -66,9 +68,11 @@ def lib():
         L.kxo_mixture_thermo.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp]
         L.kxo_production_rates.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp]
         L.kxo_rates_detail.argtypes = [vp, C.c_double, C.c_double, vp, vp, vp, vp, vp, vp]
-        L.kxo_rate_constants.argtypes = [vp, C.c_double, vp, vp]
+        L.kxo_rate_constants.argtypes = [vp, C.c_double, C.c_double, vp, vp]
         L.kxo_troe_F.argtypes = [vp, C.c_double, C.c_double]
         L.kxo_troe_F.restype = C.c_double
+        L.kxo_sri_F.argtypes = [vp, C.c_double, C.c_double]
+        L.kxo_sri_F.restype = C.c_double
         L.kxo_pure_transport.argtypes = [vp, C.c_double, C.c_double, vp, vp, vp]
         L.kxo_wilke_phi.argtypes = [vp, C.c_double, C.c_int, C.c_int]
         L.kxo_wilke_phi.restype = C.c_double
@@ -107,6 +111,15 @@ class OracleMech:
             a = i32(k)
             self._keep[k] = a
             setattr(s, field_of.get(k, k), a.ctypes.data_as(_ip))
+        for k, conv, ptr in (("sri", f64, _dp), ("plog_p", f64, _dp), ("plog_A", f64, _dp),
+                             ("plog_beta", f64, _dp), ("plog_Ea", f64, _dp),
+                             ("chem_act", i32, _ip), ("plog_ptr", i32, _ip)):
+            if mech.get(k) is None:
+                setattr(s, k, None)
+                continue
+            a = conv(k)
+            self._keep[k] = a
+            setattr(s, k, a.ctypes.data_as(ptr))
         s.fit_order = int(mech["fit_order"])
         s.fit_L0 = float(mech["fit_L0"])
         s.fit_h = float(mech["fit_h"])
@@ -158,9 +171,11 @@ class OracleMech:
                                _ptr(scale), _ptr(qf), _ptr(qr), _ptr(c))
         return dict(wdot=wdot, scale=scale, qf=qf, qr=qr, c=c)
 
-    def rate_constants(self, T: float):
+    def rate_constants(self, T: float, p: float = PATM):
+        """k_f (k_inf for falloff reactions; the interpolated k_f of a pressure
+        table at p) and k_0 (falloff only) at temperature T."""
         kf, k0 = np.empty(self.nr), np.empty(self.nr)
-        lib().kxo_rate_constants(self.ref, float(T), _ptr(kf), _ptr(k0))
+        lib().kxo_rate_constants(self.ref, float(T), float(p), _ptr(kf), _ptr(k0))
         return kf, k0
 
     # ---------------------------------------------------------------- transport
@@ -188,6 +203,11 @@ class OracleMech:
 def troe_F(params4, T: float, Pr: float) -> float:
     a = np.ascontiguousarray(params4, np.float64)
     return lib().kxo_troe_F(_ptr(a), float(T), float(Pr))
+
+
+def sri_F(params5, T: float, Pr: float) -> float:
+    a = np.ascontiguousarray(params5, np.float64)
+    return lib().kxo_sri_F(_ptr(a), float(T), float(Pr))
 
 
 def set_threads(n: int) -> None:

@@ -25,6 +25,7 @@ constexpr int kWave = 64;
 enum : uint8_t {
     kFlagReversible = 1,
     kFlagKfConst = 2,    // beta = E_R = 0: k_f = A without an exponential
+    kFlagChemAct = 4,    // chemically activated falloff: c = F / (1 + P_r) with k_0 in r_i
 };
 
 // One reaction slot in kernel order.  Reactions are sorted heaviest type
@@ -46,23 +47,33 @@ struct alignas(16) DevRxn {
 };
 static_assert(sizeof(DevRxn) == 48, "DevRxn layout");
 
-// Third-body and falloff data of one reaction.  Up to kInlineEff explicit
-// efficiencies are stored inline (LDS byte offset of the species and
-// alpha - default; unused entries point at the dummy species with 0); any
-// further ones are in DevEff[ext_off .. ext_off + ext_cnt).  160 bytes.
+// Third-body, falloff and pressure-table data of one reaction.  Up to
+// kInlineEff explicit efficiencies are stored inline (LDS byte offset of the
+// species and alpha - default; unused entries point at the dummy species with
+// 0); any further ones are in DevEff[ext_off .. ext_off + ext_cnt).  A PLOG
+// reaction's reference pressures are DevPlog[plog_off .. plog_off + plog_cnt).
+// 176 bytes.
 constexpr int kInlineEff = 8;
 struct alignas(16) DevAux {
     double eff_default;      // efficiency of unlisted species
     double lnA0, beta0, ER0; // k_0 (falloff)
-    double troe_alpha;
-    double troe_inv_T3;      // 1 / T***
-    double troe_inv_T1;      // 1 / T*
-    double troe_T2;          // T** (used when has_T2)
+    // Falloff blend parameters (eq:blend):
+    //   Troe: alpha, 1/T***, 1/T*, T** (used when has_T2), 0
+    //   SRI:  a, b, 1/c, ln d, e
+    double fp[5];
     double dalpha[kInlineEff];
     uint16_t eoff[kInlineEff];
-    int32_t has_T2, ext_off, ext_cnt, pad;
+    int32_t has_T2, ext_off, ext_cnt;
+    int32_t plog_off, plog_cnt, pad;
 };
-static_assert(sizeof(DevAux) == 160, "DevAux layout");
+static_assert(sizeof(DevAux) == 176, "DevAux layout");
+
+// One reference pressure of a PLOG reaction: ln p_j, the Arrhenius exponent
+// ln k_j = lnA + beta ln T - ER / T, and 1 / (ln p_(j+1) - ln p_j) (0 for the
+// last).  48 bytes.
+struct alignas(16) DevPlog {
+    double lnp, lnA, beta, ER, inv_dlnp, pad;
+};
 
 struct alignas(16) DevEff {
     double dalpha;           // alpha_ki - eff_default
@@ -96,6 +107,7 @@ struct MechDev {
     const DevRxn *rxn;         // [nr] kernel order
     const DevAux *aux;         // [naux]
     const DevEff *eff;         // [neff]
+    const DevPlog *plog;       // [nplog]
     const DevSpecies *sp;      // [ns]
     const int32_t *gpos;       // [nchunks] groups of eight +q entries of the gather
     const int32_t *gneg;       // [nchunks] groups of eight -q entries

@@ -92,11 +92,42 @@ kx_status validate(const kx_mech_desc *d, std::vector<double> &W)
     for (int i = 0; i < nr; ++i) {
         const std::string ri = " (reaction " + std::to_string(i) + ")";
         const int t = d->rxn_type[i];
-        if (t < KX_RXN_ELEMENTARY || t > KX_RXN_TROE)
+        if (t < KX_RXN_ELEMENTARY || t > KX_RXN_PLOG)
             return fail(KX_EINVAL, "kx_mech_create: unknown reaction type" + ri);
-        if (!(d->A[i] > 0.0) || !std::isfinite(d->beta[i]) || !std::isfinite(d->Ea[i]))
+        const bool falloff = t == KX_RXN_LINDEMANN || t == KX_RXN_TROE || t == KX_RXN_SRI;
+        if (t == KX_RXN_PLOG) {
+            if (!d->plog_ptr || !d->plog_p || !d->plog_A || !d->plog_beta || !d->plog_Ea)
+                return fail(KX_EINVAL, "kx_mech_create: NULL PLOG array" + ri);
+            const int b = d->plog_ptr[i], e = d->plog_ptr[i + 1];
+            if (b < 0 || e <= b)
+                return fail(KX_EINVAL, "kx_mech_create: PLOG reaction without pressures" + ri);
+            for (int j = b; j < e; ++j) {
+                if (!(d->plog_p[j] > 0.0) || !std::isfinite(d->plog_p[j]) ||
+                    (j > b && !(d->plog_p[j] > d->plog_p[j - 1])))
+                    return fail(KX_EINVAL, "kx_mech_create: PLOG pressures must be positive "
+                                           "and strictly increasing" + ri);
+                if (!(d->plog_A[j] > 0.0) || !std::isfinite(d->plog_A[j]) ||
+                    !std::isfinite(d->plog_beta[j]) || !std::isfinite(d->plog_Ea[j]))
+                    return fail(KX_EINVAL, "kx_mech_create: PLOG A must be > 0, beta and "
+                                           "Ea finite" + ri);
+            }
+        } else if (!(d->A[i] > 0.0) || !std::isfinite(d->A[i]) || !std::isfinite(d->beta[i]) ||
+                   !std::isfinite(d->Ea[i])) {
             return fail(KX_EINVAL, "kx_mech_create: A must be > 0, beta and Ea finite" + ri);
-        if (t >= KX_RXN_LINDEMANN &&
+        }
+        if (d->chem_act && d->chem_act[i] && !falloff)
+            return fail(KX_EINVAL, "kx_mech_create: chem_act on a reaction that is not a "
+                                   "falloff reaction" + ri);
+        if (t == KX_RXN_SRI) {
+            if (!d->sri) return fail(KX_EINVAL, "kx_mech_create: NULL sri array" + ri);
+            const double *q = d->sri + 5 * i;
+            for (int j = 0; j < 5; ++j)
+                if (!std::isfinite(q[j]))
+                    return fail(KX_EINVAL, "kx_mech_create: SRI parameters must be finite" + ri);
+            if (!(q[0] >= 0.0) || !(q[2] != 0.0) || !(q[3] > 0.0))
+                return fail(KX_EINVAL, "kx_mech_create: SRI needs a >= 0, c != 0, d > 0" + ri);
+        }
+        if (falloff &&
             (!(d->A0[i] > 0.0) || !std::isfinite(d->beta0[i]) || !std::isfinite(d->Ea0[i])))
             return fail(KX_EINVAL, "kx_mech_create: falloff A0 must be > 0" + ri);
         if (t == KX_RXN_TROE && (!(d->troe[4 * i + 1] != 0.0) || !(d->troe[4 * i + 2] != 0.0)))
@@ -129,7 +160,7 @@ kx_status validate(const kx_mech_desc *d, std::vector<double> &W)
         for (int el = 0; el < ne; ++el)
             if (bal[el] != 0)
                 return fail(KX_EINVAL, "kx_mech_create: reaction is not element-balanced" + ri);
-        if (t != KX_RXN_ELEMENTARY) {
+        if (t != KX_RXN_ELEMENTARY && t != KX_RXN_PLOG) {
             if (d->eff_ptr[i] < 0 || d->eff_ptr[i + 1] < d->eff_ptr[i])
                 return fail(KX_EINVAL, "kx_mech_create: bad efficiency CSR" + ri);
             for (int e = d->eff_ptr[i]; e < d->eff_ptr[i + 1]; ++e)
@@ -158,7 +189,9 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     // ---- reaction order: heaviest type first, constant-k_f last within a type
     std::vector<int> perm(nr);
     std::iota(perm.begin(), perm.end(), 0);
-    auto kfconst = [&](int i) { return d->beta[i] == 0.0 && d->Ea[i] == 0.0; };
+    auto kfconst = [&](int i) {
+        return d->rxn_type[i] != KX_RXN_PLOG && d->beta[i] == 0.0 && d->Ea[i] == 0.0;
+    };
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
         if (d->rxn_type[a] != d->rxn_type[b]) return d->rxn_type[a] > d->rxn_type[b];
         return !kfconst(a) && kfconst(b);
@@ -167,6 +200,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     std::vector<DevRxn> rx(nr);
     std::vector<DevAux> aux;
     std::vector<DevEff> eff;
+    std::vector<DevPlog> plog;
     for (int s = 0; s < nr; ++s) {
         const int i = perm[s];
         DevRxn r;
@@ -184,21 +218,29 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
         for (int e = d->prod_ptr[i]; e < d->prod_ptr[i + 1]; ++e)
             for (int v = 0; v < d->prod_nu[e]; ++v) r.poff[c++] = (uint16_t)(16 * d->prod_sp[e]);
         r.type = (uint8_t)d->rxn_type[i];
-        r.flags = (d->reversible[i] ? kFlagReversible : 0) | (kfconst(i) ? kFlagKfConst : 0);
+        r.flags = (d->reversible[i] ? kFlagReversible : 0) | (kfconst(i) ? kFlagKfConst : 0) |
+                  (d->chem_act && d->chem_act[i] ? kFlagChemAct : 0);
+        if (r.type == KX_RXN_PLOG) {  // k_f comes from the pressure table
+            r.lnA = 0.0;
+            r.beta = r.ER = 0.0;
+            r.A = 1.0;
+        }
         r.aux = 0xFFFF;
         if (r.type != KX_RXN_ELEMENTARY) {
             if (aux.size() >= 0xFFFF)
-                return fail(KX_EUNSUPPORTED, "kx_mech_create: too many third-body reactions");
+                return fail(KX_EUNSUPPORTED, "kx_mech_create: too many non-elementary reactions");
             DevAux a;
             std::memset(&a, 0, sizeof a);
-            a.eff_default = d->eff_default[i];
+            const bool collider = r.type != KX_RXN_PLOG;
+            a.eff_default = collider ? d->eff_default[i] : 0.0;
             for (int q = 0; q < kInlineEff; ++q) {
                 a.eoff[q] = (uint16_t)(16 * ns);  // dummy species, alpha - default = 0
                 a.dalpha[q] = 0.0;
             }
             int q = 0;
             a.ext_off = (int32_t)eff.size();
-            for (int e = d->eff_ptr[i]; e < d->eff_ptr[i + 1]; ++e) {
+            const int e0 = collider ? d->eff_ptr[i] : 0, e1 = collider ? d->eff_ptr[i + 1] : 0;
+            for (int e = e0; e < e1; ++e) {
                 const double da = d->eff_val[e] - d->eff_default[i];
                 if (q < kInlineEff) {
                     a.eoff[q] = (uint16_t)(16 * d->eff_sp[e]);
@@ -213,17 +255,40 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
                 }
             }
             a.ext_cnt = (int32_t)eff.size() - a.ext_off;
-            if (r.type >= KX_RXN_LINDEMANN) {
+            if (r.type == KX_RXN_LINDEMANN || r.type == KX_RXN_TROE || r.type == KX_RXN_SRI) {
                 a.lnA0 = std::log(d->A0[i]);
                 a.beta0 = d->beta0[i];
                 a.ER0 = d->Ea0[i] / kRcal;
             }
             if (r.type == KX_RXN_TROE) {
-                a.troe_alpha = d->troe[4 * i + 0];
-                a.troe_inv_T3 = 1.0 / d->troe[4 * i + 1];
-                a.troe_inv_T1 = 1.0 / d->troe[4 * i + 2];
+                a.fp[0] = d->troe[4 * i + 0];
+                a.fp[1] = 1.0 / d->troe[4 * i + 1];
+                a.fp[2] = 1.0 / d->troe[4 * i + 2];
                 a.has_T2 = std::isnan(d->troe[4 * i + 3]) ? 0 : 1;
-                a.troe_T2 = a.has_T2 ? d->troe[4 * i + 3] : 0.0;
+                a.fp[3] = a.has_T2 ? d->troe[4 * i + 3] : 0.0;
+            }
+            if (r.type == KX_RXN_SRI) {
+                const double *q = d->sri + 5 * i;
+                a.fp[0] = q[0];
+                a.fp[1] = q[1];
+                a.fp[2] = 1.0 / q[2];
+                a.fp[3] = std::log(q[3]);
+                a.fp[4] = q[4];
+            }
+            if (r.type == KX_RXN_PLOG) {
+                a.plog_off = (int32_t)plog.size();
+                a.plog_cnt = d->plog_ptr[i + 1] - d->plog_ptr[i];
+                for (int j = d->plog_ptr[i]; j < d->plog_ptr[i + 1]; ++j) {
+                    DevPlog e;
+                    std::memset(&e, 0, sizeof e);
+                    e.lnp = std::log(d->plog_p[j]);
+                    e.lnA = std::log(d->plog_A[j]);
+                    e.beta = d->plog_beta[j];
+                    e.ER = d->plog_Ea[j] / kRcal;
+                    e.inv_dlnp = j + 1 < d->plog_ptr[i + 1]
+                                     ? 1.0 / (std::log(d->plog_p[j + 1]) - e.lnp) : 0.0;
+                    plog.push_back(e);
+                }
             }
             r.aux = (uint16_t)aux.size();
             aux.push_back(a);
@@ -232,6 +297,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     }
     if (eff.empty()) eff.resize(1);
     if (aux.empty()) aux.resize(1);
+    if (plog.empty()) plog.resize(1);
 
     // ---- species-major gather lists per reaction chunk.  Each species lists
     // the chunk slots of the reactions that produce it (+q, once per unit of
@@ -371,6 +437,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
 
     Blob b;
     const size_t o_rxn = add_vec(b, rx), o_aux = add_vec(b, aux), o_eff = add_vec(b, eff);
+    const size_t o_plog = add_vec(b, plog);
     const size_t o_sp = add_vec(b, spv), o_gpos = add_vec(b, gpos), o_gneg = add_vec(b, gneg);
     const size_t o_goff = add_vec(b, goff);
     const size_t o_gent = add_vec(b, gent);
@@ -429,6 +496,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     v.rxn = (const DevRxn *)at(o_rxn);
     v.aux = (const DevAux *)at(o_aux);
     v.eff = (const DevEff *)at(o_eff);
+    v.plog = (const DevPlog *)at(o_plog);
     v.sp = (const DevSpecies *)at(o_sp);
     v.gpos = (const int32_t *)at(o_gpos);
     v.gneg = (const int32_t *)at(o_gneg);

@@ -57,37 +57,62 @@ __device__ __forceinline__ double exp_mixed(double x)
     return ldexp((double)er, (int)nd);
 }
 
-// Troe blending factor (eq:blend).  The base-10 logarithms of the paper are
-// formed from natural ones: log10 F_cent = ln F_cent / ln 10, and
-// F = 10^(log10 F_cent / (1 + f1^2)) = exp(ln F_cent / (1 + f1^2)).
-__device__ __forceinline__ double troe_F64(const DevAux &ax, double T, double invT, double lnPr)
+// Falloff blending factor F (eq:blend), Troe and SRI in one code path (so a
+// wave mixing the two runs it once):
+//   Troe  log10 F = log10 F_cent / (1 + f1^2), f1 = (l + c) / (n - 0.14 (l + c)),
+//         F_cent = (1 - alpha) e^(-T/T***) + alpha e^(-T/T*) [+ e^(-T**/T)],
+//         c = -0.4 - 0.67 log10 F_cent, n = 0.75 - 1.27 log10 F_cent;
+//   SRI   F = d T^e B^X, B = a e^(-b/T) + e^(-T/c), X = 1 / (1 + l^2),
+// with l = log10 P_r.  Both are ln F = ln B / (1 + w^2) + extra, where B is
+// F_cent or the SRI bracket, w = f1 or l, and extra = 0 or ln d + e ln T.  The
+// base-10 logarithms are formed from natural ones.
+__device__ __forceinline__ double blend_F64(const DevAux &ax, bool sri, double T, double lnT,
+                                            double invT, double lnPr)
 {
     constexpr double kInvLn10 = 0.43429448190325182765;
-    double Fc = (1.0 - ax.troe_alpha) * kexp(-T * ax.troe_inv_T3) +
-                ax.troe_alpha * kexp(-T * ax.troe_inv_T1);
-    if (ax.has_T2) Fc += kexp(-ax.troe_T2 * invT);
-    const double lnFc = kln(Fc);
-    const double lFc = lnFc * kInvLn10;
-    const double c = -0.4 - 0.67 * lFc;
-    const double nn = 0.75 - 1.27 * lFc;
-    const double x = fma(lnPr, kInvLn10, c);
-    const double f1 = x * krcp(nn - 0.14 * x);
-    return kexp(lnFc * krcp(fma(f1, f1, 1.0)));
+    const double a0 = ax.fp[0], a1 = ax.fp[1], a2 = ax.fp[2], a3 = ax.fp[3], a4 = ax.fp[4];
+    double B = (sri ? a0 : 1.0 - a0) * kexp(-a1 * (sri ? invT : T)) +
+               (sri ? 1.0 : a0) * kexp(-T * a2);
+    if (!sri && ax.has_T2) B += kexp(-a3 * invT);
+    const double lnB = kln(fmax(B, DBL_MIN));
+    const double lB = lnB * kInvLn10;
+    const double x = fma(lnPr, kInvLn10, sri ? 0.0 : fma(-0.67, lB, -0.4));
+    const double nn = sri ? 1.0 : fma(-1.27, lB, 0.75);
+    const double w = x * krcp(fma(sri ? 0.0 : -0.14, x, nn));
+    return kexp(fma(lnB, krcp(fma(w, w, 1.0)), sri ? fma(a4, lnT, a3) : 0.0));
 }
 
-// FP32 Troe blend from log10 P_r (computed by the caller without overflow).
-__device__ __forceinline__ float troe_F32(const DevAux &ax, float T, float invT, float lPr)
+// The same in FP32 from l = log10 P_r (computed by the caller without overflow).
+__device__ __forceinline__ float blend_F32(const DevAux &ax, bool sri, float T, float lnT,
+                                           float invT, float lPr)
 {
-    const float al = (float)ax.troe_alpha;
-    float Fc = (1.0f - al) * __expf(-T * (float)ax.troe_inv_T3) +
-               al * __expf(-T * (float)ax.troe_inv_T1);
-    if (ax.has_T2) Fc += __expf(-(float)ax.troe_T2 * invT);
-    const float lFc = log10f(Fc);
-    const float c = -0.4f - 0.67f * lFc;
-    const float nn = 0.75f - 1.27f * lFc;
-    const float x = lPr + c;
-    const float f1 = x / (nn - 0.14f * x);
-    return exp10f(lFc / (1.0f + f1 * f1));
+    const float a0 = (float)ax.fp[0], a1 = (float)ax.fp[1], a2 = (float)ax.fp[2];
+    const float a3 = (float)ax.fp[3], a4 = (float)ax.fp[4];
+    float B = (sri ? a0 : 1.0f - a0) * __expf(-a1 * (sri ? invT : T)) +
+              (sri ? 1.0f : a0) * __expf(-T * a2);
+    if (!sri && ax.has_T2) B += __expf(-a3 * invT);
+    const float lnB = __logf(fmaxf(B, FLT_MIN));
+    const float lB = lnB * 0.43429448190325182765f;
+    const float x = lPr + (sri ? 0.0f : -0.4f - 0.67f * lB);
+    const float nn = sri ? 1.0f : 0.75f - 1.27f * lB;
+    const float w = x / (nn - (sri ? 0.0f : 0.14f) * x);
+    return __expf(lnB / (1.0f + w * w) + (sri ? a4 * lnT + a3 : 0.0f));
+}
+
+// Exponent ln k_f of a pressure-table reaction at ln p: linear in ln p between
+// the neighbouring reference pressures, the nearest end point's value outside
+// them (App. A.2, pressure-dependent reactions).
+__device__ __forceinline__ double plog_exponent(const DevPlog *pl, int cnt, double lnT,
+                                                double invT, double lnp)
+{
+    int j = 0;
+    while (j + 1 < cnt && pl[j + 1].lnp <= lnp) ++j;
+    const DevPlog &a = pl[j];
+    const double x1 = fma(a.beta, lnT, fma(-a.ER, invT, a.lnA));
+    if (j + 1 >= cnt || lnp <= a.lnp) return x1;
+    const DevPlog &b = pl[j + 1];
+    const double x2 = fma(b.beta, lnT, fma(-b.ER, invT, b.lnA));
+    return fma(x2 - x1, (lnp - a.lnp) * a.inv_dlnp, x1);
 }
 
 // log10 of a positive double over its whole range, in FP32 arithmetic.
@@ -153,7 +178,8 @@ __device__ __forceinline__ double third_body(const MechDev &m, const DevAux &ax,
 template <bool MIXED>
 __device__ __forceinline__ double rate_of_progress(const MechDev &m, const RxnWords &w,
                                                    const char *__restrict__ pb, double Ti,
-                                                   double lnT, double invT, double Mconc)
+                                                   double lnT, double invT, double Mconc,
+                                                   double lnp)
 {
     const double lnA = as_double(w.w0.x, w.w0.y);
     const double beta = as_double(w.w0.z, w.w0.w);
@@ -163,14 +189,19 @@ __device__ __forceinline__ double rate_of_progress(const MechDev &m, const RxnWo
     const unsigned flags = (w.w2.w >> 8) & 0xFFu;
     const unsigned aux = w.w2.w >> 16;
 
-    // the LDS reads go first so that their latency hides behind the exponential
+    // exponent of k_f (eq:k_f); k_f = A without an exponential when beta = E_R = 0
+    // (such reactions are sorted together, so the branch is mostly wave-uniform),
+    // or interpolated in ln p for a pressure-table reaction
+    const bool kconst = (flags & kFlagKfConst) != 0;
+    double xf = kconst ? lnA : fma(beta, lnT, fma(-ER, invT, lnA));
+    if (type == KX_RXN_PLOG) {
+        const DevAux &ax = m.aux[aux];
+        xf = plog_exponent(m.plog + ax.plog_off, ax.plog_cnt, lnT, invT, lnp);
+    }
+    // the LDS reads go before the exponential so that their latency hides behind it
     const Pair r0 = load_pair(pb, w.w2.x & 0xFFFFu);
     const Pair r1 = load_pair(pb, w.w2.x >> 16);
     const double bp0 = load_b(pb, w.w2.y >> 16), bp1 = load_b(pb, w.w2.z & 0xFFFFu);
-    // exponent of k_f (eq:k_f); k_f = A without an exponential when beta = E_R = 0
-    // (such reactions are sorted together, so the branch is mostly wave-uniform)
-    const bool kconst = (flags & kFlagKfConst) != 0;
-    const double xf = kconst ? lnA : fma(beta, lnT, fma(-ER, invT, lnA));
     double kf = A;
     if (!kconst) kf = MIXED ? exp_mixed(xf) : kexp(xf);
     double Ap = r0.a * r1.a;
@@ -187,25 +218,31 @@ __device__ __forceinline__ double rate_of_progress(const MechDev &m, const RxnWo
         Bpp *= load_b(pb, o5);
     }
     double c = 1.0;
-    if (type != KX_RXN_ELEMENTARY) {
+    if (type != KX_RXN_ELEMENTARY && type != KX_RXN_PLOG) {
         const DevAux &ax = m.aux[aux];
         const double X = third_body(m, ax, pb, Mconc);
         c = X;
         if (type != KX_RXN_THREEBODY) {
-            // P_r = k_0 [X] / k_inf = exp(x_0 - x_inf) [X] (no division)
+            // P_r = k_0 [X] / k_inf = e0 [X] with e0 = exp(x_0 - x_inf) (no division)
             const double d0 = fma(ax.beta0, lnT, fma(-ax.ER0, invT, ax.lnA0)) - xf;
-            const double Pr = (MIXED ? exp_mixed(d0) : kexp(d0)) * X;
+            const double e0 = MIXED ? exp_mixed(d0) : kexp(d0);
+            const double Pr = e0 * X;
             double F = 1.0;
-            if (type == KX_RXN_TROE) {
+            if (type == KX_RXN_TROE || type == KX_RXN_SRI) {
+                const bool sri = type == KX_RXN_SRI;
                 if (MIXED) {
-                    F = (double)troe_F32(ax, (float)Ti, (float)invT, log10_wide(Pr));
+                    F = (double)blend_F32(ax, sri, (float)Ti, (float)lnT, (float)invT,
+                                          log10_wide(Pr));
                 } else {
                     // ln max(P_r, DBL_MIN) without forming the logarithm of P_r
                     const double lnPr = fmax(d0 + kln(fmax(X, DBL_MIN)), -708.39641853226410622);
-                    F = troe_F64(ax, Ti, invT, lnPr);
+                    F = blend_F64(ax, sri, Ti, lnT, invT, lnPr);
                 }
             }
-            c = Pr * krcp(1.0 + Pr) * F;
+            // eq:c_i: P_r/(1+P_r) F; chemically activated: F/(1+P_r) with k_0 =
+            // e0 k_inf in r_i, i.e. c k_inf = e0 F/(1+P_r) k_inf
+            const double g = krcp(1.0 + Pr) * F;
+            c = (flags & kFlagChemAct) ? e0 * g : Pr * g;
         }
     }
     const double rev = (flags & kFlagReversible) ? 1.0 : 0.0;
@@ -242,7 +279,7 @@ __host__ __device__ constexpr int rates_tile_points_for(int spl) { return spl ==
 struct PointConst {
     double T, lnT, invT, M;  // temperature, ln T, 1/T, [M] = p / RT
     double P0, cf;           // p_atm / RT; C_k = Y_k / W_k * cf with cf = [M] W-bar
-    double pad[2];
+    double lnp, pad;         // ln p (pressure-table reactions)
 };
 
 // LDS layout of one workgroup (one wave):
@@ -310,7 +347,8 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
         q.M = P[i] * invRT;
         q.P0 = kPatm * invRT;
         q.cf = q.M * krcp(wsum);
-        q.pad[0] = q.pad[1] = 0.0;
+        q.lnp = kln(P[i]);
+        q.pad = 0.0;
         pc[lane] = q;
     }
     __syncthreads();
@@ -346,7 +384,7 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
         wave_sync();
         // the point of this lane in phase 2
         const PointConst &ql = pc[pl + jl];
-        const double Tl = ql.T, lnTl = ql.lnT, invTl = ql.invT, Ml = ql.M;
+        const double Tl = ql.T, lnTl = ql.lnT, invTl = ql.invT, Ml = ql.M, lnpl = ql.lnp;
 
         // ---- phases 2 and 3, one chunk of reactions at a time
         double acc[SPL][2], cmp[SPL][2];
@@ -373,7 +411,7 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
                     w.w1 = rsrc[3 * rn + 1];
                     w.w2 = rsrc[3 * rn + 2];
                 }
-                sq[2 * r + jl] = rate_of_progress<MIXED>(m, cur, pbl, Tl, lnTl, invTl, Ml);
+                sq[2 * r + jl] = rate_of_progress<MIXED>(m, cur, pbl, Tl, lnTl, invTl, Ml, lnpl);
             }
             wave_sync();
             const int npos = m.gpos[c], ngrp = npos + m.gneg[c];

@@ -49,7 +49,7 @@ FIT_ORDER = 5
 FIT_L0 = 0.5 * (math.log(T_FIT_LO) + math.log(T_FIT_HI))
 FIT_H = 0.5 * (math.log(T_FIT_HI) - math.log(T_FIT_LO))
 
-RXN_ELEMENTARY, RXN_THREEBODY, RXN_LINDEMANN, RXN_TROE = 0, 1, 2, 3
+RXN_ELEMENTARY, RXN_THREEBODY, RXN_LINDEMANN, RXN_TROE, RXN_SRI, RXN_PLOG = 0, 1, 2, 3, 4, 5
 
 
 # --------------------------------------------------------------------------
@@ -314,6 +314,12 @@ class MechSpec:
     diff_fit_kind: int = 1
     name: str = ""
     extra: dict = field(default_factory=dict)
+    # further reaction forms (App. A.2), made by converting reactions of the
+    # base mechanism after all of its draws (the base arrays are unchanged):
+    # Troe -> SRI, falloff -> chemically activated, elementary -> PLOG
+    n_sri: int = 0
+    n_chemact: int = 0
+    n_plog: int = 0
 
     @property
     def n_reactions(self) -> int:
@@ -325,6 +331,10 @@ class MechSpec:
 MECH_9 = MechSpec(9, 17, 3, 0, 1, seed=9021, name="syn9")
 MECH_53 = MechSpec(53, 266, 30, 0, 29, seed=53325, name="syn53")
 MECH_200 = MechSpec(200, 1200, 180, 30, 90, seed=2001500, name="syn200")
+# syn53 with part of its reactions in the further forms: 10 SRI, 8 chemically
+# activated falloff, 20 pressure-table (PLOG) reactions
+MECH_53X = MechSpec(53, 266, 30, 0, 29, seed=53325, name="syn53x", n_sri=10, n_chemact=8,
+                    n_plog=20)
 
 
 def make_mechanism(spec: MechSpec) -> dict:
@@ -480,6 +490,46 @@ def make_mechanism(spec: MechSpec) -> dict:
     diff_fit[iu] = dfit_u
     diff_fit[(iu[1], iu[0])] = dfit_u
 
+    sri = chem_act = plog = None
+    if spec.n_sri or spec.n_chemact or spec.n_plog:
+        rng2 = np.random.Generator(np.random.PCG64(spec.seed + 7777))
+        troe_ids = np.flatnonzero(rtype == RXN_TROE)
+        if spec.n_sri > len(troe_ids):
+            raise ValueError("n_sri exceeds the number of Troe reactions")
+        sri = np.zeros((nr, 5))
+        for i in rng2.choice(troe_ids, size=spec.n_sri, replace=False):
+            rtype[i] = RXN_SRI
+            troe[i] = 0.0
+            # a, b (K), c (K; a very large c drops the second term to 1), d, e
+            sri[i] = (rng2.uniform(0.1, 2.0), rng2.uniform(0.0, 2000.0),
+                      rng2.uniform(100.0, 3000.0) if rng2.random() < 0.7 else 1e30,
+                      rng2.uniform(0.5, 2.0), rng2.uniform(-0.5, 0.5))
+        falloff = np.flatnonzero((rtype == RXN_LINDEMANN) | (rtype == RXN_TROE)
+                                 | (rtype == RXN_SRI))
+        if spec.n_chemact > len(falloff):
+            raise ValueError("n_chemact exceeds the number of falloff reactions")
+        chem_act = np.zeros(nr, np.int32)
+        chem_act[rng2.choice(falloff, size=spec.n_chemact, replace=False)] = 1
+        elem_ids = np.flatnonzero(rtype == RXN_ELEMENTARY)
+        if spec.n_plog > len(elem_ids):
+            raise ValueError("n_plog exceeds the number of elementary reactions")
+        conv = set(rng2.choice(elem_ids, size=spec.n_plog, replace=False).tolist())
+        pptr, pp, pA, pb, pE = [0], [], [], [], []
+        for i in range(nr):
+            if i in conv:
+                rtype[i] = RXN_PLOG
+                npt = int(rng2.integers(1, 5))
+                pres = np.sort(10.0 ** rng2.uniform(-1.0, 2.0, npt)) * P_ATM
+                pres = np.unique(pres)
+                for q in pres:
+                    pp.append(q)
+                    pA.append(A[i] * 10.0 ** rng2.uniform(-1.0, 1.0))
+                    pb.append(beta[i] + rng2.uniform(-0.3, 0.3))
+                    pE.append(Ea[i] * rng2.uniform(0.8, 1.2))
+            pptr.append(len(pp))
+        plog = {"plog_ptr": np.array(pptr, np.int32), "plog_p": np.array(pp),
+                "plog_A": np.array(pA), "plog_beta": np.array(pb), "plog_Ea": np.array(pE)}
+
     return {
         "name": spec.name,
         "n_species": ns,
@@ -508,6 +558,11 @@ def make_mechanism(spec: MechSpec) -> dict:
         "visc_fit": visc_fit,
         "cond_fit": cond_fit,
         "diff_fit": diff_fit,
+        "sri": sri,
+        "chem_act": chem_act,
+        **(plog if plog is not None else
+           {"plog_ptr": None, "plog_p": None, "plog_A": None, "plog_beta": None,
+            "plog_Ea": None}),
         # generator metadata (not part of the descriptor)
         "_h298_over_r": h298,
         "_s298_over_r": s298,

@@ -47,6 +47,8 @@ class _Desc(C.Structure):
         ("eff_default", _dp), ("fit_order", C.c_int32), ("fit_L0", C.c_double),
         ("fit_h", C.c_double), ("diff_fit_kind", C.c_int32),
         ("visc_fit", _dp), ("cond_fit", _dp), ("diff_fit", _dp),
+        ("sri", _dp), ("chem_act", _ip), ("plog_ptr", _ip), ("plog_p", _dp),
+        ("plog_A", _dp), ("plog_beta", _dp), ("plog_Ea", _dp),
     ]
 
 
@@ -54,6 +56,10 @@ _F64_FIELDS = ["elem_mass", "nasa_lo", "nasa_hi", "t_mid", "A", "beta", "Ea", "A
                "Ea0", "troe", "eff_val", "eff_default", "visc_fit", "cond_fit", "diff_fit"]
 _I32_FIELDS = ["composition", "rxn_type", "reversible", "reac_ptr", "reac_sp", "reac_nu",
                "prod_ptr", "prod_sp", "prod_nu", "eff_ptr", "eff_sp"]
+
+# Optional arrays of the further reaction forms (NULL when a mechanism has none).
+_OPT_F64_FIELDS = ["sri", "plog_p", "plog_A", "plog_beta", "plog_Ea"]
+_OPT_I32_FIELDS = ["chem_act", "plog_ptr"]
 
 _lib = None
 
@@ -113,6 +119,16 @@ def make_desc(mech: dict):
             a = np.zeros(1, np.int32)
         keep[k] = a
         setattr(d, k, a.ctypes.data_as(_ip))
+    for k, dt, ptr in ([(k, np.float64, _dp) for k in _OPT_F64_FIELDS] +
+                       [(k, np.int32, _ip) for k in _OPT_I32_FIELDS]):
+        if mech.get(k) is None:
+            setattr(d, k, None)
+            continue
+        a = np.ascontiguousarray(mech[k], dtype=dt)
+        if a.size == 0:
+            a = np.zeros(1, dt)
+        keep[k] = a
+        setattr(d, k, a.ctypes.data_as(ptr))
     d.fit_order = int(mech["fit_order"])
     d.fit_L0 = float(mech["fit_L0"])
     d.fit_h = float(mech["fit_h"])

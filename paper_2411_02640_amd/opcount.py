@@ -23,7 +23,8 @@ PRICE = {"exp": 24, "log": 24, "div": 8, "sqrt": 8}
 def rates_ops(mech: dict) -> dict:
     ns, nr = mech["n_species"], mech["n_reactions"]
     t = mech["rxn_type"]
-    kfconst = (mech["beta"] == 0) & (mech["Ea"] == 0)
+    kfconst = (mech["beta"] == 0) & (mech["Ea"] == 0) & (t != 5)
+    plog_ptr = mech.get("plog_ptr")
     c = dict(fma=0, mul=0, add=0, exp=0, log=0, div=0, sqrt=0)
     # mixture basics: sum Y/W (fma), C_k (2 mul), one division; ln T, 1/T
     c["fma"] += ns
@@ -45,16 +46,27 @@ def rates_ops(mech: dict) -> dict:
         nu_p = int(mech["prod_nu"][p].sum())
         c["mul"] += 2 * nu_r + nu_p + 3      # A', B', B'', c * kf * A' * bracket
         c["add"] += 1                        # bracket
-        if t[i] != 0:
+        if t[i] == 5:  # pressure table: two Arrhenius exponents and a lerp in ln p
+            if plog_ptr[i + 1] - plog_ptr[i] > 1:
+                c["fma"] += 3
+                c["mul"] += 1
+                c["add"] += 2
+        if t[i] in (1, 2, 3, 4):
             ne = mech["eff_ptr"][i + 1] - mech["eff_ptr"][i]
             c["mul"] += 1 + ne
             c["fma"] += ne
-        if t[i] >= 2:
+        if t[i] in (2, 3, 4):
             c["fma"] += 2
             c["exp"] += 1
             c["mul"] += 2
             c["div"] += 2
             c["add"] += 1
+        if t[i] == 4:  # SRI: two exps, a log and the final exp
+            c["exp"] += 3
+            c["log"] += 1
+            c["fma"] += 4
+            c["mul"] += 3
+            c["div"] += 1
         if t[i] == 3:
             c["exp"] += 3 if not np.isnan(mech["troe"][i, 3]) else 2
             c["log"] += 2

@@ -16,7 +16,8 @@ def pytest_configure(config):
 @functools.lru_cache(maxsize=None)
 def _mech(name):
     from paper_2411_02640_amd import inputs as I
-    spec = {"syn9": I.MECH_9, "syn53": I.MECH_53, "syn200": I.MECH_200}[name]
+    spec = {"syn9": I.MECH_9, "syn53": I.MECH_53, "syn200": I.MECH_200,
+            "syn53x": I.MECH_53X}[name]
     return I.make_mechanism(spec)
 
 
@@ -33,6 +34,11 @@ def mech53():
 @pytest.fixture(scope="session")
 def mech200():
     return _mech("syn200")
+
+
+@pytest.fixture(scope="session")
+def mech53x():
+    return _mech("syn53x")
 
 
 @pytest.fixture(scope="session")

@@ -37,7 +37,7 @@ def test_version():
     assert "gfx950" in kx.version()
 
 
-@pytest.mark.parametrize("name", ["mech9", "mech53", "mech200"])
+@pytest.mark.parametrize("name", ["mech9", "mech53", "mech200", "mech53x"])
 def test_host_create(name, request):
     mech = request.getfixturevalue(name)
     m = kx.HostMechanism(mech)
@@ -159,3 +159,44 @@ def test_null_arguments():
     L2 = kx._serve_lib()
     assert L2.kx_mech_create_host(C.byref(d), None) == kx.KX_EINVAL
     assert L.kx_mech_destroy(None) == kx.KX_OK
+
+
+def _one(rtype, **kw):
+    base = dict(A=1e12, beta=0.0, Ea=100.0, A0=1e16, beta0=0.0, Ea0=0.0)
+    base.update(kw)
+    return tiny_mechs.single_reaction_mech(rtype, **base)
+
+
+def test_further_reaction_forms_accepted():
+    for m in (_one(4, sri=[0.5, 300.0, 900.0, 1.0, 0.0]),
+              _one(3, troe=(0.5, 100.0, 1000.0, np.nan), chem_act=1),
+              _one(5, plog=[(1e5, 1e12, 0.0, 0.0), (1e7, 2e12, 0.1, 50.0)]),
+              _one(5, A=0.0, plog=[(1e6, 1e12, 0.0, 0.0)])):
+        kx.HostMechanism(m).close()
+
+
+def test_reject_bad_sri_parameters():
+    _expect(_one(4, sri=[0.5, 300.0, 0.0, 1.0, 0.0]), kx.KX_EINVAL, "SRI needs")
+    _expect(_one(4, sri=[0.5, 300.0, 900.0, 0.0, 0.0]), kx.KX_EINVAL, "SRI needs")
+    _expect(_one(4, sri=[-0.1, 300.0, 900.0, 1.0, 0.0]), kx.KX_EINVAL, "SRI needs")
+    _expect(_one(4, sri=[0.5, np.inf, 900.0, 1.0, 0.0]), kx.KX_EINVAL, "finite")
+    m = _one(4, sri=[0.5, 300.0, 900.0, 1.0, 0.0])
+    m["sri"] = None
+    _expect(m, kx.KX_EINVAL, "NULL sri")
+
+
+def test_reject_bad_pressure_tables():
+    _expect(_one(5, plog=[(1e7, 1e12, 0.0, 0.0), (1e5, 2e12, 0.0, 0.0)]), kx.KX_EINVAL,
+            "strictly increasing")
+    _expect(_one(5, plog=[(1e6, 1e12, 0.0, 0.0), (1e6, 2e12, 0.0, 0.0)]), kx.KX_EINVAL,
+            "strictly increasing")
+    _expect(_one(5, plog=[(-1.0, 1e12, 0.0, 0.0)]), kx.KX_EINVAL, "strictly increasing")
+    _expect(_one(5, plog=[(1e6, 0.0, 0.0, 0.0)]), kx.KX_EINVAL, "PLOG A must be > 0")
+    m = _one(5, plog=[(1e6, 1e12, 0.0, 0.0)])
+    m["plog_ptr"] = np.array([0, 0], np.int32)
+    _expect(m, kx.KX_EINVAL, "without pressures")
+
+
+def test_reject_chem_act_on_non_falloff():
+    _expect(_one(0, chem_act=1), kx.KX_EINVAL, "chem_act")
+    _expect(_one(1, chem_act=1), kx.KX_EINVAL, "chem_act")

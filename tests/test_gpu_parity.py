@@ -151,6 +151,26 @@ def test_special_case_mechanism(kx):
     check_rates(kx, m, T, p, Y, "special cases")
 
 
+def test_further_reaction_forms(kx, mech53x):
+    """SRI falloff, chemically activated falloff (Lindemann-free Troe and SRI)
+    and pressure-table reactions (syn53x: 10 SRI, 8 chemically activated, 20
+    PLOG), FP64 and mixed, at pressures from below to above the tables'
+    reference pressures (0.1-100 atm), with a ragged tail; and
+    near-equilibrium states, where the net rate is a small difference."""
+    T, p, Y = I.make_states(53, I.StateSpec(4096 + 11, seed=41, p_atm_range=(0.02, 300.0),
+                                            dirichlet_alpha=0.3))
+    check_rates(kx, mech53x, T, p, Y, "further forms")
+    dm = dev_mech(kx, mech53x)
+    w = run_rates(kx, dm, T, p, Y, precision="mixed")
+    ref, sc = O.OracleMech(mech53x).production_rates(T, p, Y)
+    r = PM.mixed_wdot_report(w, ref, sc)
+    _say("  mixed", r)
+    assert r["ok"], r
+    om = O.OracleMech(mech53x)
+    Te, pe, Ye = O.equilibrium_states(om, 1024, seed=43, perturb=1e-6)
+    check_rates(kx, mech53x, Te, pe, Ye, "further forms near equilibrium")
+
+
 def test_diffusion_fit_kind_direct(kx):
     """Tables holding fits of D_kj itself (diff_fit_kind = 0): the vector-ALU
     transport kernel with a reciprocal per pair, FP64 and mixed."""

@@ -77,7 +77,7 @@ def test_mixture_thermo(mech9):
 
 
 # ----------------------------------------------------------------- kinetics (A.2)
-@pytest.mark.parametrize("name", ["mech9", "mech53"])
+@pytest.mark.parametrize("name", ["mech9", "mech53", "mech53x"])
 def test_element_and_mass_conservation(name, request):
     """sum_k a_ke wdot_k = 0 and sum_k W_k wdot_k = 0 (every reaction balanced):
     catches a flipped side, a wrong nu or a mis-indexed species."""
@@ -95,7 +95,7 @@ def test_element_and_mass_conservation(name, request):
     assert (w[-1] == 0.0).all()  # the inert diluent
 
 
-@pytest.mark.parametrize("name", ["mech9", "mech53"])
+@pytest.mark.parametrize("name", ["mech9", "mech53", "mech53x"])
 def test_zero_net_rate_at_constructed_equilibrium(name, request):
     """At C_k = (p_atm/RT) exp(-G_k/RT + sum_e lam_e a_ke) every reaction has
     q_f = q_r (eq:K_p, K_c = K_p (p_atm/RT)^sum nu): catches a sign of dG, a
@@ -182,6 +182,87 @@ def test_troe_blend_closed_forms(oracle_lib):
     lfc = math.log10(1.5)
     c = -0.4 - 0.67 * lfc
     assert O.troe_F(three_half, T, 10.0 ** (-c)) == pytest.approx(1.5, rel=1e-14)
+
+
+def test_sri_blend_closed_forms(oracle_lib):
+    """eq:blend, SRI form, X = 1/(1 + log10(P_r)^2): with a = 1, b = 0 and
+    c -> inf the bracket is 2, so F = 2 at P_r = 1, sqrt(2) at P_r = 10 and 0.1
+    and 2^(1/5) at P_r = 100 (a natural log in X would give 2^0.159 at
+    P_r = 10); F -> 1 far from the centre; b, c, d and e enter as
+    a exp(-b/T), exp(-T/c) and d T^e."""
+    T = 1300.0
+    p = [1.0, 0.0, 1e300, 1.0, 0.0]
+    assert O.sri_F(p, T, 1.0) == pytest.approx(2.0, rel=1e-15)
+    assert O.sri_F(p, T, 10.0) == pytest.approx(math.sqrt(2.0), rel=1e-15)
+    assert O.sri_F(p, T, 0.1) == pytest.approx(math.sqrt(2.0), rel=1e-15)
+    assert O.sri_F(p, T, 100.0) == pytest.approx(2.0 ** 0.2, rel=1e-15)
+    assert O.sri_F(p, T, 1e300) == pytest.approx(1.0, abs=1e-4)
+    b_half = [4.0, T * math.log(2.0), 1e300, 1.0, 0.0]  # 4 e^{-ln 2} + 1 = 3
+    assert O.sri_F(b_half, T, 1.0) == pytest.approx(3.0, rel=1e-14)
+    c_half = [0.0, 0.0, T / math.log(2.0), 1.0, 0.0]  # e^{-ln 2} = 1/2
+    assert O.sri_F(c_half, T, 1.0) == pytest.approx(0.5, rel=1e-14)
+    de = [1.0, 0.0, 1e300, 3.0, 1.0]
+    assert O.sri_F(de, T, 10.0) == pytest.approx(3.0 * T * math.sqrt(2.0), rel=1e-14)
+
+
+def test_pressure_table_interpolation():
+    """App. A.2 pressure-dependent reactions: at a reference pressure k_f is that
+    pressure's Arrhenius rate (the same as an elementary reaction with those
+    parameters); ln k_f is linear in ln p, so at ln p a fraction f of the way
+    between neighbours k_f = k_j^(1-f) k_(j+1)^f (linear interpolation in p or
+    in k fails this); outside the table the end points' rates hold."""
+    T = 1100.0
+    pts = [(0.5 * O.PATM, 2e12, 0.3, 4000.0), (3.0 * O.PATM, 9e12, -0.2, 6000.0),
+           (40.0 * O.PATM, 5e13, 0.1, 9000.0)]
+    om = O.OracleMech(TM.single_reaction_mech(5, plog=pts))
+    ref = [O.OracleMech(TM.single_reaction_mech(0, A=a, beta=b, Ea=e)).rate_constants(T)[0][0]
+           for _, a, b, e in pts]
+    kf = lambda p: om.rate_constants(T, p)[0][0]
+    for (pj, *_), kj in zip(pts, ref):
+        assert kf(pj) == pytest.approx(kj, rel=1e-13)
+    for j in range(2):
+        for f in (0.5, 0.25, 0.9):
+            pf = pts[j][0] ** (1 - f) * pts[j + 1][0] ** f
+            assert kf(pf) == pytest.approx(ref[j] ** (1 - f) * ref[j + 1] ** f, rel=1e-12)
+    assert kf(0.01 * O.PATM) == ref[0]
+    assert kf(1e3 * O.PATM) == ref[2]
+    # the rate of progress uses the interpolated k_f at the point's pressure
+    T1, p1, Y1 = _single_state(T=T, p_atm=7.0)
+    d = om.rates_detail(T1, p1, Y1)
+    W = TM.ABX_COMP @ np.array([1.008, 15.999, 14.007])
+    W = np.asarray(W, float)
+    C = Y1 / W / np.sum(Y1 / W) * p1 / (O.RU * T1)
+    assert d["qf"][0] == pytest.approx(kf(p1) * C[TM.A_] * C[TM.B_], rel=1e-13)
+
+
+@pytest.mark.parametrize("rtype", [2, 3, 4])
+def test_chemically_activated_form(rtype):
+    """eq:c_i: a chemically activated reaction proceeds at k_0 F/(1+P_r), the
+    falloff form at k_inf P_r/(1+P_r) F = k_0 [X] F/(1+P_r): the ratio of the
+    two rates is [X] whatever F and P_r are (using k_inf in the activated rate,
+    or P_r/(1+P_r), breaks it); at low pressure c -> F(P_r -> 0) (1 for
+    Lindemann) and at high pressure c -> 0."""
+    T, p, Y = _single_state()
+    kw = dict(A=2e12, beta=0.2, Ea=3000.0, A0=5e17, beta0=-0.7, Ea0=1000.0, rev=0,
+              eff={TM.B_: 2.0})
+    if rtype == 3:
+        kw["troe"] = (0.6, 200.0, 1500.0, 3000.0)
+    if rtype == 4:
+        kw["sri"] = [0.8, 600.0, 900.0, 1.3, 0.1]
+    fall = O.OracleMech(TM.single_reaction_mech(rtype, **kw)).rates_detail(T, p, Y)
+    act = O.OracleMech(TM.single_reaction_mech(rtype, chem_act=1, **kw)).rates_detail(T, p, Y)
+    W = np.asarray(TM.ABX_COMP @ np.array([1.008, 15.999, 14.007]), float)
+    C = Y / W / np.sum(Y / W) * p / (O.RU * T)
+    X = C.sum() + (2.0 - 1.0) * C[TM.B_]
+    ratio = (fall["c"][0] * fall["qf"][0]) / (act["c"][0] * act["qf"][0])
+    assert ratio == pytest.approx(X, rel=1e-13)
+    if rtype == 2:
+        lo = O.OracleMech(TM.single_reaction_mech(2, chem_act=1, **kw)).rates_detail(
+            T, 1e-9 * O.PATM, Y)
+        assert lo["c"][0] == pytest.approx(1.0, rel=1e-6)
+        hi = O.OracleMech(TM.single_reaction_mech(2, chem_act=1, **kw)).rates_detail(
+            T, 1e9 * O.PATM, Y)
+        assert hi["c"][0] < 1e-6
 
 
 def test_third_body_single_collider():

@@ -18,8 +18,8 @@ def _csr(lists):
 
 def build(species_comp, nasa, reactions, visc=None, cond=None, diff=None):
     """reactions: list of dicts with keys type, reac [(sp, nu)], prod [(sp, nu)],
-    A, beta, Ea and optionally A0, beta0, Ea0, troe (4), eff {sp: alpha},
-    eff_default."""
+    A, beta, Ea and optionally A0, beta0, Ea0, troe (4), sri (5), chem_act,
+    plog [(p, A, beta, Ea)], eff {sp: alpha}, eff_default."""
     ns = len(species_comp)
     nr = len(reactions)
     comp = np.array(species_comp, np.int32)
@@ -32,6 +32,19 @@ def build(species_comp, nasa, reactions, visc=None, cond=None, diff=None):
             eff_sp.append(s)
             eff_val.append(a)
         eff_ptr.append(len(eff_sp))
+    extra = {"sri": None, "chem_act": None, "plog_ptr": None, "plog_p": None,
+             "plog_A": None, "plog_beta": None, "plog_Ea": None}
+    if any("sri" in r or "chem_act" in r or "plog" in r for r in reactions):
+        extra["sri"] = np.array([r.get("sri", [0.0] * 5) for r in reactions], float)
+        extra["chem_act"] = np.array([r.get("chem_act", 0) for r in reactions], np.int32)
+        ptr, pts = [0], []
+        for r in reactions:
+            pts += r.get("plog", [])
+            ptr.append(len(pts))
+        pts = np.array(pts, float).reshape(-1, 4)
+        extra.update(plog_ptr=np.array(ptr, np.int32), plog_p=pts[:, 0].copy(),
+                     plog_A=pts[:, 1].copy(), plog_beta=pts[:, 2].copy(),
+                     plog_Ea=pts[:, 3].copy())
     fo = 5
     if visc is None:
         visc = np.tile([2e-4, 5e-5, 1e-6, 0.0, 0.0], (ns, 1))
@@ -61,6 +74,7 @@ def build(species_comp, nasa, reactions, visc=None, cond=None, diff=None):
         "fit_order": fo, "fit_L0": 7.0, "fit_h": 1.2, "diff_fit_kind": 0,
         "visc_fit": np.asarray(visc, float), "cond_fit": np.asarray(cond, float),
         "diff_fit": np.asarray(diff, float),
+        **extra,
     }
 
 
@@ -93,10 +107,11 @@ def abx_mechanism():
 
 
 def single_reaction_mech(rtype, A=1e13, beta=0.0, Ea=0.0, A0=0.0, beta0=0.0, Ea0=0.0,
-                         troe=(0, 0, 0, 0), eff=None, eff_default=1.0):
+                         troe=(0, 0, 0, 0), eff=None, eff_default=1.0, rev=1, **more):
+    """A + B <=> AB of one type; `more` passes sri, chem_act or plog through."""
     rx = [dict(type=rtype, reac=[(A_, 1), (B_, 1)], prod=[(AB_, 1)], A=A, beta=beta, Ea=Ea,
                A0=A0, beta0=beta0, Ea0=Ea0, troe=list(troe), eff=eff or {},
-               eff_default=eff_default)]
+               eff_default=eff_default, rev=rev, **more)]
     return build(ABX_COMP, ABX_NASA, rx)
 
 
