@@ -236,6 +236,47 @@ def _weighted_polyfit(u, y, order):
     return np.linalg.solve(M, rhs[..., None])[..., 0]
 
 
+def transport_fit_grid():
+    """The 64 temperatures (log-spaced on [T_FIT_LO, T_FIT_HI]) the fits use."""
+    return np.exp(np.linspace(math.log(T_FIT_LO), math.log(T_FIT_HI), 64))
+
+
+def transport_fits(W, sigma_cm, eps, zrot298, natoms, cp_over_r, diff_fit_kind: int = 1):
+    """ln T polynomial fits (App. A.3 "Polynomial fits", in the centred variable
+    u) of the pure-species viscosity and conductivity and of the binary
+    diffusion coefficients at 1 atm (or their reciprocals, diff_fit_kind 1),
+    from Lennard-Jones kinetic theory on the grid of transport_fit_grid().
+
+    W[ns] g/mol, sigma_cm[ns], eps[ns] (epsilon/k, K), zrot298[ns], natoms[ns]
+    (1 atom, 2 linear, >= 3 nonlinear), cp_over_r[ns, 64] on the grid.
+    Returns visc_fit[ns, 5], cond_fit[ns, 5], diff_fit[ns, ns, 5].
+    """
+    ns = len(W)
+    Tg = transport_fit_grid()
+    ug = (np.log(Tg) - FIT_L0) / FIT_H
+    eta = np.empty((ns, Tg.size))
+    lam = np.empty((ns, Tg.size))
+    Dg = _binary_diffusion_1atm(Tg[None, None, :], W[:, None, None], W[None, :, None],
+                                sigma_cm[:, None, None], sigma_cm[None, :, None],
+                                eps[:, None, None], eps[None, :, None])
+    for k in range(ns):
+        eta[k] = _pure_viscosity(Tg, W[k], sigma_cm[k], eps[k])
+        rho = P_ATM * W[k] / (R_GAS * Tg)
+        rhoD_eta = rho * Dg[k, k] / eta[k]
+        cv_r = cp_over_r[k] - 1.0
+        lam[k] = _pure_conductivity(Tg, W[k], eta[k], rhoD_eta, cv_r, natoms[k],
+                                    zrot298[k], eps[k])
+    visc_fit = _weighted_polyfit(ug, eta, FIT_ORDER)
+    cond_fit = _weighted_polyfit(ug, lam, FIT_ORDER)
+    iu = np.triu_indices(ns)
+    target = Dg[iu] if diff_fit_kind == 0 else 1.0 / Dg[iu]
+    dfit_u = _weighted_polyfit(ug, target, FIT_ORDER)
+    diff_fit = np.empty((ns, ns, FIT_ORDER))
+    diff_fit[iu] = dfit_u
+    diff_fit[(iu[1], iu[0])] = dfit_u
+    return visc_fit, cond_fit, diff_fit
+
+
 # --------------------------------------------------------------------------
 # reactions
 # --------------------------------------------------------------------------
@@ -467,28 +508,10 @@ def make_mechanism(spec: MechSpec) -> dict:
     sigma = rng.uniform(2.5, 5.5, ns) * 1e-8     # cm
     eps = rng.uniform(30.0, 600.0, ns)           # K (epsilon / k_B)
     zrot = rng.uniform(0.0, 4.0, ns)
-    Tg = np.exp(np.linspace(math.log(T_FIT_LO), math.log(T_FIT_HI), 64))
-    ug = (np.log(Tg) - FIT_L0) / FIT_H
-    eta = np.empty((ns, Tg.size))
-    lam = np.empty((ns, Tg.size))
-    Dg = _binary_diffusion_1atm(Tg[None, None, :], W[:, None, None], W[None, :, None],
-                                sigma[:, None, None], sigma[None, :, None],
-                                eps[:, None, None], eps[None, :, None])
-    for k in range(ns):
-        eta[k] = _pure_viscosity(Tg, W[k], sigma[k], eps[k])
-        rho = P_ATM * W[k] / (R_GAS * Tg)
-        rhoD_eta = rho * Dg[k, k] / eta[k]
-        cv_r = _cp_model(Tg, clo[k], chi[k], theta[k]) - 1.0
-        lam[k] = _pure_conductivity(Tg, W[k], eta[k], rhoD_eta, cv_r, natoms[k],
-                                    zrot[k], eps[k])
-    visc_fit = _weighted_polyfit(ug, eta, FIT_ORDER)
-    cond_fit = _weighted_polyfit(ug, lam, FIT_ORDER)
-    iu = np.triu_indices(ns)
-    target = Dg[iu] if spec.diff_fit_kind == 0 else 1.0 / Dg[iu]
-    dfit_u = _weighted_polyfit(ug, target, FIT_ORDER)
-    diff_fit = np.empty((ns, ns, FIT_ORDER))
-    diff_fit[iu] = dfit_u
-    diff_fit[(iu[1], iu[0])] = dfit_u
+    Tg = transport_fit_grid()
+    cp_r = np.stack([_cp_model(Tg, clo[k], chi[k], theta[k]) for k in range(ns)])
+    visc_fit, cond_fit, diff_fit = transport_fits(W, sigma, eps, zrot, natoms, cp_r,
+                                                  spec.diff_fit_kind)
 
     sri = chem_act = plog = None
     if spec.n_sri or spec.n_chemact or spec.n_plog:

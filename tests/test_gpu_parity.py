@@ -171,6 +171,19 @@ def test_further_reaction_forms(kx, mech53x):
     check_rates(kx, mech53x, Te, pe, Ye, "further forms near equilibrium")
 
 
+def test_imported_yaml_mechanism(kx):
+    """A mechanism read by the Cantera-YAML importer (the synthetic fixture:
+    every reaction form, duplicates, a single-range NASA species, a single
+    collider), FP64 rates and transport through the C ABI."""
+    import os
+    from paper_2411_02640_amd import mech_yaml as MY
+    m = MY.load(os.path.join(os.path.dirname(__file__), "golden", "mini_mech.yaml"))
+    T, p, Y = I.make_states(m["n_species"], I.StateSpec(3001, seed=51, p_atm_range=(0.05, 50.0),
+                                                        dirichlet_alpha=0.5))
+    check_rates(kx, m, T, p, Y, "imported")
+    check_transport(kx, m, T, p, Y, "imported")
+
+
 def test_diffusion_fit_kind_direct(kx):
     """Tables holding fits of D_kj itself (diff_fit_kind = 0): the vector-ALU
     transport kernel with a reciprocal per pair, FP64 and mixed."""
