@@ -132,6 +132,14 @@ typedef struct {
                                      linear in ln p between neighbouring p_j; below the
                                      first (above the last) pressure k_f is that point's
                                      k_j.  A, beta, Ea of a PLOG reaction are not read. */
+    const int32_t *ord_ptr;       /* [Nr+1] CSR of explicit forward reaction orders (may be
+                                     NULL): the forward rate of progress is
+                                     k_f prod_k [X_k]^o_k with o_k the listed order, or
+                                     nu'_k for a reactant not listed; only for
+                                     irreversible reactions, at most 4 species with a
+                                     non-zero order per reaction */
+    const int32_t *ord_sp;        /*   species index */
+    const double *ord_val;        /*   order o_k >= 0 (need not be an integer) */
 } kx_mech_desc;
 
 typedef struct kx_mech kx_mech; /* opaque device-resident mechanism */
@@ -143,9 +151,11 @@ typedef struct kx_mech kx_mech; /* opaque device-resident mechanism */
  * twice on one side of a reaction, unbalanced element counts, an unknown
  * reaction type, a non-symmetric diff_fit, fit_order outside 1..8,
  * fit_h == 0, SRI parameters outside their ranges, chem_act set on a reaction
- * that is not a falloff reaction, and PLOG tables that are empty, not
- * increasing in pressure or with A <= 0.  KX_EUNSUPPORTED: more than 3 molecules (sum of nu) on one side
- * of a reaction, or more than 256 species.  On success *out owns the tables until
+ * that is not a falloff reaction, PLOG tables that are empty, not
+ * increasing in pressure or with A <= 0, and explicit orders on a reversible
+ * reaction or with a negative order.  KX_EUNSUPPORTED: more than 3 molecules (sum of nu) on one side
+ * of a reaction, more than 4 species with a non-zero explicit order, or more
+ * than 256 species.  On success *out owns the tables until
  * kx_mech_destroy.  Allocates device memory (hipMalloc); blocks until the
  * upload is complete. */
 kx_status kx_mech_create(const kx_mech_desc *desc, int device, kx_mech **out);

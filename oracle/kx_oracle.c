@@ -28,6 +28,8 @@
  *    rate constant is k_0 F/(1+P_r).
  *  - Pressure tables (PLOG): ln k_f linear in ln p between the two neighbouring
  *    reference pressures; outside the table the nearest end point's k_j.
+ *  - Explicit forward orders (irreversible reactions): the forward product is
+ *    prod_k C_k^o_k with the listed o_k, nu'_k for unlisted reactants.
  *  - Units: cgs, concentrations in mol/cm^3, Ea in cal/mol.
  */
 #include <float.h>
@@ -75,6 +77,8 @@ typedef struct {
     const int32_t *chem_act;     /* [nr] (or NULL) */
     const int32_t *plog_ptr;     /* [nr+1] (or NULL) */
     const double *plog_p, *plog_A, *plog_beta, *plog_Ea;
+    const int32_t *ord_ptr, *ord_sp;  /* (or NULL) */
+    const double *ord_val;
 } kxo_mech;
 
 static int g_threads = 0;
@@ -317,8 +321,14 @@ static void rates_point(const kxo_mech *m, double T, double p, const double *Y,
             kr = kf / Kc;
         }
         double Rf = 1.0, Rr = 1.0;
-        for (int e = m->reac_ptr[i]; e < m->reac_ptr[i + 1]; ++e)
-            Rf *= int_pow(C[m->reac_sp[e]], m->reac_nu[e]);
+        const int o0 = m->ord_ptr ? m->ord_ptr[i] : 0, o1 = m->ord_ptr ? m->ord_ptr[i + 1] : 0;
+        for (int e = m->reac_ptr[i]; e < m->reac_ptr[i + 1]; ++e) {
+            int listed = 0;
+            for (int f = o0; f < o1; ++f)
+                if (m->ord_sp[f] == m->reac_sp[e]) listed = 1;
+            if (!listed) Rf *= int_pow(C[m->reac_sp[e]], m->reac_nu[e]);
+        }
+        for (int f = o0; f < o1; ++f) Rf *= pow(C[m->ord_sp[f]], m->ord_val[f]);
         for (int e = m->prod_ptr[i]; e < m->prod_ptr[i + 1]; ++e)
             Rr *= int_pow(C[m->prod_sp[e]], m->prod_nu[e]);
         const double qf = kf * Rf, qr = kr * Rr;

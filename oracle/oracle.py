@@ -51,6 +51,7 @@ class _Mech(C.Structure):
         ("visc_fit", _dp), ("cond_fit", _dp), ("diff_fit", _dp),
         ("sri", _dp), ("chem_act", _ip), ("plog_ptr", _ip), ("plog_p", _dp),
         ("plog_A", _dp), ("plog_beta", _dp), ("plog_Ea", _dp),
+        ("ord_ptr", _ip), ("ord_sp", _ip), ("ord_val", _dp),
     ]
 
 
@@ -113,7 +114,8 @@ class OracleMech:
             setattr(s, field_of.get(k, k), a.ctypes.data_as(_ip))
         for k, conv, ptr in (("sri", f64, _dp), ("plog_p", f64, _dp), ("plog_A", f64, _dp),
                              ("plog_beta", f64, _dp), ("plog_Ea", f64, _dp),
-                             ("chem_act", i32, _ip), ("plog_ptr", i32, _ip)):
+                             ("chem_act", i32, _ip), ("plog_ptr", i32, _ip),
+                             ("ord_ptr", i32, _ip), ("ord_sp", i32, _ip), ("ord_val", f64, _dp)):
             if mech.get(k) is None:
                 setattr(s, k, None)
                 continue

@@ -26,6 +26,7 @@ enum : uint8_t {
     kFlagReversible = 1,
     kFlagKfConst = 2,    // beta = E_R = 0: k_f = A without an exponential
     kFlagChemAct = 4,    // chemically activated falloff: c = F / (1 + P_r) with k_0 in r_i
+    kFlagOrders = 8,     // explicit forward orders (irreversible): prod C^o from DevAux
 };
 
 // One reaction slot in kernel order.  Reactions are sorted heaviest type
@@ -52,8 +53,9 @@ static_assert(sizeof(DevRxn) == 48, "DevRxn layout");
 // species and alpha - default; unused entries point at the dummy species with
 // 0); any further ones are in DevEff[ext_off .. ext_off + ext_cnt).  A PLOG
 // reaction's reference pressures are DevPlog[plog_off .. plog_off + plog_cnt).
-// 176 bytes.
+// 224 bytes.
 constexpr int kInlineEff = 8;
+constexpr int kMaxOrd = 4;            // species with explicit orders per reaction
 struct alignas(16) DevAux {
     double eff_default;      // efficiency of unlisted species
     double lnA0, beta0, ER0; // k_0 (falloff)
@@ -65,8 +67,12 @@ struct alignas(16) DevAux {
     uint16_t eoff[kInlineEff];
     int32_t has_T2, ext_off, ext_cnt;
     int32_t plog_off, plog_cnt, pad;
+    // explicit forward orders: LDS byte offset of the species pair and the
+    // order (unused entries have order 0)
+    double oval[kMaxOrd];
+    uint16_t ooff[kMaxOrd];
 };
-static_assert(sizeof(DevAux) == 176, "DevAux layout");
+static_assert(sizeof(DevAux) == 224, "DevAux layout");
 
 // One reference pressure of a PLOG reaction: ln p_j, the Arrhenius exponent
 // ln k_j = lnA + beta ln T - ER / T, and 1 / (ln p_(j+1) - ln p_j) (0 for the

@@ -115,6 +115,23 @@ kx_status validate(const kx_mech_desc *d, std::vector<double> &W)
                    !std::isfinite(d->Ea[i])) {
             return fail(KX_EINVAL, "kx_mech_create: A must be > 0, beta and Ea finite" + ri);
         }
+        if (d->ord_ptr && d->ord_ptr[i + 1] > d->ord_ptr[i]) {
+            if (!d->ord_sp || !d->ord_val || d->ord_ptr[i] < 0)
+                return fail(KX_EINVAL, "kx_mech_create: bad order arrays" + ri);
+            if (d->reversible[i])
+                return fail(KX_EINVAL, "kx_mech_create: explicit orders need an "
+                                       "irreversible reaction" + ri);
+            for (int e = d->ord_ptr[i]; e < d->ord_ptr[i + 1]; ++e) {
+                if (d->ord_sp[e] < 0 || d->ord_sp[e] >= ns)
+                    return fail(KX_EINVAL, "kx_mech_create: order species out of range" + ri);
+                if (!(d->ord_val[e] >= 0.0) || !std::isfinite(d->ord_val[e]))
+                    return fail(KX_EINVAL, "kx_mech_create: orders must be finite and >= 0" +
+                                               ri);
+                for (int f = d->ord_ptr[i]; f < e; ++f)
+                    if (d->ord_sp[f] == d->ord_sp[e])
+                        return fail(KX_EINVAL, "kx_mech_create: order listed twice" + ri);
+            }
+        }
         if (d->chem_act && d->chem_act[i] && !falloff)
             return fail(KX_EINVAL, "kx_mech_create: chem_act on a reaction that is not a "
                                    "falloff reaction" + ri);
@@ -225,13 +242,37 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
             r.beta = r.ER = 0.0;
             r.A = 1.0;
         }
+        // forward orders: reactants at nu' unless listed, listed species at
+        // their order; zero orders dropped
+        std::vector<std::pair<int, double>> ord;
+        const bool has_ord = d->ord_ptr && d->ord_ptr[i + 1] > d->ord_ptr[i];
+        if (has_ord) {
+            for (int e = d->reac_ptr[i]; e < d->reac_ptr[i + 1]; ++e)
+                ord.push_back({d->reac_sp[e], (double)d->reac_nu[e]});
+            for (int e = d->ord_ptr[i]; e < d->ord_ptr[i + 1]; ++e) {
+                bool found = false;
+                for (auto &o : ord)
+                    if (o.first == d->ord_sp[e]) {
+                        o.second = d->ord_val[e];
+                        found = true;
+                    }
+                if (!found) ord.push_back({d->ord_sp[e], d->ord_val[e]});
+            }
+            ord.erase(std::remove_if(ord.begin(), ord.end(),
+                                     [](const std::pair<int, double> &o) { return o.second == 0.0; }),
+                      ord.end());
+            if ((int)ord.size() > kMaxOrd)
+                return fail(KX_EUNSUPPORTED, "kx_mech_create: more than 4 species with "
+                                             "explicit orders (reaction " + std::to_string(i) + ")");
+            r.flags |= kFlagOrders;
+        }
         r.aux = 0xFFFF;
-        if (r.type != KX_RXN_ELEMENTARY) {
+        if (r.type != KX_RXN_ELEMENTARY || has_ord) {
             if (aux.size() >= 0xFFFF)
                 return fail(KX_EUNSUPPORTED, "kx_mech_create: too many non-elementary reactions");
             DevAux a;
             std::memset(&a, 0, sizeof a);
-            const bool collider = r.type != KX_RXN_PLOG;
+            const bool collider = r.type != KX_RXN_PLOG && r.type != KX_RXN_ELEMENTARY;
             a.eff_default = collider ? d->eff_default[i] : 0.0;
             for (int q = 0; q < kInlineEff; ++q) {
                 a.eoff[q] = (uint16_t)(16 * ns);  // dummy species, alpha - default = 0
@@ -274,6 +315,14 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
                 a.fp[2] = 1.0 / q[2];
                 a.fp[3] = std::log(q[3]);
                 a.fp[4] = q[4];
+            }
+            for (int q = 0; q < kMaxOrd; ++q) {
+                a.ooff[q] = (uint16_t)(16 * ns);
+                a.oval[q] = 0.0;
+            }
+            for (size_t q = 0; q < ord.size(); ++q) {
+                a.ooff[q] = (uint16_t)(16 * ord[q].first);
+                a.oval[q] = ord[q].second;
             }
             if (r.type == KX_RXN_PLOG) {
                 a.plog_off = (int32_t)plog.size();

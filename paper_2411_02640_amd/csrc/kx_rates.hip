@@ -217,6 +217,25 @@ __device__ __forceinline__ double rate_of_progress(const MechDev &m, const RxnWo
         Bp *= r2.b;
         Bpp *= load_b(pb, o5);
     }
+    if (flags & kFlagOrders) {
+        // explicit forward orders (irreversible): prod_k C_k^o_k, C_k = a_k b_k
+        const DevAux &ax = m.aux[aux];
+        double s = 0.0;
+        bool zero = false;
+#pragma unroll
+        for (int e = 0; e < kMaxOrd; ++e) {
+            const double o = ax.oval[e];
+            if (o != 0.0) {
+                const Pair q = load_pair(pb, ax.ooff[e]);
+                const double C = q.a * q.b;
+                zero = zero || !(C > 0.0);
+                s = fma(o, kln(fmax(C, DBL_MIN)), s);
+            }
+        }
+        Ap = zero ? 0.0 : kexp(s);
+        Bp = 1.0;
+        Bpp = 0.0;
+    }
     double c = 1.0;
     if (type != KX_RXN_ELEMENTARY && type != KX_RXN_PLOG) {
         const DevAux &ax = m.aux[aux];

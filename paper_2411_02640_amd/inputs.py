@@ -361,6 +361,8 @@ class MechSpec:
     n_sri: int = 0
     n_chemact: int = 0
     n_plog: int = 0
+    # elementary -> irreversible with explicit forward orders
+    n_orders: int = 0
 
     @property
     def n_reactions(self) -> int:
@@ -376,6 +378,8 @@ MECH_200 = MechSpec(200, 1200, 180, 30, 90, seed=2001500, name="syn200")
 # activated falloff, 20 pressure-table (PLOG) reactions
 MECH_53X = MechSpec(53, 266, 30, 0, 29, seed=53325, name="syn53x", n_sri=10, n_chemact=8,
                     n_plog=20)
+# syn53 with 20 irreversible reactions of non-integer forward orders
+MECH_53O = MechSpec(53, 266, 30, 0, 29, seed=53325, name="syn53o", n_orders=20)
 
 
 def make_mechanism(spec: MechSpec) -> dict:
@@ -513,7 +517,27 @@ def make_mechanism(spec: MechSpec) -> dict:
     visc_fit, cond_fit, diff_fit = transport_fits(W, sigma, eps, zrot, natoms, cp_r,
                                                   spec.diff_fit_kind)
 
-    sri = chem_act = plog = None
+    sri = chem_act = plog = orders = None
+    reversible = np.ones(nr, np.int32)
+    if spec.n_orders:
+        rng3 = np.random.Generator(np.random.PCG64(spec.seed + 8888))
+        elem_ids = np.flatnonzero(rtype == RXN_ELEMENTARY)
+        optr, osp, oval = [0], [], []
+        conv = set(rng3.choice(elem_ids, size=spec.n_orders, replace=False).tolist())
+        for i in range(nr):
+            if i in conv:
+                reversible[i] = 0
+                reac = reac_sp[reac_ptr[i]:reac_ptr[i + 1]]
+                for k, nu in zip(reac, reac_nu[reac_ptr[i]:reac_ptr[i + 1]]):
+                    osp.append(int(k))
+                    oval.append(float(nu) * rng3.uniform(0.5, 1.5))
+                if rng3.random() < 0.5:   # a species that is not a reactant
+                    cand = [k for k in range(ns - 1) if k not in reac]
+                    osp.append(int(rng3.choice(cand)))
+                    oval.append(rng3.uniform(0.1, 0.5))
+            optr.append(len(osp))
+        orders = {"ord_ptr": np.array(optr, np.int32), "ord_sp": np.array(osp, np.int32),
+                  "ord_val": np.array(oval)}
     if spec.n_sri or spec.n_chemact or spec.n_plog:
         rng2 = np.random.Generator(np.random.PCG64(spec.seed + 7777))
         troe_ids = np.flatnonzero(rtype == RXN_TROE)
@@ -564,7 +588,7 @@ def make_mechanism(spec: MechSpec) -> dict:
         "nasa_hi": nasa_hi,
         "t_mid": t_mid,
         "rxn_type": rtype,
-        "reversible": np.ones(nr, np.int32),
+        "reversible": reversible,
         "reac_ptr": reac_ptr, "reac_sp": reac_sp, "reac_nu": reac_nu,
         "prod_ptr": prod_ptr, "prod_sp": prod_sp, "prod_nu": prod_nu,
         "A": A, "beta": beta, "Ea": Ea,
@@ -586,6 +610,8 @@ def make_mechanism(spec: MechSpec) -> dict:
         **(plog if plog is not None else
            {"plog_ptr": None, "plog_p": None, "plog_A": None, "plog_beta": None,
             "plog_Ea": None}),
+        **(orders if orders is not None else
+           {"ord_ptr": None, "ord_sp": None, "ord_val": None}),
         # generator metadata (not part of the descriptor)
         "_h298_over_r": h298,
         "_s298_over_r": s298,

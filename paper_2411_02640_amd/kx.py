@@ -49,6 +49,7 @@ class _Desc(C.Structure):
         ("visc_fit", _dp), ("cond_fit", _dp), ("diff_fit", _dp),
         ("sri", _dp), ("chem_act", _ip), ("plog_ptr", _ip), ("plog_p", _dp),
         ("plog_A", _dp), ("plog_beta", _dp), ("plog_Ea", _dp),
+        ("ord_ptr", _ip), ("ord_sp", _ip), ("ord_val", _dp),
     ]
 
 
@@ -58,8 +59,8 @@ _I32_FIELDS = ["composition", "rxn_type", "reversible", "reac_ptr", "reac_sp", "
                "prod_ptr", "prod_sp", "prod_nu", "eff_ptr", "eff_sp"]
 
 # Optional arrays of the further reaction forms (NULL when a mechanism has none).
-_OPT_F64_FIELDS = ["sri", "plog_p", "plog_A", "plog_beta", "plog_Ea"]
-_OPT_I32_FIELDS = ["chem_act", "plog_ptr"]
+_OPT_F64_FIELDS = ["sri", "plog_p", "plog_A", "plog_beta", "plog_Ea", "ord_val"]
+_OPT_I32_FIELDS = ["chem_act", "plog_ptr", "ord_ptr", "ord_sp"]
 
 _lib = None
 

@@ -21,9 +21,11 @@ What is read:
   ``default-efficiency``; ``<=>`` / ``=`` reversible, ``=>`` irreversible;
   ``duplicate`` is accepted (duplicates simply add).
 
+Explicit forward ``orders`` are read for irreversible reactions.
+
 Rejected with ValueError: other thermo models or reaction types (Chebyshev,
-Blowers-Masel, surface reactions), explicit ``orders``, non-integer
-stoichiometric coefficients, negative pre-exponential factors, A written with
+Blowers-Masel, surface reactions), ``orders`` on a reversible reaction,
+non-integer stoichiometric coefficients, negative pre-exponential factors, A written with
 units, efficiencies of undeclared species.
 
 The polynomial transport fits are built from the Lennard-Jones parameters by
@@ -103,7 +105,7 @@ class _Units:
         if self.energy not in _ENERGY_CAL_MOL or self.pressure not in _PRESSURE_DYN:
             raise ValueError(f"unsupported units {u}")
 
-    def A(self, v, order: int) -> float:
+    def A(self, v, order: float) -> float:
         """A of a rate constant of `order` concentrations, to (cm^3/mol)^(order-1)/s."""
         if _num(v) is None:
             raise ValueError(f"A with explicit units ({v!r}) is not supported")
@@ -244,15 +246,21 @@ def load(src, T_fit=(I.T_FIT_LO, I.T_FIT_HI)) -> dict:
     sri = np.zeros((nr, 5))
     chem_act = np.zeros(nr, np.int32)
     eff_default = np.ones(nr)
-    reac, prod, effs = [], [], []
+    reac, prod, effs, ords = [], [], [], []
     pptr, pp, pA, pb, pE = [0], [], [], [], []
     for i, r in enumerate(rxn_list):
         eq = r["equation"]
-        if "orders" in r:
-            raise ValueError(f"{eq}: explicit reaction orders are not supported")
         if r.get("negative-A"):
             raise ValueError(f"{eq}: negative pre-exponential factors are not supported")
         rs, ps, reversible, coll, plus_m = _parse_equation(eq)
+        if "orders" in r:
+            if reversible:
+                raise ValueError(f"{eq}: explicit reaction orders need an irreversible "
+                                 "reaction")
+            for nm, o in r["orders"].items():
+                if nm not in index:
+                    raise ValueError(f"{eq}: order of undeclared species {nm}")
+                ords.append((i, index[nm], _f(o)))
         for nm, _ in rs + ps:
             if nm not in index:
                 raise ValueError(f"{eq}: undeclared species {nm}")
@@ -260,6 +268,10 @@ def load(src, T_fit=(I.T_FIT_LO, I.T_FIT_HI)) -> dict:
         prod.append([(index[nm], nu) for nm, nu in ps])
         rev[i] = 1 if reversible else 0
         order = sum(nu for _, nu in rs)
+        if "orders" in r:
+            # the units of A follow the sum of the forward orders
+            listed = {nm: _f(o) for nm, o in r["orders"].items()}
+            order = sum(nu for nm, nu in rs if nm not in listed) + sum(listed.values())
         kind = r.get("type", "elementary")
         eff = dict(r.get("efficiencies", {}) or {})
         if kind == "elementary":
@@ -352,6 +364,9 @@ def load(src, T_fit=(I.T_FIT_LO, I.T_FIT_HI)) -> dict:
             cp_r[k, g] = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])))
     visc_fit, cond_fit, diff_fit = I.transport_fits(W, sigma, eps, zrot, natoms, cp_r, 1)
 
+    ord_ptr = np.searchsorted([o[0] for o in ords], np.arange(nr + 1)).astype(np.int32)
+    ord_sp = np.array([o[1] for o in ords], np.int32)
+    ord_val = np.array([o[2] for o in ords], np.float64)
     any_extra = bool((rtype == I.RXN_SRI).any() or chem_act.any()
                      or (rtype == I.RXN_PLOG).any())
     return {
@@ -374,6 +389,9 @@ def load(src, T_fit=(I.T_FIT_LO, I.T_FIT_HI)) -> dict:
         "plog_A": np.array(pA) if any_extra else None,
         "plog_beta": np.array(pb) if any_extra else None,
         "plog_Ea": np.array(pE) if any_extra else None,
+        "ord_ptr": ord_ptr if ords else None,
+        "ord_sp": ord_sp if ords else None,
+        "ord_val": ord_val if ords else None,
         "_species_names": names, "_elements": elements, "_warnings": warnings,
     }
 
@@ -484,6 +502,11 @@ def dump(mech: dict, names=None, elements=None, transport=None) -> str:
                 lines.append(f"  - {{P: {flt(mech['plog_p'][j] / 10.0)}, A: "
                              f"{flt(mech['plog_A'][j])}, b: {flt(mech['plog_beta'][j])}, "
                              f"Ea: {flt(mech['plog_Ea'][j])}}}")
+        op = mech.get("ord_ptr")
+        if op is not None and op[i + 1] > op[i]:
+            lines.append("  orders: {" + ", ".join(
+                f"{names[mech['ord_sp'][e]]}: {flt(mech['ord_val'][e])}"
+                for e in range(op[i], op[i + 1])) + "}")
         if t in (1, 2, 3, 4) and single is None:
             if effs:
                 lines.append("  efficiencies: {" + ", ".join(f"{n}: {flt(v)}"

@@ -17,7 +17,7 @@ def pytest_configure(config):
 def _mech(name):
     from paper_2411_02640_amd import inputs as I
     spec = {"syn9": I.MECH_9, "syn53": I.MECH_53, "syn200": I.MECH_200,
-            "syn53x": I.MECH_53X}[name]
+            "syn53x": I.MECH_53X, "syn53o": I.MECH_53O}[name]
     return I.make_mechanism(spec)
 
 
@@ -39,6 +39,11 @@ def mech200():
 @pytest.fixture(scope="session")
 def mech53x():
     return _mech("syn53x")
+
+
+@pytest.fixture(scope="session")
+def mech53o():
+    return _mech("syn53o")
 
 
 @pytest.fixture(scope="session")

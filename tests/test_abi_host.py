@@ -37,7 +37,7 @@ def test_version():
     assert "gfx950" in kx.version()
 
 
-@pytest.mark.parametrize("name", ["mech9", "mech53", "mech200", "mech53x"])
+@pytest.mark.parametrize("name", ["mech9", "mech53", "mech200", "mech53x", "mech53o"])
 def test_host_create(name, request):
     mech = request.getfixturevalue(name)
     m = kx.HostMechanism(mech)
@@ -200,3 +200,24 @@ def test_reject_bad_pressure_tables():
 def test_reject_chem_act_on_non_falloff():
     _expect(_one(0, chem_act=1), kx.KX_EINVAL, "chem_act")
     _expect(_one(1, chem_act=1), kx.KX_EINVAL, "chem_act")
+
+
+def _ord(orders, rev=0):
+    rx = [dict(type=0, reac=[(tiny_mechs.A_, 1), (tiny_mechs.B_, 1)],
+               prod=[(tiny_mechs.AB_, 1)], A=1e12, beta=0.0, Ea=0.0, rev=rev, ord=orders)]
+    return tiny_mechs.build(tiny_mechs.ABX_COMP, tiny_mechs.ABX_NASA, rx)
+
+
+def test_explicit_orders_validation():
+    kx.HostMechanism(_ord([(0, 1.5), (3, 0.2)])).close()
+    kx.HostMechanism(_ord([(0, 0.0), (1, 0.0), (2, 0.5), (3, 0.2)])).close()  # zeros dropped
+    _expect(_ord([(0, 1.5)], rev=1), kx.KX_EINVAL, "irreversible")
+    _expect(_ord([(0, -0.5)]), kx.KX_EINVAL, "orders must be finite")
+    _expect(_ord([(0, 1.0), (0, 2.0)]), kx.KX_EINVAL, "listed twice")
+    _expect(_ord([(9, 1.0)]), kx.KX_EINVAL, "out of range")
+    # five species with non-zero orders (two reactants + three more) exceed four
+    comp = tiny_mechs.ABX_COMP + [(2, 0, 0)]
+    nasa = tiny_mechs.ABX_NASA + [tiny_mechs.ABX_NASA[2]]
+    rx = [dict(type=0, reac=[(0, 1), (1, 1)], prod=[(2, 1)], A=1e12, beta=0.0, Ea=0.0, rev=0,
+               ord=[(2, 0.1), (3, 0.1), (4, 0.1)])]
+    _expect(tiny_mechs.build(comp, nasa, rx), kx.KX_EUNSUPPORTED, "more than 4")

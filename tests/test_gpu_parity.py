@@ -171,6 +171,20 @@ def test_further_reaction_forms(kx, mech53x):
     check_rates(kx, mech53x, Te, pe, Ye, "further forms near equilibrium")
 
 
+def test_explicit_orders(kx, mech53o):
+    """20 irreversible reactions with non-integer forward orders (one with a
+    non-reactant species), FP64 and mixed."""
+    T, p, Y = I.make_states(53, I.StateSpec(4096 + 3, seed=45, p_atm_range=(0.5, 40.0),
+                                            dirichlet_alpha=0.3))
+    check_rates(kx, mech53o, T, p, Y, "explicit orders")
+    dm = dev_mech(kx, mech53o)
+    w = run_rates(kx, dm, T, p, Y, precision="mixed")
+    ref, sc = O.OracleMech(mech53o).production_rates(T, p, Y)
+    r = PM.mixed_wdot_report(w, ref, sc)
+    _say("  mixed", r)
+    assert r["ok"], r
+
+
 def test_imported_yaml_mechanism(kx):
     """A mechanism read by the Cantera-YAML importer (the synthetic fixture:
     every reaction form, duplicates, a single-range NASA species, a single

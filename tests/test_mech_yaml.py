@@ -23,8 +23,8 @@ def test_fixture_units_and_forms():
     m = MY.load(FIXTURE)
     names = m["_species_names"]
     assert names == ["A", "B", "AB", "A2", "B2", "AB2", "X"]
-    np.testing.assert_array_equal(m["rxn_type"], [0, 0, 1, 3, 4, 2, 5, 0, 0])
-    np.testing.assert_array_equal(m["reversible"], [1, 0, 1, 1, 1, 1, 1, 1, 1])
+    np.testing.assert_array_equal(m["rxn_type"], [0, 0, 1, 3, 4, 2, 5, 0, 0, 0])
+    np.testing.assert_array_equal(m["reversible"], [1, 0, 1, 1, 1, 1, 1, 1, 1, 0])
     assert m["A"][0] == pytest.approx(1e13, rel=1e-15)
     assert m["Ea"][0] == pytest.approx(1e4, rel=1e-15)
     assert m["A"][1] == pytest.approx(2e13, rel=1e-15) and m["Ea"][1] == 1e4
@@ -37,7 +37,7 @@ def test_fixture_units_and_forms():
     assert m["eff_default"][4] == 0.0                             # (+X): X alone collides
     sl = slice(m["eff_ptr"][4], m["eff_ptr"][5])
     assert m["eff_sp"][sl].tolist() == [names.index("X")] and m["eff_val"][sl].tolist() == [1.0]
-    assert m["chem_act"].tolist() == [0, 0, 0, 0, 0, 1, 0, 0, 0]
+    assert m["chem_act"].tolist() == [0, 0, 0, 0, 0, 1, 0, 0, 0, 0]
     assert m["A0"][5] == pytest.approx(7e13, rel=1e-15)           # k_0 bimolecular
     assert m["A"][5] == pytest.approx(8e7, rel=1e-15)             # k_inf unimolecular
     sl = slice(m["plog_ptr"][6], m["plog_ptr"][7])
@@ -49,6 +49,11 @@ def test_fixture_units_and_forms():
     assert m["eff_val"][sl].tolist() == [2.5, 0.5]
     # 2 A <=> A2 twice (duplicates add); nu = 2 on the left
     assert m["reac_nu"][m["reac_ptr"][7]] == 2 and m["A"][7] + m["A"][8] == pytest.approx(4e12)
+    # explicit orders: A's units follow their sum (1.5 + 0.7 + 0.25 = 2.45)
+    sl = slice(m["ord_ptr"][9], m["ord_ptr"][10])
+    assert [names[k] for k in m["ord_sp"][sl]] == ["A", "AB2", "B"]
+    assert m["ord_val"][sl].tolist() == [1.5, 0.7, 0.25]
+    assert m["A"][9] == pytest.approx(5e9 * 1e3 ** 1.45, rel=1e-14)
     # one NASA range: used on both sides of t_mid = its upper end
     k = names.index("AB2")
     assert m["t_mid"][k] == 1000.0 and (m["nasa_lo"][k] == m["nasa_hi"][k]).all()
@@ -56,7 +61,7 @@ def test_fixture_units_and_forms():
     kx.HostMechanism(m).close()
 
 
-@pytest.mark.parametrize("name", ["mech9", "mech53x"])
+@pytest.mark.parametrize("name", ["mech9", "mech53x", "mech53o"])
 def test_round_trip(name, request):
     """export -> import gives back the kinetics and thermo arrays (and the same
     oracle rates); viscosity and diffusion fits agree; conductivity fits differ
@@ -75,7 +80,8 @@ def test_round_trip(name, request):
         np.testing.assert_array_equal(r[k], m[k], err_msg=k)
     for k in ("A", "beta", "Ea"):   # not read for pressure-table reactions
         np.testing.assert_array_equal(r[k][~plog], m[k][~plog], err_msg=k)
-    for k in ("sri", "chem_act", "plog_ptr", "plog_A", "plog_beta", "plog_Ea"):
+    for k in ("sri", "chem_act", "plog_ptr", "plog_A", "plog_beta", "plog_Ea", "ord_ptr",
+              "ord_sp", "ord_val"):
         if m[k] is None:
             assert r[k] is None or not np.any(r[k]), k
         else:
@@ -92,7 +98,7 @@ def test_round_trip(name, request):
 
 
 @pytest.mark.parametrize("bad, words", [
-    ("orders: {A: 1.5}", "orders"),
+    ("orders: {A: 1.5}", "irreversible"),
     ("type: Chebyshev", "not supported"),
     ("negative-A: true", "negative"),
 ])

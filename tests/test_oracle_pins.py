@@ -77,7 +77,7 @@ def test_mixture_thermo(mech9):
 
 
 # ----------------------------------------------------------------- kinetics (A.2)
-@pytest.mark.parametrize("name", ["mech9", "mech53", "mech53x"])
+@pytest.mark.parametrize("name", ["mech9", "mech53", "mech53x", "mech53o"])
 def test_element_and_mass_conservation(name, request):
     """sum_k a_ke wdot_k = 0 and sum_k W_k wdot_k = 0 (every reaction balanced):
     catches a flipped side, a wrong nu or a mis-indexed species."""
@@ -263,6 +263,35 @@ def test_chemically_activated_form(rtype):
         hi = O.OracleMech(TM.single_reaction_mech(2, chem_act=1, **kw)).rates_detail(
             T, 1e9 * O.PATM, Y)
         assert hi["c"][0] < 1e-6
+
+
+def test_explicit_forward_orders():
+    """Explicit orders (irreversible A + B -> AB with o_A = 1.5, o_B = 1, and
+    o_D = 0.25 for a species that is not a reactant): the forward rate changes
+    by (C_A'/C_A)^1.5 (C_B'/C_B) (C_D'/C_D)^0.25 between two states, and by
+    lambda^2.75 when the pressure is scaled by lambda at fixed composition
+    (the stoichiometric product would give lambda^2)."""
+    kw = dict(A=3e12, beta=0.4, Ea=2000.0, rev=0)
+    rx = [dict(type=0, reac=[(TM.A_, 1), (TM.B_, 1)], prod=[(TM.AB_, 1)],
+               ord=[(TM.A_, 1.5), (TM.D_, 0.25)], **kw)]
+    m = TM.build(TM.ABX_COMP, TM.ABX_NASA, rx)
+    om = O.OracleMech(m)
+    W = np.asarray(TM.ABX_COMP @ np.array([1.008, 15.999, 14.007]), float)
+    T = 1300.0
+    conc = lambda Y, p: Y / W / np.sum(Y / W) * p / (O.RU * T)
+    Y1 = np.array([0.2, 0.3, 0.1, 0.4])
+    Y2 = np.array([0.05, 0.5, 0.15, 0.3])
+    p = 3.0 * O.PATM
+    q1 = om.rates_detail(T, p, Y1)["qf"][0]
+    q2 = om.rates_detail(T, p, Y2)["qf"][0]
+    C1, C2 = conc(Y1, p), conc(Y2, p)
+    want = ((C2[TM.A_] / C1[TM.A_]) ** 1.5 * (C2[TM.B_] / C1[TM.B_])
+            * (C2[TM.D_] / C1[TM.D_]) ** 0.25)
+    assert q2 / q1 == pytest.approx(want, rel=1e-13)
+    q3 = om.rates_detail(T, 4.0 * p, Y1)["qf"][0]
+    assert q3 / q1 == pytest.approx(4.0 ** 2.75, rel=1e-13)
+    d = om.rates_detail(T, p, Y1)
+    assert d["qr"][0] == 0.0
 
 
 def test_third_body_single_collider():

@@ -19,7 +19,7 @@ def _csr(lists):
 def build(species_comp, nasa, reactions, visc=None, cond=None, diff=None):
     """reactions: list of dicts with keys type, reac [(sp, nu)], prod [(sp, nu)],
     A, beta, Ea and optionally A0, beta0, Ea0, troe (4), sri (5), chem_act,
-    plog [(p, A, beta, Ea)], eff {sp: alpha}, eff_default."""
+    plog [(p, A, beta, Ea)], ord [(sp, order)], eff {sp: alpha}, eff_default."""
     ns = len(species_comp)
     nr = len(reactions)
     comp = np.array(species_comp, np.int32)
@@ -33,7 +33,17 @@ def build(species_comp, nasa, reactions, visc=None, cond=None, diff=None):
             eff_val.append(a)
         eff_ptr.append(len(eff_sp))
     extra = {"sri": None, "chem_act": None, "plog_ptr": None, "plog_p": None,
-             "plog_A": None, "plog_beta": None, "plog_Ea": None}
+             "plog_A": None, "plog_beta": None, "plog_Ea": None, "ord_ptr": None,
+             "ord_sp": None, "ord_val": None}
+    if any("ord" in r for r in reactions):
+        optr, osp, oval = [0], [], []
+        for r in reactions:
+            for k, o in r.get("ord", []):
+                osp.append(k)
+                oval.append(o)
+            optr.append(len(osp))
+        extra.update(ord_ptr=np.array(optr, np.int32), ord_sp=np.array(osp, np.int32),
+                     ord_val=np.array(oval, float))
     if any("sri" in r or "chem_act" in r or "plog" in r for r in reactions):
         extra["sri"] = np.array([r.get("sri", [0.0] * 5) for r in reactions], float)
         extra["chem_act"] = np.array([r.get("chem_act", 0) for r in reactions], np.int32)
