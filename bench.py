@@ -151,6 +151,28 @@ def other_workloads(kx, I, torch, steps, warmup):
                       "fp64_rates_ms": r["fp64"]["rates_ms"],
                       "fp64_transport_ms": r["fp64"]["transport_ms"]})
     res["sweep_syn53"] = sweep
+    # the analytical Jacobian d wdot / d C: one 53 x 53 matrix per point, 2^16
+    # points (1.47 GB of output per launch)
+    log("jacobian syn53 at 2^16 points")
+    dm = kx.Mechanism(m53, 0)
+    nj = 1 << 16
+    (_, T, p, Y), = serve_load.make_pool(dm, 53, [nj], 30)
+    out = torch.empty((nj, 53, 53), dtype=torch.float64, device="cuda:0")
+    for _ in range(warmup):
+        kx.jacobian(dm, T, p, Y, out=out)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        kx.jacobian(dm, T, p, Y, out=out)
+    ev[1].record()
+    torch.cuda.synchronize()
+    jms = ev[0].elapsed_time(ev[1]) / steps
+    res["jacobian_syn53_2p16"] = {"n_points": nj, "ms": jms, "Mpoints_s": nj / jms / 1e3,
+                                  "output_GB_s": nj * 53 * 53 * 8 / (jms * 1e-3) / 1e9}
+    del out, T, p, Y
+    dm.close()
+    torch.cuda.empty_cache()
     return res
 
 

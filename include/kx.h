@@ -212,6 +212,19 @@ kx_status kx_transport_ex(const kx_mech *mech, int64_t n, const double *T, const
 kx_status kx_thermo(const kx_mech *mech, int64_t n, const double *T, const double *Y,
                     double *cp_k, double *h_k, double *cp_mix, hipStream_t stream);
 
+/* Analytical Jacobian of the production rates (App. A.2 differentiated; the
+ * paper names it as the input of implicit BDF integrators, §1, §4):
+ * jac[(i * Ns + k) * Ns + j] = d wdot_k / d C_j in 1/s at point i, at fixed
+ * temperature T[i], the derivative taken at C_k = X_k p / (R_u T) with the
+ * pressure following the concentrations (p = R_u T sum_k C_k, so [M] = sum C
+ * and a pressure-table rate constant sees the change of p).  One dense
+ * row-major Ns x Ns matrix per point, contiguous (the layout batched linear
+ * solvers take); jac holds n * Ns * Ns doubles (device memory).  Plain FP64.
+ * KX_EUNSUPPORTED for mechanisms of more than 128 species.  Where an explicit
+ * order below one meets an absent species the derivative is +inf. */
+kx_status kx_jacobian(const kx_mech *mech, int64_t n, const double *T, const double *p,
+                      const double *Y, double *jac, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Serving: a continuous-batching request server (project addition; the paper
  * notes that GPUs reach their throughput only with >~1e5 points, so small

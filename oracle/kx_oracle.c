@@ -32,6 +32,7 @@
  *    prod_k C_k^o_k with the listed o_k, nu'_k for unlisted reactants.
  *  - Units: cgs, concentrations in mol/cm^3, Ea in cal/mol.
  */
+#include <complex.h>
 #include <float.h>
 #include <math.h>
 #include <stdint.h>
@@ -388,6 +389,171 @@ void kxo_rates_detail(const kxo_mech *m, double T, double p, const double *Y,
     double *ws = malloc(sizeof(double) * 5 * (size_t)m->ns);
     rates_point(m, T, p, Y, 1, wdot, scale, 1, qf, qr, c, ws);
     free(ws);
+}
+
+/* ------------------------------------------------ Jacobian by complex step
+ *
+ * d wdot_k / d C_j at fixed T, the pressure following the concentrations
+ * (p = R_u T sum_k C_k, so [M] = sum_k C_k and a pressure table sees p), by
+ * complex-step differentiation: the rates are evaluated once more in complex
+ * arithmetic at C + i h e_j and the derivative is Im(wdot) / h.  This is
+ * exact to rounding (no difference of nearly equal values) and shares none of
+ * the derivative algebra of an analytical Jacobian.  The complex evaluation
+ * repeats the real one above step for step. */
+
+static double complex int_pow_c(double complex x, int n)
+{
+    double complex r = 1.0;
+    int a = n < 0 ? -n : n;
+    for (int i = 0; i < a; ++i) r *= x;
+    return n < 0 ? 1.0 / r : r;
+}
+
+static double complex log10_clamped_c(double complex x)
+{
+    return creal(x) > DBL_MIN ? clog(x) / log(10.0) : log10(DBL_MIN);
+}
+
+static double complex troe_F_c(const double *p4, double T, double complex Pr)
+{
+    const double alpha = p4[0], T3 = p4[1], T1 = p4[2], T2 = p4[3];
+    double Fcent = (1.0 - alpha) * exp(-T / T3) + alpha * exp(-T / T1);
+    if (!isnan(T2)) Fcent += exp(-T2 / T);
+    const double lFc = log10(Fcent);
+    const double c = -0.4 - 0.67 * lFc, nn = 0.75 - 1.27 * lFc, d = 0.14;
+    const double complex lPr = log10_clamped_c(Pr);
+    const double complex f1 = (lPr + c) / (nn - d * (lPr + c));
+    return cexp(log(10.0) * lFc / (1.0 + f1 * f1));
+}
+
+static double complex sri_F_c(const double *p5, double T, double complex Pr)
+{
+    const double a = p5[0], b = p5[1], c = p5[2], d = p5[3], e = p5[4];
+    const double complex lPr = log10_clamped_c(Pr);
+    const double complex X = 1.0 / (1.0 + lPr * lPr);
+    return d * pow(T, e) * cexp(X * log(a * exp(-b / T) + exp(-T / c)));
+}
+
+static double complex plog_kf_c(const kxo_mech *m, int i, double T, double complex p)
+{
+    const int b = m->plog_ptr[i], e = m->plog_ptr[i + 1];
+    const double *P = m->plog_p;
+    const double pr = creal(p);
+    if (pr <= P[b]) return arrhenius(m->plog_A[b], m->plog_beta[b], m->plog_Ea[b], T);
+    if (pr >= P[e - 1])
+        return arrhenius(m->plog_A[e - 1], m->plog_beta[e - 1], m->plog_Ea[e - 1], T);
+    int j = b;
+    while (!(pr < P[j + 1])) ++j;
+    const double k1 = arrhenius(m->plog_A[j], m->plog_beta[j], m->plog_Ea[j], T);
+    const double k2 = arrhenius(m->plog_A[j + 1], m->plog_beta[j + 1], m->plog_Ea[j + 1], T);
+    return cexp(log(k1) + (log(k2) - log(k1)) * (clog(p) - log(P[j])) /
+                              (log(P[j + 1]) - log(P[j])));
+}
+
+/* wdot(C) at temperature T in complex arithmetic; g[ns] = G_k/RT at T. */
+static void rates_conc_c(const kxo_mech *m, double T, const double complex *C, const double *g,
+                         double complex *wdot)
+{
+    const int ns = m->ns;
+    double complex Mc = 0.0;
+    for (int k = 0; k < ns; ++k) {
+        Mc += C[k];
+        wdot[k] = 0.0;
+    }
+    for (int i = 0; i < m->nr; ++i) {
+        const int type = m->rtype[i];
+        double complex kf = (type == KXO_PLOG) ? plog_kf_c(m, i, T, Mc * KXO_RU * T)
+                                               : arrhenius(m->A[i], m->beta[i], m->Ea[i], T);
+        double complex c = 1.0;
+        if (type != KXO_ELEMENTARY && type != KXO_PLOG) {
+            double complex X = 0.0;
+            for (int k = 0; k < ns; ++k) {
+                double alpha = m->eff_default[i];
+                for (int e = m->eff_ptr[i]; e < m->eff_ptr[i + 1]; ++e)
+                    if (m->eff_sp[e] == k) alpha = m->eff_val[e];
+                X += alpha * C[k];
+            }
+            if (type == KXO_THREEBODY) {
+                c = X;
+            } else {
+                const double k0 = arrhenius(m->A0[i], m->beta0[i], m->Ea0[i], T);
+                const double complex Pr = k0 * X / kf;
+                double complex F = 1.0;
+                if (type == KXO_TROE) F = troe_F_c(m->troe + 4 * i, T, Pr);
+                if (type == KXO_SRI) F = sri_F_c(m->sri + 5 * i, T, Pr);
+                if (m->chem_act && m->chem_act[i]) {
+                    c = F / (1.0 + Pr);
+                    kf = k0;
+                } else {
+                    c = Pr / (1.0 + Pr) * F;
+                }
+            }
+        }
+        double complex kr = 0.0;
+        if (m->rev[i]) {
+            double dG = 0.0;
+            int dnu = 0;
+            for (int e = m->prod_ptr[i]; e < m->prod_ptr[i + 1]; ++e) {
+                dG += m->prod_nu[e] * g[m->prod_sp[e]];
+                dnu += m->prod_nu[e];
+            }
+            for (int e = m->reac_ptr[i]; e < m->reac_ptr[i + 1]; ++e) {
+                dG -= m->reac_nu[e] * g[m->reac_sp[e]];
+                dnu -= m->reac_nu[e];
+            }
+            kr = kf / (exp(-dG) * int_pow(KXO_PATM / (KXO_RU * T), dnu));
+        }
+        double complex Rf = 1.0, Rr = 1.0;
+        const int o0 = m->ord_ptr ? m->ord_ptr[i] : 0, o1 = m->ord_ptr ? m->ord_ptr[i + 1] : 0;
+        for (int e = m->reac_ptr[i]; e < m->reac_ptr[i + 1]; ++e) {
+            int listed = 0;
+            for (int f = o0; f < o1; ++f)
+                if (m->ord_sp[f] == m->reac_sp[e]) listed = 1;
+            if (!listed) Rf *= int_pow_c(C[m->reac_sp[e]], m->reac_nu[e]);
+        }
+        for (int f = o0; f < o1; ++f)
+            if (m->ord_val[f] != 0.0) Rf *= cpow(C[m->ord_sp[f]], m->ord_val[f]);
+        for (int e = m->prod_ptr[i]; e < m->prod_ptr[i + 1]; ++e)
+            Rr *= int_pow_c(C[m->prod_sp[e]], m->prod_nu[e]);
+        const double complex R = c * (kf * Rf - kr * Rr);
+        for (int k = 0; k < ns; ++k) {
+            const int nu = net_nu(m, i, k);
+            if (nu != 0) wdot[k] += nu * R;
+        }
+    }
+}
+
+/* jac[i][k][j] = d wdot_k / d C_j for n points (T, p, Y as for the rates; the
+ * derivative is taken at the concentrations C_k = X_k p / (R_u T)). */
+void kxo_jacobian(const kxo_mech *m, int64_t n, const double *T, const double *p,
+                  const double *Y, double *jac)
+{
+    const int ns = m->ns;
+#pragma omp parallel num_threads(g_threads > 0 ? g_threads : kxo_max_threads())
+    {
+        double complex *C = malloc(sizeof(double complex) * ns);
+        double complex *w = malloc(sizeof(double complex) * ns);
+        double *g = malloc(sizeof(double) * ns);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double inv_wbar = 0.0;
+            for (int k = 0; k < ns; ++k) inv_wbar += Y[k * n + i] / species_weight(m, k);
+            const double wbar = 1.0 / inv_wbar;
+            kxo_thermo(m, T[i], NULL, NULL, NULL, g);
+            for (int j = 0; j < ns; ++j) {
+                for (int k = 0; k < ns; ++k)
+                    C[k] = Y[k * n + i] * wbar / species_weight(m, k) * p[i] / (KXO_RU * T[i]);
+                const double h = 1e-30;
+                C[j] += h * I;
+                rates_conc_c(m, T[i], C, g, w);
+                for (int k = 0; k < ns; ++k)
+                    jac[((size_t)i * ns + k) * ns + j] = cimag(w[k]) / h;
+            }
+        }
+        free(C);
+        free(w);
+        free(g);
+    }
 }
 
 /* Forward rate constants k_f (k_inf for falloff) and, for falloff reactions,

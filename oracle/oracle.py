@@ -78,6 +78,7 @@ def lib():
         L.kxo_wilke_phi.argtypes = [vp, C.c_double, C.c_int, C.c_int]
         L.kxo_wilke_phi.restype = C.c_double
         L.kxo_transport.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
+        L.kxo_jacobian.argtypes = [vp, C.c_int64, vp, vp, vp, vp]
         L.kxo_set_threads.argtypes = [C.c_int]
         L.kxo_max_threads.restype = C.c_int
         _lib = L
@@ -179,6 +180,16 @@ class OracleMech:
         kf, k0 = np.empty(self.nr), np.empty(self.nr)
         lib().kxo_rate_constants(self.ref, float(T), float(p), _ptr(kf), _ptr(k0))
         return kf, k0
+
+    def jacobian(self, T, p, Y):
+        """jac[n, ns, ns]: d wdot_k / d C_j at fixed T (complex step)."""
+        T = np.ascontiguousarray(T, np.float64)
+        p = np.ascontiguousarray(p, np.float64)
+        Y = np.ascontiguousarray(Y, np.float64)
+        n = T.size
+        jac = np.empty((n, self.ns, self.ns))
+        lib().kxo_jacobian(self.ref, n, _ptr(T), _ptr(p), _ptr(Y), _ptr(jac))
+        return jac
 
     # ---------------------------------------------------------------- transport
     def pure_transport(self, T: float, p: float):

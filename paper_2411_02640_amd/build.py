@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libkx.so")
-SOURCES = ["kx_api.cpp", "kx_mech.cpp", "kx_serve.cpp", "kx_rates.hip", "kx_transport.hip"]
+SOURCES = ["kx_api.cpp", "kx_mech.cpp", "kx_serve.cpp", "kx_rates.hip", "kx_transport.hip",
+           "kx_jacobian.hip"]
 ARCH = "gfx950"
 
 

@@ -154,6 +154,18 @@ kx_status kx_thermo(const kx_mech *mech, int64_t n, const double *T, const doubl
     return launch_thermo(mech, n, T, Y, cp_k, h_k, cp_mix, stream);
 }
 
+kx_status kx_jacobian(const kx_mech *mech, int64_t n, const double *T, const double *p,
+                      const double *Y, double *jac, hipStream_t stream)
+{
+    kx_status st = check_common(mech, n, "kx_jacobian");
+    if (st != KX_OK) return st;
+    if (n == 0) return ok();
+    if (!T || !p || !Y || !jac) return fail(KX_EINVAL, "kx_jacobian: NULL array");
+    DeviceGuard g(mech->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    return launch_jacobian(mech, n, T, p, Y, jac, stream);
+}
+
 const char *kx_last_error(void) { return t_last_error.c_str(); }
 
 const char *kx_version(void) { return "kx 0.1 gfx950"; }

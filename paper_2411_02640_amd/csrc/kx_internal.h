@@ -188,6 +188,8 @@ kx_status launch_transport(const kx_mech *m, int64_t n, const double *T, const d
                            int precision, hipStream_t s);
 kx_status launch_thermo(const kx_mech *m, int64_t n, const double *T, const double *Y,
                         double *cpk, double *hk, double *cpmix, hipStream_t s);
+kx_status launch_jacobian(const kx_mech *m, int64_t n, const double *T, const double *p,
+                          const double *Y, double *jac, hipStream_t s);
 
 // Points per tile of the two kernels for a mechanism and precision (the
 // serving work lists are cut in the same tiles as a direct call, so a request

@@ -82,6 +82,7 @@ def lib():
         L.kx_transport.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
         L.kx_transport_ex.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, i32, vp]
         L.kx_thermo.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+        L.kx_jacobian.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.kx_last_error.restype = C.c_char_p
         L.kx_version.restype = C.c_char_p
         for name in ("kx_mech_create", "kx_mech_destroy", "kx_mech_info", "kx_production_rates",
@@ -224,6 +225,20 @@ def thermo(mech: Mechanism, T, Y, stream=None):
                           C.c_void_p(hk.data_ptr()), C.c_void_p(cp.data_ptr()),
                           _stream_ptr(stream, dev)))
     return cpk, hk, cp
+
+
+def jacobian(mech: Mechanism, T, p, Y, out=None, stream=None):
+    """jac[n, Ns, Ns] = d wdot_k / d C_j (1/s) at fixed T for device tensors T, p, Y."""
+    n = T.shape[0]
+    ns = mech.n_species
+    dev = mech.device
+    args = [_dev_tensor(T, dev, (n,), "T"), _dev_tensor(p, dev, (n,), "p"),
+            _dev_tensor(Y, dev, (ns, n), "Y")]
+    if out is None:
+        out = torch.empty((n, ns, ns), dtype=torch.float64, device=f"cuda:{dev}")
+    j = _dev_tensor(out, dev, (n, ns, ns), "out")
+    check(lib().kx_jacobian(mech.handle, n, *args, j, _stream_ptr(stream, dev)))
+    return out
 
 
 # --------------------------------------------------------------------------

@@ -198,6 +198,61 @@ def test_imported_yaml_mechanism(kx):
     check_transport(kx, m, T, p, Y, "imported")
 
 
+# |J_gpu - J_ref| per entry relative to the largest |J| of its row.  Both sides
+# are FP64 sums of the same terms in different orders (complex step on the
+# oracle side), so the difference is a few ulps of the row's largest terms;
+# 1e-12 leaves a margin of ~20 over the largest difference seen (5e-14).
+JAC_TOL = 1e-12
+
+
+def _check_jacobian(kx, mech, T, p, Y, label):
+    _say("jacobian", label, mech.get("name", ""), "n =", T.size)
+    dm = dev_mech(kx, mech)
+    Td, pd, Yd = to_dev(T, p, Y)
+    J = kx.jacobian(dm, Td, pd, Yd).cpu().numpy()
+    ref = O.OracleMech(mech).jacobian(T, p, Y)
+    assert np.isfinite(J).all()
+    row = np.abs(ref).max(axis=2, keepdims=True)
+    err = np.abs(J - ref) / np.where(row > 0, row, 1.0)
+    _say("   max error / row scale", float(err.max()),
+         "median", float(np.median(err)))
+    assert err.max() <= JAC_TOL, float(err.max())
+    return J, ref
+
+
+def test_jacobian(kx, mech9, mech53x, mech53o):
+    """d wdot / d C through the C ABI against the oracle's complex-step
+    Jacobian (a different method: no derivative formulas), for syn9 (all 4096
+    points + a ragged tail), a tiny mechanism with one reaction of every form,
+    and samples of the 53-species mechanisms with SRI, chemically activated and
+    pressure-table reactions and with explicit orders."""
+    from . import tiny_mechs as TM
+    T, p, Y = I.make_states(9, I.StateSpec(4096 + 7, seed=61))
+    _check_jacobian(kx, mech9, T, p, Y, "syn9")
+    m = TM.all_forms_mechanism()
+    T, p, Y = I.make_states(4, I.StateSpec(2048, seed=62, p_atm_range=(0.1, 20.0),
+                                           dirichlet_alpha=1.0))
+    _check_jacobian(kx, m, T, p, Y, "all forms")
+    for mech, seed in ((mech53x, 63), (mech53o, 64)):
+        T, p, Y = I.make_states(53, I.StateSpec(129, seed=seed, p_atm_range=(0.05, 150.0),
+                                                dirichlet_alpha=0.3))
+        _check_jacobian(kx, mech, T, p, Y, mech["name"])
+
+
+def test_jacobian_rows_conserve_mass(kx, mech53):
+    """sum_k W_k J_kj = 0 (every reaction balanced) on the GPU result for the
+    benchmark mechanism, 2^14 points."""
+    T, p, Y = I.make_states(53, I.STATES_53, n_points=1 << 14)
+    dm = dev_mech(kx, mech53)
+    J = kx.jacobian(dm, *to_dev(T, p, Y))
+    W = torch.from_numpy(np.asarray(mech53["composition"] @ mech53["elem_mass"], float)).to(DEV)
+    s = (W[None, :, None] * J).sum(dim=1)
+    a = (W[None, :, None] * J.abs()).sum(dim=1)
+    rel = (s.abs() / torch.clamp(a, min=1e-300)).max().item()
+    _say("jacobian mass rows: max |W.J| / (W.|J|)", rel)
+    assert rel < 1e-13
+
+
 def test_diffusion_fit_kind_direct(kx):
     """Tables holding fits of D_kj itself (diff_fit_kind = 0): the vector-ALU
     transport kernel with a reciprocal per pair, FP64 and mixed."""

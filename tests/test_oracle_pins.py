@@ -294,6 +294,56 @@ def test_explicit_forward_orders():
     assert d["qr"][0] == 0.0
 
 
+def _wdot_of_C(om, m, T, C):
+    """wdot at concentrations C (Y and p rebuilt from C; p = R T sum C)."""
+    W = np.asarray(m["composition"] @ m["elem_mass"], float)
+    Y = C * W / np.sum(C * W)
+    return om.rates_detail(T, O.RU * T * np.sum(C), Y)["wdot"]
+
+
+def test_jacobian_matches_central_differences(mech9):
+    """The complex-step Jacobian d wdot / d C (App. A.2 differentiated) agrees
+    with central differences of the rates themselves (a different evaluation)
+    for every reaction form, and its weighted column sums vanish with the
+    rates' (mass conservation: sum_k W_k wdot_k = 0 for every C)."""
+    T = 1400.0
+    for m in (mech9, TM.all_forms_mechanism()):
+        om = O.OracleMech(m)
+        ns = m["n_species"]
+        W = np.asarray(m["composition"] @ m["elem_mass"], float)
+        Y = np.linspace(1.0, 2.0, ns) / np.linspace(1.0, 2.0, ns).sum()
+        p = 2.0 * O.PATM
+        J = om.jacobian(np.array([T]), np.array([p]), Y[:, None])[0]
+        C = Y / W / np.sum(Y / W) * p / (O.RU * T)
+        for j in range(ns):
+            h = 1e-6 * C[j]
+            Cp, Cm = C.copy(), C.copy()
+            Cp[j] += h
+            Cm[j] -= h
+            fd = (_wdot_of_C(om, m, T, Cp) - _wdot_of_C(om, m, T, Cm)) / (2 * h)
+            scale = np.abs(J[:, j]).max()
+            assert np.abs(J[:, j] - fd).max() <= 1e-6 * scale, (m["name"], j)
+        assert (np.abs(W @ J) <= 1e-12 * (W @ np.abs(J)) + 1e-300).all()
+
+
+def test_jacobian_closed_form():
+    """A + B -> AB, irreversible, k_f = const: J = k_f [[-C_B, -C_A], ...] in
+    the (A, B) columns, +k_f (C_B, C_A) for AB, zero elsewhere."""
+    m = TM.single_reaction_mech(0, A=3.3e12, rev=0)
+    om = O.OracleMech(m)
+    T, p, Y = _single_state()
+    W = np.asarray(m["composition"] @ m["elem_mass"], float)
+    C = Y / W / np.sum(Y / W) * p / (O.RU * T)
+    J = om.jacobian(np.array([T]), np.array([p]), Y[:, None])[0]
+    k = 3.3e12
+    want = np.zeros((4, 4))
+    want[TM.A_, TM.A_] = want[TM.B_, TM.A_] = -k * C[TM.B_]
+    want[TM.A_, TM.B_] = want[TM.B_, TM.B_] = -k * C[TM.A_]
+    want[TM.AB_, TM.A_] = k * C[TM.B_]
+    want[TM.AB_, TM.B_] = k * C[TM.A_]
+    np.testing.assert_allclose(J, want, rtol=1e-14, atol=0)
+
+
 def test_third_body_single_collider():
     """[X]_i = [X_m] when only species m collides (eff_default 0, alpha_m 1)."""
     T, p, Y = _single_state()

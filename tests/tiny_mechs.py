@@ -4,6 +4,7 @@ import math
 import numpy as np
 
 RCAL = 8.31446261815324 / 4.184
+PATM = 1013250.0
 
 
 def _csr(lists):
@@ -128,3 +129,28 @@ def single_reaction_mech(rtype, A=1e13, beta=0.0, Ea=0.0, A0=0.0, beta0=0.0, Ea0
 def ea_for_half(T):
     """E_a (cal/mol) with exp(-E_a/(R T)) = 1/2 at temperature T."""
     return math.log(2.0) * RCAL * T
+
+
+def all_forms_mechanism():
+    """{A, B, AB, D} with one reaction of every form: elementary, three-body,
+    Troe, SRI, chemically activated Troe, a pressure table and explicit orders."""
+    base = dict(beta=0.3, Ea=3000.0)
+    rx = [
+        dict(type=0, reac=[(A_, 1), (B_, 1)], prod=[(AB_, 1)], A=3e13, **base),
+        dict(type=1, reac=[(A_, 1), (B_, 1)], prod=[(AB_, 1)], A=2e15, beta=-0.8,
+             Ea=0.0, eff={B_: 2.5, D_: 0.7}),
+        dict(type=3, reac=[(A_, 1), (B_, 1)], prod=[(AB_, 1)], A=1.5e12, beta=0.3,
+             Ea=5e3, A0=4e18, beta0=-1.1, Ea0=2e3, troe=[0.62, 150.0, 1800.0, 4500.0],
+             eff={AB_: 3.0}),
+        dict(type=4, reac=[(A_, 1), (B_, 1)], prod=[(AB_, 1)], A=9e12, beta=0.1,
+             Ea=800.0, A0=2e17, beta0=-0.5, Ea0=0.0, sri=[0.8, 600.0, 900.0, 1.3, 0.1]),
+        dict(type=3, reac=[(A_, 1), (B_, 1)], prod=[(AB_, 1)], A=1e12, beta=0.0,
+             Ea=0.0, A0=1e17, beta0=0.0, Ea0=0.0, troe=[0.5, 200.0, 1500.0, np.nan],
+             chem_act=1),
+        dict(type=5, reac=[(AB_, 1), (A_, 1)], prod=[(B_, 1), (A_, 2)], A=1.0,
+             beta=0.0, Ea=0.0, plog=[(0.5 * PATM, 7e14, 0.0, 3.1e4), (5 * PATM, 2e15, 0.1,
+                                                                          3.2e4)]),
+        dict(type=0, reac=[(A_, 1), (B_, 1)], prod=[(AB_, 1)], A=3e12, rev=0,
+             ord=[(A_, 1.5), (D_, 0.25)], **base),
+    ]
+    return build(ABX_COMP, ABX_NASA, rx)
