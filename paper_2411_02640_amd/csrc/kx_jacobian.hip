@@ -41,7 +41,7 @@ namespace kx {
 namespace {
 
 constexpr int kJacMaxSpecies = 128;
-constexpr int kRec = 8;  // doubles per reaction record of phase 2
+constexpr int kRec = 9;  // doubles per reaction record of phase 2 (the last packs indices)
 
 struct JPair {
     double a, C;
@@ -238,7 +238,21 @@ __global__ __launch_bounds__(kWave) void jacobian_kernel(MechDev m, int64_t n,
                 }
                 const double D = dcdX * (F - B);
                 dense = fma(cmod * (F - B) * slope, krcp(Mc), dense);
+                // species of the six slots (or of the four orders), type and flags
+                // packed into one 8-byte word, so phase 3 reads no reaction table
+                uint64_t pk = ((uint64_t)flags << 56) | ((uint64_t)type << 48);
+                if (flags & kFlagOrders) {
+                    const DevAux &ax = m.aux[R.aux];
+#pragma unroll
+                    for (int e = 0; e < kMaxOrd; ++e) pk |= (uint64_t)(ax.ooff[e] / 16) << (8 * e);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < kMaxSide; ++q)
+                        pk |= ((uint64_t)(R.roff[q] / 16) << (8 * q)) |
+                              ((uint64_t)(R.poff[q] / 16) << (8 * (q + 3)));
+                }
                 double *rr = rec + kRec * r;
+                rr[8] = __longlong_as_double((long long)pk);
                 rr[0] = cmod * Pd[0];
                 rr[1] = cmod * Pd[1];
                 rr[2] = cmod * Pd[2];
@@ -265,21 +279,24 @@ __global__ __launch_bounds__(kWave) void jacobian_kernel(MechDev m, int64_t n,
                     for (int u = 0; u < 8; ++u) {
                         const int r = (int)(off[u] / 16);
                         if (r >= cnt) continue;  // padding entry
-                        const DevRxn &R = m.rxn[base + r];
                         const double *rr = rec + kRec * r;
-                        if (R.flags & kFlagOrders) {
-                            const DevAux &ax = m.aux[R.aux];
-                            for (int e = 0; e < kMaxOrd; ++e)
-                                if (ax.oval[e] != 0.0) Jk[ax.ooff[e] / 16] += sg * rr[e];
+                        const uint64_t pk = (uint64_t)__double_as_longlong(rr[8]);
+                        const unsigned flags = (unsigned)(pk >> 56), type = (unsigned)(pk >> 48) & 0xFFu;
+                        if (flags & kFlagOrders) {
+                            for (int e = 0; e < kMaxOrd; ++e) {
+                                const int jo = (int)((pk >> (8 * e)) & 0xFFu);
+                                if (jo < ns) Jk[jo] += sg * rr[e];
+                            }
                         } else {
                             for (int q = 0; q < kMaxSide; ++q) {
-                                const int jr = R.roff[q] / 16, jp = R.poff[q] / 16;
+                                const int jr = (int)((pk >> (8 * q)) & 0xFFu);
+                                const int jp = (int)((pk >> (8 * (q + 3))) & 0xFFu);
                                 if (jr < ns) Jk[jr] += sg * rr[q];
                                 if (jp < ns) Jk[jp] -= sg * rr[3 + q];
                             }
                         }
-                        if (R.type != KX_RXN_ELEMENTARY && R.type != KX_RXN_PLOG) {
-                            const DevAux &ax = m.aux[R.aux];
+                        if (type != KX_RXN_ELEMENTARY && type != KX_RXN_PLOG) {
+                            const DevAux &ax = m.aux[m.rxn[base + r].aux];
                             const double D = sg * rr[6];
                             for (int e = 0; e < kInlineEff; ++e)
                                 if (ax.dalpha[e] != 0.0) Jk[ax.eoff[e] / 16] += D * ax.dalpha[e];
