@@ -17,14 +17,14 @@
 //   c = e0 F/(1+P_r) (chem. activated, referred to k_inf):
 //                             dc/d[X] = e0 F (g/([X](1+P_r)) - e0/(1+P_r)^2).
 //
-// Work decomposition.  One workgroup (one wave) per point; J is accumulated in
-// LDS (row k owned by lane k, so no two lanes write the same word):
-//   1. species (lane = k): C_k, Gibbs g_k, a_k = (p_atm/RT) e^{-g_k}; zero row k;
-//   2. reactions (lane = r, one chunk at a time): k_f, k_r = k_f A'/A'' (the
+// Work decomposition.  One workgroup of one or two waves per point; J is accumulated
+// in LDS (row k owned by thread k, so no two threads write the same word):
+//   1. species (thread = k): C_k, Gibbs g_k, a_k = (p_atm/RT) e^{-g_k}; zero row k;
+//   2. reactions (thread = r, one chunk at a time): k_f, k_r = k_f A'/A'' (the
 //      product of a over reactants over that over products is 1/K_c, eq:K_p),
 //      the slot partials c dF/dC, c dB/dC, D = dc/d[X] (F - B) and the part
 //      that is the same for every column j, into an LDS record per reaction;
-//   3. species (lane = k): the chunk's gather lists (the +/- entries of the
+//   3. species (thread = k): the chunk's gather lists (the +/- entries of the
 //      production rates, repeated |nu| times) add nu_ki d R_i / d C_j into row k;
 //   4. the matrix, plus the per-row constant, goes out as one contiguous block.
 // Output layout: jac[(i * ns + k) * ns + j] -- one dense ns x ns matrix per
@@ -85,15 +85,16 @@ size_t jac_lds_bytes(const MechDev &m)
            + sizeof(double) * kRec * (size_t)(m.chunk + 1);  // records (+zero record)
 }
 
-template <int SPL>
-__global__ __launch_bounds__(kWave) void jacobian_kernel(MechDev m, int64_t n,
+// NT threads (one or two waves; thread k owns row k, ns <= NT)
+template <int NT>
+__global__ __launch_bounds__(NT) void jacobian_kernel(MechDev m, int64_t n,
                                                          const double *__restrict__ T,
                                                          const double *__restrict__ P,
                                                          const double *__restrict__ Y,
                                                          double *__restrict__ jac)
 {
     extern __shared__ double lds[];
-    const int ns = m.ns, nsq = ns * ns, lane = threadIdx.x;
+    const int ns = m.ns, nsq = ns * ns, tid = threadIdx.x;
     double *J = lds;
     double *rowc = J + nsq;
     // ns * ns + ns is even, so the pairs start 16-byte aligned after ns + 2 slots
@@ -106,18 +107,23 @@ __global__ __launch_bounds__(kWave) void jacobian_kernel(MechDev m, int64_t n,
         const double lnT = kln(Ti), invT = krcp(Ti);
         const double invRT = krcp(kRu * Ti);
         const double Mc = pi * invRT, P0 = kPatm * invRT, lnp = kln(pi);
-        // W-bar: sum_k Y_k / W_k over the wave
+        // W-bar: sum_k Y_k / W_k over the workgroup (the two waves meet in the
+        // record area, which phase 2 fills only later)
         double part = 0.0;
-        for (int k = lane; k < ns; k += kWave) part = fma(Y[(int64_t)k * n + i], m.sp[k].inv_W, part);
+        for (int k = tid; k < ns; k += NT) part = fma(Y[(int64_t)k * n + i], m.sp[k].inv_W, part);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
+        if (NT > kWave) {
+            if ((tid & (kWave - 1)) == 0) rec[tid / kWave] = part;
+            __syncthreads();
+            part = rec[0] + rec[1];
+            __syncthreads();
+        }
         const double cf = Mc * krcp(part);
 
         // ---- phase 1: species
-#pragma unroll
-        for (int s = 0; s < SPL; ++s) {
-            const int k = lane + kWave * s;
-            if (k < ns) {
+        for (int k = tid; k < ns; k += NT) {
+            {
                 const DevSpecies &S = m.sp[k];
                 JPair q;
                 q.a = P0 * kexp(-jgibbs(S, Ti, lnT, invT));
@@ -127,18 +133,18 @@ __global__ __launch_bounds__(kWave) void jacobian_kernel(MechDev m, int64_t n,
                 rowc[k] = 0.0;
             }
         }
-        if (lane == 0) {
+        if (tid == 0) {
             sp[ns].a = 1.0;
             sp[ns].C = 1.0;
         }
-        if (lane < kRec) rec[kRec * m.chunk + lane] = 0.0;
+        if (tid < kRec) rec[kRec * m.chunk + tid] = 0.0;
         __syncthreads();
 
         for (int c = 0; c < m.nchunks; ++c) {
             const int base = c * m.chunk;
             const int cnt = min(m.chunk, m.nr - base);
-            // ---- phase 2: one reaction per lane
-            for (int r = lane; r < cnt; r += kWave) {
+            // ---- phase 2: one reaction per thread
+            for (int r = tid; r < cnt; r += NT) {
                 const DevRxn &R = m.rxn[base + r];
                 const unsigned type = R.type, flags = R.flags;
                 const bool kconst = (flags & kFlagKfConst) != 0;
@@ -263,13 +269,10 @@ __global__ __launch_bounds__(kWave) void jacobian_kernel(MechDev m, int64_t n,
                 rr[7] = dense;
             }
             __syncthreads();
-            // ---- phase 3: lane = species k, its +/- entries of this chunk
+            // ---- phase 3: thread = species k, its +/- entries of this chunk
             const int npos = m.gpos[c], ngrp = npos + m.gneg[c];
-#pragma unroll
-            for (int s = 0; s < SPL; ++s) {
-                const int k = lane + kWave * s;
-                if (k >= ns) continue;
-                const uint4 *ge = m.gent + ((size_t)m.goff[c] * gw + lane + kWave * s) * 2;
+            for (int k = tid; k < ns; k += NT) {
+                const uint4 *ge = m.gent + ((size_t)m.goff[c] * gw + k) * 2;
                 double *Jk = J + k * ns;
                 double rc = 0.0;
                 for (int it = 0; it < ngrp; ++it) {
@@ -314,7 +317,7 @@ __global__ __launch_bounds__(kWave) void jacobian_kernel(MechDev m, int64_t n,
         }
         // ---- phase 4: the matrix with the per-row constants, one contiguous block
         double *out = jac + (size_t)i * nsq;
-        for (int e = lane; e < nsq; e += kWave) out[e] = J[e] + rowc[e / ns];
+        for (int e = tid; e < nsq; e += NT) out[e] = J[e] + rowc[e / ns];
         __syncthreads();
     }
 }
@@ -337,11 +340,15 @@ kx_status launch_jacobian(const kx_mech *mech, int64_t n, const double *T, const
         return fail(KX_EUNSUPPORTED, "kx_jacobian: at most 128 species are supported");
     const size_t lds = jac_lds_bytes(m);
     if (lds > 160 * 1024) return fail(KX_EUNSUPPORTED, "kx_jacobian: mechanism too large for LDS");
-    auto kern = m.gpass <= 1 ? jacobian_kernel<1> : jacobian_kernel<2>;
+    // one wave when it covers both the species and the reactions of a step,
+    // two otherwise
+    const bool two = m.ns > kWave || m.nr > kWave;
+    auto kern = two ? jacobian_kernel<2 * kWave> : jacobian_kernel<kWave>;
     kx_status st = set_lds(kern, lds);
     if (st != KX_OK) return st;
     const unsigned grid = (unsigned)std::min<int64_t>(n, 16384);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave), lds, s, m, n, T, p, Y, jac);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(two ? 2 * kWave : kWave), lds, s, m, n, T, p, Y,
+                       jac);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "jacobian kernel launch");
     return ok();
