@@ -438,22 +438,12 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
 #pragma unroll
             for (int s = 0; s < SPL; ++s) {
                 const uint4 *g = ge + 2 * kWave * s;
-                uint4 nx0 = make_uint4(0, 0, 0, 0), nx1 = nx0;
-                if (ngrp > 0) {
-                    nx0 = g[0];
-                    nx1 = g[1];
-                }
-                for (int it = 0; it < ngrp; ++it) {
-                    const uint4 v0 = nx0, v1 = nx1;
-                    if (it + 1 < ngrp) {
-                        nx0 = g[(size_t)(it + 1) * 2 * gw];
-                        nx1 = g[(size_t)(it + 1) * 2 * gw + 1];
-                    }
+                // one group: eight entries summed plainly (the mixed path
+                // compensates the running sum across groups); all eight reads
+                // are issued before the first sum (left to itself the scheduler
+                // waits for each read in turn)
+                auto group = [&](const uint4 &v0, const uint4 &v1, int it) {
                     const unsigned off[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-                    // the eight entries of a group are summed plainly; the
-                    // mixed path compensates the running sum across groups
-                    // all eight reads are issued before the first sum (left to
-                    // itself the scheduler waits for each read in turn)
                     double2 q2[8];
 #pragma unroll
                     for (int u = 0; u < 8; ++u)
@@ -472,7 +462,26 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
                     }
                     accumulate<MIXED>(acc[s][0], cmp[s][0], g0);
                     accumulate<MIXED>(acc[s][1], cmp[s][1], g1);
+                };
+                // two groups per trip with alternating offset registers (the
+                // next group's offsets in flight, and no copies between trips)
+                uint4 a0 = make_uint4(0, 0, 0, 0), a1 = a0, b0 = a0, b1 = a0;
+                if (ngrp > 0) {
+                    a0 = g[0];
+                    a1 = g[1];
                 }
+                int it = 0;
+                for (; it + 1 < ngrp; it += 2) {
+                    b0 = g[(size_t)(it + 1) * 2 * gw];
+                    b1 = g[(size_t)(it + 1) * 2 * gw + 1];
+                    group(a0, a1, it);
+                    if (it + 2 < ngrp) {
+                        a0 = g[(size_t)(it + 2) * 2 * gw];
+                        a1 = g[(size_t)(it + 2) * 2 * gw + 1];
+                    }
+                    group(b0, b1, it + 1);
+                }
+                if (it < ngrp) group(a0, a1, it);
             }
             wave_sync();
         }
