@@ -317,7 +317,23 @@ struct PointConst {
 //              64-lane iteration;
 //   phase 3 -- lane = species, both points: one 16-byte LDS read per list entry
 //              returns the rate of progress of the reaction at both points.
-template <bool MIXED, int SPL>
+// A 16-byte LDS read at a byte address (the gather lists hold addresses
+// relative to the dynamic LDS, which starts at 0 when the kernel has no static
+// LDS; rates_tile<..., true> is only entered after checking that).
+__device__ __forceinline__ double2 lds_read16(unsigned addr)
+{
+    typedef double v2d __attribute__((ext_vector_type(2)));
+    const v2d v = *(const __attribute__((address_space(3))) v2d *)(size_t)addr;
+    return make_double2(v.x, v.y);
+}
+
+__device__ __forceinline__ unsigned lds_base()
+{
+    extern __shared__ double lds[];
+    return (unsigned)(size_t)(__attribute__((address_space(3))) double *)lds;
+}
+
+template <bool MIXED, int SPL, bool DIRECT>
 __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t i0, int npts,
                                            int tp, const double *__restrict__ T,
                                            const double *__restrict__ P,
@@ -447,7 +463,8 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
                     double2 q2[8];
 #pragma unroll
                     for (int u = 0; u < 8; ++u)
-                        q2[u] = *reinterpret_cast<const double2 *>(qb + off[u]);
+                        q2[u] = DIRECT ? lds_read16(off[u])
+                                       : *reinterpret_cast<const double2 *>(qb + off[u]);
                     __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // DS reads
                     __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);  // VALU
                     double g0 = q2[0].x, g1 = q2[0].y;
@@ -521,7 +538,11 @@ __global__ __launch_bounds__(kWave, SPL == 1 ? 4 : (SPL == 2 ? 3 : 2)) void rate
                                                       double *__restrict__ wdot, int tp)
 {
     const int64_t i0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * tp;
-    rates_tile<MIXED, SPL>(m, n, i0, (int)min((int64_t)tp, n - i0), tp, T, P, Y, wdot);
+    const int np = (int)min((int64_t)tp, n - i0);
+    if (lds_base() == 0)
+        rates_tile<MIXED, SPL, true>(m, n, i0, np, tp, T, P, Y, wdot);
+    else
+        rates_tile<MIXED, SPL, false>(m, n, i0, np, tp, T, P, Y, wdot);
 }
 
 // Batched requests: workgroups take tiles from a shared counter until the
@@ -542,7 +563,7 @@ __global__ __launch_bounds__(kWave, SPL == 1 ? 4 : (SPL == 2 ? 3 : 2)) void rate
         while (r + 1 < wl->nitems && wl->start[0][r + 1] <= t) ++r;
         const WorkItem it = wl->items[r];
         const int64_t i0 = (int64_t)(t - wl->start[0][r]) * tp;
-        rates_tile<MIXED, SPL>(m, it.n, i0, (int)min((int64_t)tp, it.n - i0), tp, it.T, it.p,
+        rates_tile<MIXED, SPL, false>(m, it.n, i0, (int)min((int64_t)tp, it.n - i0), tp, it.T, it.p,
                                it.Y, it.wdot);
     }
 }
