@@ -30,6 +30,9 @@
  *    reference pressures; outside the table the nearest end point's k_j.
  *  - Explicit forward orders (irreversible reactions): the forward product is
  *    prod_k C_k^o_k with the listed o_k, nu'_k for unlisted reactants.
+ *  - QSS species (linearised QSSA of Lu & Law, 2006; the paper only plans
+ *    them): C_Q from wdot_Q = 0, the mixture (W-bar, third-body sums) that of
+ *    the transported species.
  *  - Units: cgs, concentrations in mol/cm^3, Ea in cal/mol.
  */
 #include <complex.h>
@@ -267,22 +270,17 @@ static void neumaier_add(double *sum, double *comp, double x)
  * scale_k = sum_i |nu_ki| |c_i| (k_f prod C^nu' + k_r prod C^nu''), the size
  * of the terms whose difference the net rate is.
  */
-static void rates_point(const kxo_mech *m, double T, double p, const double *Y,
-                        int64_t stride, double *wdot, double *scale, int64_t ostride,
-                        double *qf_out, double *qr_out, double *c_out, double *ws)
+/* The per-reaction part of the rates, from concentrations: C enters the law
+ * of mass action, Cm the third-body sums [X]_i (the same array unless QSS
+ * species are excluded from the collision partners, see below); g = G_k/RT.
+ * ws holds 3 ns doubles. */
+static void rates_conc(const kxo_mech *m, double T, double p, const double *Cm,
+                       const double *C, const double *g, double *wdot, double *scale,
+                       int64_t ostride, double *qf_out, double *qr_out, double *c_out,
+                       double *ws)
 {
     const int ns = m->ns, nr = m->nr;
-    double *C = ws, *g = ws + ns, *sum = ws + 2 * ns, *cmp = ws + 3 * ns,
-           *scl = ws + 4 * ns;
-
-    double inv_wbar = 0.0;
-    for (int k = 0; k < ns; ++k) inv_wbar += Y[k * stride] / species_weight(m, k);
-    const double wbar = 1.0 / inv_wbar;
-    for (int k = 0; k < ns; ++k) {
-        const double X = Y[k * stride] * wbar / species_weight(m, k);
-        C[k] = X * p / (KXO_RU * T);
-    }
-    kxo_thermo(m, T, NULL, NULL, NULL, g);
+    double *sum = ws, *cmp = ws + ns, *scl = ws + 2 * ns;
     for (int k = 0; k < ns; ++k) sum[k] = cmp[k] = scl[k] = 0.0;
 
     for (int i = 0; i < nr; ++i) {
@@ -291,10 +289,10 @@ static void rates_point(const kxo_mech *m, double T, double p, const double *Y,
                                        : arrhenius(m->A[i], m->beta[i], m->Ea[i], T);
         double c = 1.0;
         if (type == KXO_THREEBODY) {
-            c = third_body(m, i, C);
+            c = third_body(m, i, Cm);
         } else if (type == KXO_LINDEMANN || type == KXO_TROE || type == KXO_SRI) {
             const double k0 = arrhenius(m->A0[i], m->beta0[i], m->Ea0[i], T);
-            const double Pr = k0 * third_body(m, i, C) / kf;
+            const double Pr = k0 * third_body(m, i, Cm) / kf;
             double F = 1.0;
             if (type == KXO_TROE) F = troe_F(m->troe + 4 * i, T, Pr);
             if (type == KXO_SRI) F = sri_F(m->sri + 5 * i, T, Pr);
@@ -365,6 +363,24 @@ static void rates_point(const kxo_mech *m, double T, double p, const double *Y,
     }
 }
 
+static void rates_point(const kxo_mech *m, double T, double p, const double *Y,
+                        int64_t stride, double *wdot, double *scale, int64_t ostride,
+                        double *qf_out, double *qr_out, double *c_out, double *ws)
+{
+    const int ns = m->ns;
+    double *C = ws, *g = ws + ns;
+
+    double inv_wbar = 0.0;
+    for (int k = 0; k < ns; ++k) inv_wbar += Y[k * stride] / species_weight(m, k);
+    const double wbar = 1.0 / inv_wbar;
+    for (int k = 0; k < ns; ++k) {
+        const double X = Y[k * stride] * wbar / species_weight(m, k);
+        C[k] = X * p / (KXO_RU * T);
+    }
+    kxo_thermo(m, T, NULL, NULL, NULL, g);
+    rates_conc(m, T, p, C, C, g, wdot, scale, ostride, qf_out, qr_out, c_out, ws + 2 * ns);
+}
+
 /* Production rates for n points.  T[n], p[n] (dyn/cm^2), Y[ns][n];
  * wdot[ns][n] (mol/cm^3/s); scale[ns][n] may be NULL. */
 void kxo_production_rates(const kxo_mech *m, int64_t n, const double *T, const double *p,
@@ -389,6 +405,142 @@ void kxo_rates_detail(const kxo_mech *m, double T, double p, const double *Y,
     double *ws = malloc(sizeof(double) * 5 * (size_t)m->ns);
     rates_point(m, T, p, Y, 1, wdot, scale, 1, qf, qr, c, ws);
     free(ws);
+}
+
+/* ------------------------------------------------ quasi-steady-state species
+ *
+ * The paper names QSS species as planned work (§4) and gives no formulation.
+ * This follows the linearised QSSA of Lu & Law (J. Phys. Chem. A 110, 2006):
+ * the species flagged in qss[] are not transported; their concentrations C_Q
+ * follow from the algebraic balances wdot_q = 0.  With at most one QSS
+ * molecule on either side of every reaction, no QSS species among the listed
+ * third-body efficiencies and none in a reaction with explicit orders (the
+ * library rejects other mechanisms), every rate of progress is affine in C_Q,
+ * so wdot_Q(C_Q) = A C_Q + b.
+ *
+ * The mixture is that of the transported species: W-bar and C_k come from the
+ * non-QSS entries of Y (QSS entries are not read), and the third-body sums
+ * [X]_i run over the transported species only.
+ *
+ * The oracle does not assemble A from the reaction lists: it evaluates the
+ * plain rates above at C_Q = 0 (giving b) and at C_Q = sigma_j e_j for each j
+ * (giving column j of A as the difference over sigma_j), solves A C_Q = -b by
+ * Gaussian elimination with partial pivoting, and evaluates the plain rates
+ * once more with the solved C_Q. */
+
+/* Solve A x = r in place (A n x n row-major, r holds x on return) by Gaussian
+ * elimination with partial pivoting.  Returns -1 for an exactly zero pivot. */
+static int gepp_solve(int n, double *A, double *r)
+{
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < n; ++i)
+            if (fabs(A[i * n + k]) > fabs(A[piv * n + k])) piv = i;
+        if (A[piv * n + k] == 0.0) return -1;
+        if (piv != k) {
+            for (int j = 0; j < n; ++j) {
+                const double t = A[k * n + j];
+                A[k * n + j] = A[piv * n + j];
+                A[piv * n + j] = t;
+            }
+            const double t = r[k];
+            r[k] = r[piv];
+            r[piv] = t;
+        }
+        for (int i = k + 1; i < n; ++i) {
+            const double f = A[i * n + k] / A[k * n + k];
+            for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+            r[i] -= f * r[k];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        double s = r[k];
+        for (int j = k + 1; j < n; ++j) s -= A[k * n + j] * r[j];
+        r[k] = s / A[k * n + k];
+    }
+    return 0;
+}
+
+/* One point of the QSS rates.  wdot / scale for every species (a QSS row
+ * holds the residual of its balance), Cq[nq] the QSS concentrations in the
+ * species order.  ws: 7 ns + nq (nq + 3) doubles. */
+static void qss_point(const kxo_mech *m, const int32_t *qss, double T, double p,
+                      const double *Y, int64_t stride, double *wdot, double *scale,
+                      int64_t ostride, double *Cq, int64_t cstride, double *ws)
+{
+    const int ns = m->ns;
+    double *C = ws, *Cm = ws + ns, *g = ws + 2 * ns, *w = ws + 3 * ns, *rw = ws + 4 * ns;
+    double *Am = ws + 7 * ns;
+    int nq = 0;
+    for (int k = 0; k < ns; ++k) nq += qss[k] != 0;
+    double *b = Am + nq * nq;
+
+    double inv_wbar = 0.0;
+    for (int k = 0; k < ns; ++k)
+        if (!qss[k]) inv_wbar += Y[k * stride] / species_weight(m, k);
+    const double wbar = 1.0 / inv_wbar;
+    for (int k = 0; k < ns; ++k) {
+        const double X = qss[k] ? 0.0 : Y[k * stride] * wbar / species_weight(m, k);
+        C[k] = X * p / (KXO_RU * T);
+        Cm[k] = C[k];
+    }
+    kxo_thermo(m, T, NULL, NULL, NULL, g);
+
+    /* b = wdot_Q at C_Q = 0; column j of A = (wdot_Q(sigma_j e_j) - b) / sigma_j.
+     * A is the same for every sigma_j > 0, but the difference keeps its digits
+     * only while the C_q-terms at sigma_j are not small next to b: the first
+     * pass takes sigma_j = p/(R_u T), the later ones max(p/(R_u T), |C_q|) of
+     * the pass before. */
+    double *b0 = Am + nq * nq + nq, *x = b0 + nq;
+    rates_conc(m, T, p, Cm, C, g, w, NULL, 1, NULL, NULL, NULL, rw);
+    for (int k = 0, i = 0; k < ns; ++k)
+        if (qss[k]) b0[i++] = w[k];
+    const double ctot = p / (KXO_RU * T);
+    for (int i = 0; i < nq; ++i) x[i] = 0.0;
+    for (int pass = 0; pass < 3; ++pass) {
+        for (int kj = 0, j = 0; kj < ns; ++kj) {
+            if (!qss[kj]) continue;
+            const double sigma = fmax(ctot, fabs(x[j]));
+            C[kj] = sigma;
+            rates_conc(m, T, p, Cm, C, g, w, NULL, 1, NULL, NULL, NULL, rw);
+            C[kj] = 0.0;
+            for (int k = 0, i = 0; k < ns; ++k)
+                if (qss[k]) {
+                    Am[i * nq + j] = (w[k] - b0[i]) / sigma;
+                    ++i;
+                }
+            ++j;
+        }
+        for (int i = 0; i < nq; ++i) b[i] = -b0[i];
+        if (gepp_solve(nq, Am, b) != 0)
+            for (int i = 0; i < nq; ++i) b[i] = NAN;
+        for (int i = 0; i < nq; ++i) x[i] = isfinite(b[i]) ? b[i] : 0.0;
+    }
+    for (int k = 0, i = 0; k < ns; ++k)
+        if (qss[k]) {
+            C[k] = b[i];
+            Cq[(int64_t)i * cstride] = b[i];
+            ++i;
+        }
+    rates_conc(m, T, p, Cm, C, g, wdot, scale, ostride, NULL, NULL, NULL, rw);
+}
+
+/* Rates of a mechanism with QSS species for n points: wdot[ns][n] (QSS rows:
+ * the residual of the balance), scale[ns][n] (may be NULL), Cq[nq][n]. */
+void kxo_qss_rates(const kxo_mech *m, const int32_t *qss, int64_t n, const double *T,
+                   const double *p, const double *Y, double *wdot, double *scale, double *Cq)
+{
+    int nq = 0;
+    for (int k = 0; k < m->ns; ++k) nq += qss[k] != 0;
+#pragma omp parallel num_threads(g_threads > 0 ? g_threads : kxo_max_threads())
+    {
+        double *ws = malloc(sizeof(double) * (7 * (size_t)m->ns + (size_t)nq * (nq + 3)));
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            qss_point(m, qss, T[i], p[i], Y + i, n, wdot + i, scale ? scale + i : NULL, n,
+                      Cq + i, n, ws);
+        free(ws);
+    }
 }
 
 /* ------------------------------------------------ Jacobian by complex step

@@ -79,6 +79,7 @@ def lib():
         L.kxo_wilke_phi.restype = C.c_double
         L.kxo_transport.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
         L.kxo_jacobian.argtypes = [vp, C.c_int64, vp, vp, vp, vp]
+        L.kxo_qss_rates.argtypes = [vp, vp, C.c_int64, vp, vp, vp, vp, vp, vp]
         L.kxo_set_threads.argtypes = [C.c_int]
         L.kxo_max_threads.restype = C.c_int
         _lib = L
@@ -190,6 +191,24 @@ class OracleMech:
         jac = np.empty((n, self.ns, self.ns))
         lib().kxo_jacobian(self.ref, n, _ptr(T), _ptr(p), _ptr(Y), _ptr(jac))
         return jac
+
+    def qss_rates(self, T, p, Y, with_scale: bool = True):
+        """Rates of a mechanism whose ``qss`` flags mark quasi-steady species:
+        (wdot[ns, n], scale[ns, n] or None, Cq[nq, n]).  QSS rows of wdot hold
+        the residual of their balance; QSS entries of Y are not read."""
+        qss = np.ascontiguousarray(self.mech["qss"], dtype=np.int32)
+        nq = int(np.count_nonzero(qss))
+        T = np.ascontiguousarray(T, np.float64)
+        p = np.ascontiguousarray(p, np.float64)
+        Y = np.ascontiguousarray(Y, np.float64)
+        n = T.size
+        assert Y.shape == (self.ns, n) and qss.shape == (self.ns,)
+        wdot = np.empty((self.ns, n))
+        scale = np.empty((self.ns, n)) if with_scale else None
+        Cq = np.empty((nq, n))
+        lib().kxo_qss_rates(self.ref, _ptr(qss), n, _ptr(T), _ptr(p), _ptr(Y), _ptr(wdot),
+                            _ptr(scale), _ptr(Cq))
+        return wdot, scale, Cq
 
     # ---------------------------------------------------------------- transport
     def pure_transport(self, T: float, p: float):

@@ -363,6 +363,10 @@ class MechSpec:
     n_plog: int = 0
     # elementary -> irreversible with explicit forward orders
     n_orders: int = 0
+    # species made quasi-steady (linearised QSSA): chosen greedily so that no
+    # reaction side holds two QSS molecules, then dropped from the efficiency
+    # lists (the third-body sums run over transported species only)
+    n_qss: int = 0
 
     @property
     def n_reactions(self) -> int:
@@ -380,6 +384,67 @@ MECH_53X = MechSpec(53, 266, 30, 0, 29, seed=53325, name="syn53x", n_sri=10, n_c
                     n_plog=20)
 # syn53 with 20 irreversible reactions of non-integer forward orders
 MECH_53O = MechSpec(53, 266, 30, 0, 29, seed=53325, name="syn53o", n_orders=20)
+# syn53 with 6 quasi-steady-state species (the most the greedy choice finds)
+MECH_53Q = MechSpec(53, 266, 30, 0, 29, seed=53325, name="syn53q", n_qss=6)
+
+
+def _pick_qss(spec, ns, reac_ptr, reac_sp, reac_nu, prod_ptr, prod_sp, prod_nu, reversible,
+              orders, eff_ptr, eff_sp, eff_val):
+    """Seeded greedy choice of spec.n_qss quasi-steady species: every reaction
+    side keeps at most one QSS molecule, a QSS species is consumed by some
+    reaction and takes part in none with explicit orders.  The chosen species
+    leave the efficiency lists.  Returns (qss flags, eff_ptr, eff_sp, eff_val)."""
+    rng = np.random.Generator(np.random.PCG64(spec.seed + 9999))
+    nr = len(reac_ptr) - 1
+    sides = []
+    for i in range(nr):
+        r = {int(k): int(v) for k, v in zip(reac_sp[reac_ptr[i]:reac_ptr[i + 1]],
+                                             reac_nu[reac_ptr[i]:reac_ptr[i + 1]])}
+        q = {int(k): int(v) for k, v in zip(prod_sp[prod_ptr[i]:prod_ptr[i + 1]],
+                                             prod_nu[prod_ptr[i]:prod_ptr[i + 1]])}
+        sides.append((r, q))
+    banned = set()
+    if orders is not None:
+        optr, osp = orders["ord_ptr"], orders["ord_sp"]
+        for i in range(nr):
+            if optr[i + 1] > optr[i]:
+                banned |= set(sides[i][0]) | set(sides[i][1])
+                banned |= set(int(k) for k in osp[optr[i]:optr[i + 1]])
+    # the species in the fewest reactions first (the minor species a reduced
+    # mechanism makes quasi-steady), ties in seeded random order
+    degree = np.zeros(ns, np.int64)
+    for r, p in sides:
+        for k in set(r) | set(p):
+            degree[k] += 1
+    tie = rng.permutation(ns)
+    order = sorted(range(ns - 1), key=lambda k: (degree[k], tie[k]))  # bath stays
+    chosen = []
+    for q in order:
+        if len(chosen) == spec.n_qss:
+            break
+        if q in banned:
+            continue
+        trial = set(chosen) | {q}
+        if any(sum(v for k, v in side.items() if k in trial) > 1
+               for r, p in sides for side in (r, p)):
+            continue
+        consumed = any((r.get(q, 0) > p.get(q, 0)) or (p.get(q, 0) > r.get(q, 0) and
+                                                        reversible[i])
+                       for i, (r, p) in enumerate(sides))
+        if consumed:
+            chosen.append(q)
+    if len(chosen) < spec.n_qss:
+        raise RuntimeError("could not choose that many QSS species")
+    qss = np.zeros(ns, np.int32)
+    qss[chosen] = 1
+    ptr, sp, val = [0], [], []
+    for i in range(nr):
+        for e in range(eff_ptr[i], eff_ptr[i + 1]):
+            if not qss[eff_sp[e]]:
+                sp.append(int(eff_sp[e]))
+                val.append(float(eff_val[e]))
+        ptr.append(len(sp))
+    return qss, np.array(ptr, np.int32), np.array(sp, np.int32), np.array(val, np.float64)
 
 
 def make_mechanism(spec: MechSpec) -> dict:
@@ -577,6 +642,15 @@ def make_mechanism(spec: MechSpec) -> dict:
         plog = {"plog_ptr": np.array(pptr, np.int32), "plog_p": np.array(pp),
                 "plog_A": np.array(pA), "plog_beta": np.array(pb), "plog_Ea": np.array(pE)}
 
+    qss = None
+    eff_ptr = np.array(eff_ptr, np.int32)
+    eff_sp = np.array(eff_sp, np.int32)
+    eff_val = np.array(eff_val, np.float64)
+    if spec.n_qss:
+        qss, eff_ptr, eff_sp, eff_val = _pick_qss(
+            spec, ns, reac_ptr, reac_sp, reac_nu, prod_ptr, prod_sp, prod_nu, reversible,
+            orders, eff_ptr, eff_sp, eff_val)
+
     return {
         "name": spec.name,
         "n_species": ns,
@@ -594,9 +668,9 @@ def make_mechanism(spec: MechSpec) -> dict:
         "A": A, "beta": beta, "Ea": Ea,
         "A0": A0, "beta0": beta0, "Ea0": Ea0,
         "troe": troe,
-        "eff_ptr": np.array(eff_ptr, np.int32),
-        "eff_sp": np.array(eff_sp, np.int32),
-        "eff_val": np.array(eff_val, np.float64),
+        "eff_ptr": eff_ptr,
+        "eff_sp": eff_sp,
+        "eff_val": eff_val,
         "eff_default": eff_default,
         "fit_order": FIT_ORDER,
         "fit_L0": FIT_L0,
@@ -612,6 +686,7 @@ def make_mechanism(spec: MechSpec) -> dict:
             "plog_Ea": None}),
         **(orders if orders is not None else
            {"ord_ptr": None, "ord_sp": None, "ord_val": None}),
+        "qss": qss,
         # generator metadata (not part of the descriptor)
         "_h298_over_r": h298,
         "_s298_over_r": s298,

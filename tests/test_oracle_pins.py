@@ -646,3 +646,92 @@ def test_fit_evaluation_matches_kinetic_theory(mech53):
                                         mech53["_sigma_cm"][j], mech53["_eps_k"][k],
                                         mech53["_eps_k"][j])
         assert D[k, j] == pytest.approx(Dref, rel=3e-2)
+
+
+# ---------------------------------------------------- QSS species (planned, §4)
+def _qss_closed_form(m, T, p, Y):
+    """wdot (A, B, D) and C_Q of the chain mechanism written out by hand."""
+    om = O.OracleMech(m)
+    kf, _ = om.rate_constants(T, p)
+    g = om.thermo(T)[3]
+    kr0 = kf[0] / math.exp(-(g[TM.Q1_] - g[TM.QA_]))
+    kr1 = kf[1] / math.exp(-(g[TM.Q2_] - g[TM.Q1_]))
+    W = m["composition"] @ m["elem_mass"]
+    tr = [k for k in range(5) if not m["qss"][k]]
+    wbar = 1.0 / sum(Y[k] / W[k] for k in tr)
+    C = {k: Y[k] * wbar / W[k] * p / (O.RU * T) for k in tr}
+    M = sum(C[k] * (2.0 if k == TM.QD_ else 1.0) for k in tr)   # QSS species excluded
+    sink1 = kr0 + kf[3] * C[TM.QD_] + kf[4] * M
+    if m["qss"][TM.Q2_]:
+        q1 = kf[0] * C[TM.QA_] / (sink1 + kf[1] * kf[2] / (kr1 + kf[2]))
+        q2 = kf[1] * q1 / (kr1 + kf[2])
+    else:
+        q2 = C[TM.Q2_]
+        q1 = (kf[0] * C[TM.QA_] + kr1 * q2) / (sink1 + kf[1])
+    wA = -kf[0] * C[TM.QA_] + kr0 * q1
+    wB = kf[2] * q2 + (kf[3] * C[TM.QD_] + kf[4] * M) * q1
+    return wA, wB, q1, q2
+
+
+@pytest.mark.parametrize("qss", [(TM.Q1_, TM.Q2_), (TM.Q1_,)])
+def test_qss_chain_closed_form(qss):
+    """Linearised QSSA on A <=> Q1 <=> Q2 -> B with two more Q1 sinks, against
+    the balances solved by hand: catches a wrong sign or column in the linear
+    system, a dropped coupling between the two QSS species, and QSS species
+    counted in the mixture or in [M]."""
+    m = TM.qss_chain_mechanism(qss)
+    om = O.OracleMech(m)
+    rng = np.random.Generator(np.random.PCG64(71))
+    for T, patm in ((700.0, 1.0), (1300.0, 5.0), (2400.0, 30.0)):
+        Y = rng.uniform(0.05, 1.0, 5)
+        Y[list(qss)] = rng.uniform(0.0, 1.0, len(qss))    # not read
+        w, s, Cq = om.qss_rates(np.array([T]), np.array([patm * I.P_ATM]), Y[:, None])
+        wA, wB, q1, q2 = _qss_closed_form(m, T, patm * I.P_ATM, Y)
+        want_q = [q1, q2] if len(qss) == 2 else [q1]
+        np.testing.assert_allclose(Cq[:, 0], want_q, rtol=1e-13)
+        np.testing.assert_allclose([w[TM.QA_, 0], w[TM.QB_, 0]], [wA, wB], rtol=1e-12)
+        assert w[TM.QD_, 0] == 0.0
+        for k in qss:
+            assert abs(w[k, 0]) <= 1e-14 * s[k, 0]
+
+
+def test_qss_balances_and_mass(mech53q):
+    """On the 53-species mechanism with 6 QSS species the solved concentrations
+    make every QSS balance vanish (the plain rates re-evaluated) and the
+    transported species conserve mass: catches an inaccurate or wrong solve."""
+    om = O.OracleMech(mech53q)
+    T, p, Y = _states(53, 600, seed=23)
+    w, s, Cq = om.qss_rates(T, p, Y)
+    q = np.flatnonzero(mech53q["qss"])
+    assert Cq.shape == (len(q), 600) and (Cq >= 0).all()
+    assert (np.abs(w[q]) <= 1e-13 * s[q]).all()
+    W = mech53q["composition"] @ mech53q["elem_mass"]
+    tr = np.flatnonzero(mech53q["qss"] == 0)
+    mass = np.abs((W[tr, None] * w[tr]).sum(0))
+    assert (mass <= 1e-13 * (W[:, None] * s).sum(0)).all()
+
+
+def test_qss_without_qss_species_is_the_plain_rates(mech53):
+    """With no species flagged the QSS evaluation is the plain one, bit for bit."""
+    m = dict(mech53)
+    m["qss"] = np.zeros(53, np.int32)
+    om = O.OracleMech(m)
+    T, p, Y = _states(53, 200, seed=29)
+    w, s, Cq = om.qss_rates(T, p, Y)
+    w0, s0 = om.production_rates(T, p, Y)
+    assert Cq.shape == (0, 200)
+    np.testing.assert_array_equal(w, w0)
+    np.testing.assert_array_equal(s, s0)
+
+
+def test_qss_entries_of_Y_are_not_read(mech53q):
+    """The QSS species' mass fractions enter neither the mixture nor the rates."""
+    om = O.OracleMech(mech53q)
+    T, p, Y = _states(53, 100, seed=31)
+    Y2 = Y.copy()
+    q = np.flatnonzero(mech53q["qss"])
+    Y2[q] = np.random.Generator(np.random.PCG64(5)).uniform(0.0, 0.5, (len(q), 100))
+    a = om.qss_rates(T, p, Y)
+    b = om.qss_rates(T, p, Y2)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)

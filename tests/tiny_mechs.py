@@ -154,3 +154,34 @@ def all_forms_mechanism():
              ord=[(A_, 1.5), (D_, 0.25)], **base),
     ]
     return build(ABX_COMP, ABX_NASA, rx)
+
+
+# isomers A, Q1, Q2, B (one atom of each of the first two elements) and a bath D
+QA_, Q1_, Q2_, QB_, QD_ = 0, 1, 2, 3, 4
+QSS_COMP = [(1, 1, 0), (1, 1, 0), (1, 1, 0), (1, 1, 0), (0, 0, 2)]
+QSS_NASA = [
+    [3.3, 1.1e-3, -3.0e-7, 4.0e-11, -2.0e-15, 4.5e3, 3.9],
+    [3.1, 9.0e-4, -2.0e-7, 3.0e-11, -1.0e-15, 1.2e4, 4.4],
+    [3.6, 7.0e-4, -1.0e-7, 2.0e-11, -1.0e-15, 9.0e3, 5.0],
+    [3.4, 1.0e-3, -2.5e-7, 3.5e-11, -1.5e-15, -2.0e3, 4.1],
+    [3.5, 2.0e-4, 0.0, 0.0, 0.0, -1.0e3, 4.0],
+]
+
+
+def qss_chain_mechanism(qss=(Q1_, Q2_)):
+    """A <=> Q1 <=> Q2 -> B, Q1 + D -> B + D and Q1 (+M) -> B (+M) with
+    efficiency 2 for D; the species in `qss` are quasi-steady."""
+    rx = [
+        dict(type=0, reac=[(QA_, 1)], prod=[(Q1_, 1)], A=1e10, beta=0.2, Ea=5.0e3),
+        dict(type=0, reac=[(Q1_, 1)], prod=[(Q2_, 1)], A=3e11, beta=0.0, Ea=2.0e3),
+        dict(type=0, reac=[(Q2_, 1)], prod=[(QB_, 1)], A=5e9, beta=0.5, Ea=1.0e3, rev=0),
+        dict(type=0, reac=[(Q1_, 1), (QD_, 1)], prod=[(QB_, 1), (QD_, 1)], A=2e13,
+             beta=0.0, Ea=4.0e3, rev=0),
+        dict(type=1, reac=[(Q1_, 1)], prod=[(QB_, 1)], A=4e15, beta=-0.5, Ea=0.0, rev=0,
+             eff={QD_: 2.0}),
+    ]
+    m = build(QSS_COMP, QSS_NASA, rx)
+    flags = np.zeros(len(QSS_COMP), np.int32)
+    flags[list(qss)] = 1
+    m["qss"] = flags
+    return m
