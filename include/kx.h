@@ -140,6 +140,16 @@ typedef struct {
                                      non-zero order per reaction */
     const int32_t *ord_sp;        /*   species index */
     const double *ord_val;        /*   order o_k >= 0 (need not be an integer) */
+    /* Quasi-steady-state species (the paper plans them, §4; linearised QSSA of
+     * Lu & Law 2006).  May be NULL.  qss[k] = 1 marks species k as quasi-steady:
+     * it is not transported, and its concentration follows at every point from
+     * its balance wdot_k = 0.  Requirements (checked at create): at most 64 QSS
+     * species and at least one other; at most one QSS molecule on either side
+     * of every reaction (so the balances are linear in the QSS
+     * concentrations); no QSS species in an efficiency list or in a reaction
+     * with explicit orders; every QSS species consumed by some reaction (a
+     * reactant, or a product of a reversible reaction, with non-zero net nu). */
+    const int32_t *qss;           /* [Ns] 0 or 1 */
 } kx_mech_desc;
 
 typedef struct kx_mech kx_mech; /* opaque device-resident mechanism */
@@ -153,9 +163,13 @@ typedef struct kx_mech kx_mech; /* opaque device-resident mechanism */
  * fit_h == 0, SRI parameters outside their ranges, chem_act set on a reaction
  * that is not a falloff reaction, PLOG tables that are empty, not
  * increasing in pressure or with A <= 0, and explicit orders on a reversible
- * reaction or with a negative order.  KX_EUNSUPPORTED: more than 3 molecules (sum of nu) on one side
- * of a reaction, more than 4 species with a non-zero explicit order, or more
- * than 256 species.  On success *out owns the tables until
+ * reaction or with a negative order, qss flags other than 0 / 1, a QSS
+ * species that no reaction consumes, or no transported species.
+ * KX_EUNSUPPORTED: more than 3 molecules (sum of nu) on one side
+ * of a reaction, more than 4 species with a non-zero explicit order, more
+ * than 256 species, more than 64 QSS species, two QSS molecules on one side
+ * of a reaction, or a QSS species in an efficiency list or in a reaction with
+ * explicit orders.  On success *out owns the tables until
  * kx_mech_destroy.  Allocates device memory (hipMalloc); blocks until the
  * upload is complete. */
 kx_status kx_mech_create(const kx_mech_desc *desc, int device, kx_mech **out);
@@ -177,7 +191,12 @@ kx_status kx_mech_info(const kx_mech *mech, int32_t *n_species, int32_t *n_react
 
 /* Net production rates wdot[Ns][n] (App. A.2: wdot_k = sum_i nu_ki c_i r_i with
  * eq:arrhenius, eq:K_p / eq:Ck for K_c, eq:c_i, eq:blend and eq:r_i) for n points
- * with temperature T[n], pressure p[n] and mass fractions Y[Ns][n].  Plain FP64. */
+ * with temperature T[n], pressure p[n] and mass fractions Y[Ns][n].  Plain FP64.
+ * For a mechanism with QSS species the concentrations of those species are
+ * solved first (see kx_qss_concentrations) and enter the rates of progress;
+ * the mixture is that of the transported species (W-bar from their mass
+ * fractions, third-body sums over them), the QSS entries of Y are not read and
+ * the QSS rows of wdot are written as 0 (their balance). */
 kx_status kx_production_rates(const kx_mech *mech, int64_t n, const double *T,
                               const double *p, const double *Y, double *wdot,
                               hipStream_t stream);
@@ -186,7 +205,8 @@ kx_status kx_production_rates(const kx_mech *mech, int64_t n, const double *T,
  * Arrhenius, third-body and falloff arithmetic in FP32 (the Arrhenius
  * exponent argument is formed and range-reduced in FP64), while the species
  * Gibbs energies, K_c, the bracket of forward minus reverse terms and the
- * compensated wdot sum stay in FP64.  Inputs and outputs are FP64 either way. */
+ * compensated wdot sum stay in FP64.  Inputs and outputs are FP64 either way.
+ * KX_MIXED on a mechanism with QSS species returns KX_EUNSUPPORTED. */
 kx_status kx_production_rates_ex(const kx_mech *mech, int64_t n, const double *T,
                                  const double *p, const double *Y, double *wdot,
                                  int32_t precision, hipStream_t stream);
@@ -220,10 +240,27 @@ kx_status kx_thermo(const kx_mech *mech, int64_t n, const double *T, const doubl
  * and a pressure-table rate constant sees the change of p).  One dense
  * row-major Ns x Ns matrix per point, contiguous (the layout batched linear
  * solvers take); jac holds n * Ns * Ns doubles (device memory).  Plain FP64.
- * KX_EUNSUPPORTED for mechanisms of more than 128 species.  Where an explicit
+ * KX_EUNSUPPORTED for mechanisms of more than 128 species or with QSS
+ * species.  Where an explicit
  * order below one meets an absent species the derivative is +inf. */
 kx_status kx_jacobian(const kx_mech *mech, int64_t n, const double *T, const double *p,
                       const double *Y, double *jac, hipStream_t stream);
+
+/* Concentrations of the QSS species (mol/cm^3) for n points: Cq[j][n] for the
+ * j-th QSS species in species order.  At each point they solve the balances
+ * wdot_q = 0 of the linearised QSSA (Lu & Law 2006; the paper plans QSS
+ * species, §4): with the rates of progress affine in the QSS concentrations
+ * (at most one QSS molecule per reaction side), the balances are a linear
+ * system A C_Q = -b of order n_qss, assembled from the forward and reverse
+ * terms of the reactions and solved by elimination.  The mixture is that of
+ * the transported species; QSS entries of Y are not read.  A QSS species whose
+ * every sink vanishes at a point (a zero consumption rate) makes the system
+ * singular there and its concentration is then not finite.  Cq is device
+ * memory of n_qss * n doubles.  KX_EINVAL if the mechanism has no QSS species.
+ * Plain FP64. */
+kx_status kx_qss_concentrations(const kx_mech *mech, int64_t n, const double *T,
+                                const double *p, const double *Y, double *Cq,
+                                hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Serving: a continuous-batching request server (project addition; the paper
@@ -292,7 +329,8 @@ kx_status kx_server_destroy(kx_server *srv);
 
 /* Queue a request.  KX_EINVAL for a bad request; KX_ENOMEM if its output
  * footprint n * 8 * (Ns [wdot] + (Ns + 2) [transport]) exceeds the whole
- * budget.  n == 0 completes immediately. */
+ * budget; KX_EUNSUPPORTED for a mechanism with QSS species (call
+ * kx_production_rates for those).  n == 0 completes immediately. */
 kx_status kx_submit(kx_server *srv, const kx_request *req, kx_ticket *ticket);
 
 /* Current state and outputs of a request (non-blocking). */

@@ -466,7 +466,8 @@ static int gepp_solve(int n, double *A, double *r)
  * species order.  ws: 7 ns + nq (nq + 3) doubles. */
 static void qss_point(const kxo_mech *m, const int32_t *qss, double T, double p,
                       const double *Y, int64_t stride, double *wdot, double *scale,
-                      int64_t ostride, double *Cq, int64_t cstride, double *ws)
+                      int64_t ostride, double *Cq, int64_t cstride, double *ws,
+                      double *A_out, double *b_out)
 {
     const int ns = m->ns;
     double *C = ws, *Cm = ws + ns, *g = ws + 2 * ns, *w = ws + 3 * ns, *rw = ws + 4 * ns;
@@ -512,6 +513,10 @@ static void qss_point(const kxo_mech *m, const int32_t *qss, double T, double p,
             ++j;
         }
         for (int i = 0; i < nq; ++i) b[i] = -b0[i];
+        if (pass == 2 && A_out)
+            for (int i = 0; i < nq * nq; ++i) A_out[i] = Am[i];
+        if (pass == 2 && b_out)
+            for (int i = 0; i < nq; ++i) b_out[i] = b0[i];
         if (gepp_solve(nq, Am, b) != 0)
             for (int i = 0; i < nq; ++i) b[i] = NAN;
         for (int i = 0; i < nq; ++i) x[i] = isfinite(b[i]) ? b[i] : 0.0;
@@ -538,9 +543,24 @@ void kxo_qss_rates(const kxo_mech *m, const int32_t *qss, int64_t n, const doubl
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < n; ++i)
             qss_point(m, qss, T[i], p[i], Y + i, n, wdot + i, scale ? scale + i : NULL, n,
-                      Cq + i, n, ws);
+                      Cq + i, n, ws, NULL, NULL);
         free(ws);
     }
+}
+
+/* The linear system of the QSS balances at one point, as the oracle takes it
+ * (A[nq][nq] row-major and b[nq] with wdot_Q = A C_Q + b); Y is contiguous. */
+void kxo_qss_system(const kxo_mech *m, const int32_t *qss, double T, double p,
+                    const double *Y, double *A, double *b)
+{
+    int nq = 0;
+    for (int k = 0; k < m->ns; ++k) nq += qss[k] != 0;
+    double *ws = malloc(sizeof(double) * (7 * (size_t)m->ns + (size_t)nq * (nq + 3)));
+    double *w = malloc(sizeof(double) * 2 * (size_t)m->ns), *c = malloc(sizeof(double) * (nq + 1));
+    qss_point(m, qss, T, p, Y, 1, w, NULL, 1, c, 1, ws, A, b);
+    free(ws);
+    free(w);
+    free(c);
 }
 
 /* ------------------------------------------------ Jacobian by complex step

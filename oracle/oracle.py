@@ -80,6 +80,7 @@ def lib():
         L.kxo_transport.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
         L.kxo_jacobian.argtypes = [vp, C.c_int64, vp, vp, vp, vp]
         L.kxo_qss_rates.argtypes = [vp, vp, C.c_int64, vp, vp, vp, vp, vp, vp]
+        L.kxo_qss_system.argtypes = [vp, vp, C.c_double, C.c_double, vp, vp, vp]
         L.kxo_set_threads.argtypes = [C.c_int]
         L.kxo_max_threads.restype = C.c_int
         _lib = L
@@ -209,6 +210,15 @@ class OracleMech:
         lib().kxo_qss_rates(self.ref, _ptr(qss), n, _ptr(T), _ptr(p), _ptr(Y), _ptr(wdot),
                             _ptr(scale), _ptr(Cq))
         return wdot, scale, Cq
+
+    def qss_system(self, T: float, p: float, Y):
+        """(A[nq, nq], b[nq]) of the QSS balances wdot_Q = A C_Q + b at one point."""
+        qss = np.ascontiguousarray(self.mech["qss"], dtype=np.int32)
+        nq = int(np.count_nonzero(qss))
+        Y = np.ascontiguousarray(Y, np.float64)
+        A, b = np.empty((nq, nq)), np.empty(nq)
+        lib().kxo_qss_system(self.ref, _ptr(qss), float(T), float(p), _ptr(Y), _ptr(A), _ptr(b))
+        return A, b
 
     # ---------------------------------------------------------------- transport
     def pure_transport(self, T: float, p: float):

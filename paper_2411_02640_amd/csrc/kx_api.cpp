@@ -104,10 +104,14 @@ kx_status kx_production_rates_ex(const kx_mech *mech, int64_t n, const double *T
     if (st != KX_OK) return st;
     if (precision != KX_FP64 && precision != KX_MIXED)
         return fail(KX_EINVAL, "kx_production_rates: unknown precision");
+    if (mech->dev.nq > 0 && precision != KX_FP64)
+        return fail(KX_EUNSUPPORTED, "kx_production_rates: mechanisms with QSS species are "
+                                     "evaluated in FP64 only");
     if (n == 0) return ok();
     if (!T || !p || !Y || !wdot) return fail(KX_EINVAL, "kx_production_rates: NULL array");
     DeviceGuard g(mech->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    if (mech->dev.nq > 0) return launch_qss(mech, n, T, p, Y, wdot, nullptr, stream);
     return launch_rates(mech, n, T, p, Y, wdot, precision, stream);
 }
 
@@ -159,11 +163,28 @@ kx_status kx_jacobian(const kx_mech *mech, int64_t n, const double *T, const dou
 {
     kx_status st = check_common(mech, n, "kx_jacobian");
     if (st != KX_OK) return st;
+    if (mech->dev.nq > 0)
+        return fail(KX_EUNSUPPORTED, "kx_jacobian: mechanisms with QSS species are not supported");
     if (n == 0) return ok();
     if (!T || !p || !Y || !jac) return fail(KX_EINVAL, "kx_jacobian: NULL array");
     DeviceGuard g(mech->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     return launch_jacobian(mech, n, T, p, Y, jac, stream);
+}
+
+kx_status kx_qss_concentrations(const kx_mech *mech, int64_t n, const double *T,
+                                const double *p, const double *Y, double *Cq,
+                                hipStream_t stream)
+{
+    kx_status st = check_common(mech, n, "kx_qss_concentrations");
+    if (st != KX_OK) return st;
+    if (mech->dev.nq == 0)
+        return fail(KX_EINVAL, "kx_qss_concentrations: the mechanism has no QSS species");
+    if (n == 0) return ok();
+    if (!T || !p || !Y || !Cq) return fail(KX_EINVAL, "kx_qss_concentrations: NULL array");
+    DeviceGuard g(mech->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    return launch_qss(mech, n, T, p, Y, nullptr, Cq, stream);
 }
 
 const char *kx_last_error(void) { return t_last_error.c_str(); }

@@ -20,6 +20,7 @@ constexpr int kMaxSide = 3;          // molecules per reaction side (sum of nu)
 constexpr int kMaxSpecies = 256;     // species per mechanism (4 per lane)
 constexpr int kMaxFitOrder = 8;
 constexpr int kWave = 64;
+constexpr int kMaxQss = 64;          // QSS species per mechanism (one wave of rows)
 
 // Reaction flags.
 enum : uint8_t {
@@ -144,6 +145,14 @@ struct MechDev {
     int32_t mblk, kstep;
     const double *gfrag, *c1frag;
     const float *gfrag32, *c1frag32;
+    // Quasi-steady-state species (nq = 0 when there are none).  QSS index j
+    // numbers them in species order.
+    int32_t nq;
+    const int32_t *qidx;       // [ns] QSS index of species k, -1 if transported
+    const int32_t *qrow_ptr;   // [nq + 1] entries of the balance of QSS species j
+    const int2 *qrow_ent;      // {reaction slot in kernel order, net nu of j}
+    const int2 *qrx;           // [nr] kernel order: QSS index among the reactants,
+                               // among the products (-1: none)
 };
 
 // Work list of one batch of served requests (device memory, written by the
@@ -190,6 +199,9 @@ kx_status launch_thermo(const kx_mech *m, int64_t n, const double *T, const doub
                         double *cpk, double *hk, double *cpmix, hipStream_t s);
 kx_status launch_jacobian(const kx_mech *m, int64_t n, const double *T, const double *p,
                           const double *Y, double *jac, hipStream_t s);
+// Rates of a mechanism with QSS species; either output may be null.
+kx_status launch_qss(const kx_mech *m, int64_t n, const double *T, const double *p,
+                     const double *Y, double *wdot, double *Cq, hipStream_t s);
 
 // Points per tile of the two kernels for a mechanism and precision (the
 // serving work lists are cut in the same tiles as a direct call, so a request

@@ -48,6 +48,82 @@ template <class T> size_t add_vec(Blob &b, const std::vector<T> &v)
     return b.add(v.data(), v.size() * sizeof(T));
 }
 
+// Net stoichiometric coefficient nu''_ki - nu'_ki of species k in reaction i.
+int net_nu(const kx_mech_desc *d, int i, int k)
+{
+    int nu = 0;
+    for (int e = d->reac_ptr[i]; e < d->reac_ptr[i + 1]; ++e)
+        if (d->reac_sp[e] == k) nu -= d->reac_nu[e];
+    for (int e = d->prod_ptr[i]; e < d->prod_ptr[i + 1]; ++e)
+        if (d->prod_sp[e] == k) nu += d->prod_nu[e];
+    return nu;
+}
+
+// QSS species of one side of reaction i (the first one) and their molecule count.
+int qss_side(const kx_mech_desc *d, int i, bool prod, int *count)
+{
+    const int32_t *ptr = prod ? d->prod_ptr : d->reac_ptr;
+    const int32_t *sp = prod ? d->prod_sp : d->reac_sp;
+    const int32_t *nu = prod ? d->prod_nu : d->reac_nu;
+    int first = -1, c = 0;
+    for (int e = ptr[i]; e < ptr[i + 1]; ++e)
+        if (d->qss[sp[e]]) {
+            if (first < 0) first = sp[e];
+            c += nu[e];
+        }
+    *count = c;
+    return first;
+}
+
+// The linearised QSSA needs every rate of progress affine in the QSS
+// concentrations and every QSS balance to hold a sink.
+kx_status validate_qss(const kx_mech_desc *d)
+{
+    const int ns = d->n_species, nr = d->n_reactions;
+    int nq = 0;
+    for (int k = 0; k < ns; ++k) {
+        if (d->qss[k] != 0 && d->qss[k] != 1)
+            return fail(KX_EINVAL, "kx_mech_create: qss flags must be 0 or 1");
+        nq += d->qss[k];
+    }
+    if (nq > kMaxQss)
+        return fail(KX_EUNSUPPORTED, "kx_mech_create: at most 64 QSS species are supported");
+    if (nq == ns) return fail(KX_EINVAL, "kx_mech_create: every species is QSS");
+    std::vector<char> consumed(ns, 0);
+    for (int i = 0; i < nr; ++i) {
+        const std::string ri = " (reaction " + std::to_string(i) + ")";
+        int cr = 0, cp = 0;
+        qss_side(d, i, false, &cr);
+        qss_side(d, i, true, &cp);
+        if (cr > 1 || cp > 1)
+            return fail(KX_EUNSUPPORTED, "kx_mech_create: two QSS molecules on one side of a "
+                                         "reaction" + ri);
+        const int t = d->rxn_type[i];
+        if (t != KX_RXN_ELEMENTARY && t != KX_RXN_PLOG)
+            for (int e = d->eff_ptr[i]; e < d->eff_ptr[i + 1]; ++e)
+                if (d->qss[d->eff_sp[e]])
+                    return fail(KX_EUNSUPPORTED, "kx_mech_create: QSS species in an "
+                                                 "efficiency list" + ri);
+        if (d->ord_ptr && d->ord_ptr[i + 1] > d->ord_ptr[i]) {
+            bool any = cr > 0 || cp > 0;
+            for (int e = d->ord_ptr[i]; e < d->ord_ptr[i + 1]; ++e) any |= d->qss[d->ord_sp[e]] != 0;
+            if (any)
+                return fail(KX_EUNSUPPORTED, "kx_mech_create: QSS species in a reaction with "
+                                             "explicit orders" + ri);
+        }
+        for (int k = 0; k < ns; ++k) {
+            if (!d->qss[k]) continue;
+            const int nu = net_nu(d, i, k);
+            if (nu < 0 || (nu > 0 && d->reversible[i])) consumed[k] = 1;
+        }
+    }
+    for (int k = 0; k < ns; ++k)
+        if (d->qss[k] && !consumed[k])
+            return fail(KX_EINVAL, "kx_mech_create: QSS species " + std::to_string(k) +
+                                       " is consumed by no reaction");
+    return KX_OK;
+}
+
 kx_status validate(const kx_mech_desc *d, std::vector<double> &W)
 {
     if (!d) return fail(KX_EINVAL, "kx_mech_create: desc is NULL");
@@ -185,6 +261,7 @@ kx_status validate(const kx_mech_desc *d, std::vector<double> &W)
                     return fail(KX_EINVAL, "kx_mech_create: efficiency species out of range" + ri);
         }
     }
+    if (d->qss) return validate_qss(d);
     return KX_OK;
 }
 
@@ -406,6 +483,33 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     }
     if (gent.empty()) gent.resize(8, 0);
 
+    // ---- QSS species: index per species, per reaction (kernel order) the QSS
+    // species of either side, and per QSS species the reactions of its balance
+    int nq = 0;
+    std::vector<int32_t> qidx(ns, -1);
+    if (d->qss)
+        for (int k = 0; k < ns; ++k)
+            if (d->qss[k]) qidx[k] = nq++;
+    std::vector<int2> qrx(std::max(nr, 1), int2{-1, -1});
+    std::vector<int32_t> qrow_ptr(nq + 1, 0);
+    std::vector<int2> qrow_ent;
+    if (nq > 0) {
+        for (int s = 0; s < nr; ++s) {
+            int c = 0;
+            const int a = qss_side(d, perm[s], false, &c), b = qss_side(d, perm[s], true, &c);
+            qrx[s] = int2{a >= 0 ? qidx[a] : -1, b >= 0 ? qidx[b] : -1};
+        }
+        for (int k = 0; k < ns; ++k) {
+            if (qidx[k] < 0) continue;
+            for (int s = 0; s < nr; ++s) {
+                const int nu = net_nu(d, perm[s], k);
+                if (nu != 0) qrow_ent.push_back(int2{s, nu});
+            }
+            qrow_ptr[qidx[k] + 1] = (int32_t)qrow_ent.size();
+        }
+    }
+    if (qrow_ent.empty()) qrow_ent.push_back(int2{0, 0});
+
     // ---- species thermo
     std::vector<DevSpecies> spv(ns);
     for (int k = 0; k < ns; ++k) {
@@ -498,6 +602,8 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     const size_t o_dd32 = add_vec(b, to32(ddiag));
     const size_t o_gf = add_vec(b, gfrag), o_c1f = add_vec(b, c1frag);
     const size_t o_gf32 = add_vec(b, to32(gfrag)), o_c1f32 = add_vec(b, to32(c1frag));
+    const size_t o_qidx = add_vec(b, qidx), o_qrx = add_vec(b, qrx);
+    const size_t o_qptr = add_vec(b, qrow_ptr), o_qent = add_vec(b, qrow_ent);
 
     void *blob = nullptr;
     if (!host_only) {
@@ -570,6 +676,11 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     v.c1frag = mfma ? (const double *)at(o_c1f) : nullptr;
     v.gfrag32 = mfma ? (const float *)at(o_gf32) : nullptr;
     v.c1frag32 = mfma ? (const float *)at(o_c1f32) : nullptr;
+    v.nq = nq;
+    v.qidx = (const int32_t *)at(o_qidx);
+    v.qrx = (const int2 *)at(o_qrx);
+    v.qrow_ptr = (const int32_t *)at(o_qptr);
+    v.qrow_ent = (const int2 *)at(o_qent);
     *out = m;
     return ok();
 }

@@ -502,6 +502,8 @@ kx_status kx_submit(kx_server *s, const kx_request *r, kx_ticket *ticket)
         return fail(KX_EINVAL, "kx_submit: NULL input array");
     if (!s->simulate && r->mech->device != s->device)
         return fail(KX_EINVAL, "kx_submit: mechanism lives on another device");
+    if (r->mech->dev.nq > 0)
+        return fail(KX_EUNSUPPORTED, "kx_submit: mechanisms with QSS species are not served");
     const size_t bytes = r->n > 0 ? footprint(*r, r->mech->n_species) : 0;
     if (bytes > s->arena.capacity())
         return fail(KX_ENOMEM, "kx_submit: request outputs exceed the server's HBM budget");

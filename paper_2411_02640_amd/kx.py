@@ -49,7 +49,7 @@ class _Desc(C.Structure):
         ("visc_fit", _dp), ("cond_fit", _dp), ("diff_fit", _dp),
         ("sri", _dp), ("chem_act", _ip), ("plog_ptr", _ip), ("plog_p", _dp),
         ("plog_A", _dp), ("plog_beta", _dp), ("plog_Ea", _dp),
-        ("ord_ptr", _ip), ("ord_sp", _ip), ("ord_val", _dp),
+        ("ord_ptr", _ip), ("ord_sp", _ip), ("ord_val", _dp), ("qss", _ip),
     ]
 
 
@@ -60,7 +60,7 @@ _I32_FIELDS = ["composition", "rxn_type", "reversible", "reac_ptr", "reac_sp", "
 
 # Optional arrays of the further reaction forms (NULL when a mechanism has none).
 _OPT_F64_FIELDS = ["sri", "plog_p", "plog_A", "plog_beta", "plog_Ea", "ord_val"]
-_OPT_I32_FIELDS = ["chem_act", "plog_ptr", "ord_ptr", "ord_sp"]
+_OPT_I32_FIELDS = ["chem_act", "plog_ptr", "ord_ptr", "ord_sp", "qss"]
 
 _lib = None
 
@@ -83,10 +83,12 @@ def lib():
         L.kx_transport_ex.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, i32, vp]
         L.kx_thermo.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
         L.kx_jacobian.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        L.kx_qss_concentrations.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.kx_last_error.restype = C.c_char_p
         L.kx_version.restype = C.c_char_p
         for name in ("kx_mech_create", "kx_mech_destroy", "kx_mech_info", "kx_production_rates",
-                     "kx_production_rates_ex", "kx_transport", "kx_transport_ex", "kx_thermo"):
+                     "kx_production_rates_ex", "kx_transport", "kx_transport_ex", "kx_thermo",
+                     "kx_jacobian", "kx_qss_concentrations"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -152,6 +154,8 @@ class Mechanism:
         check(lib().kx_mech_info(h, C.byref(ns), C.byref(nr), C.byref(nb)))
         self.n_species, self.n_reactions, self.device_bytes = ns.value, nr.value, nb.value
         self.name = mech.get("name", "")
+        q = mech.get("qss")
+        self.n_qss = 0 if q is None else int(np.count_nonzero(q))
 
     def close(self) -> None:
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -238,6 +242,21 @@ def jacobian(mech: Mechanism, T, p, Y, out=None, stream=None):
         out = torch.empty((n, ns, ns), dtype=torch.float64, device=f"cuda:{dev}")
     j = _dev_tensor(out, dev, (n, ns, ns), "out")
     check(lib().kx_jacobian(mech.handle, n, *args, j, _stream_ptr(stream, dev)))
+    return out
+
+
+def qss_concentrations(mech: Mechanism, T, p, Y, out=None, stream=None):
+    """Cq[n_qss, n] (mol/cm^3): the concentrations of the mechanism's QSS
+    species, in species order, for device tensors T, p, Y."""
+    n = T.shape[0]
+    ns, nq = mech.n_species, mech.n_qss
+    dev = mech.device
+    args = [_dev_tensor(T, dev, (n,), "T"), _dev_tensor(p, dev, (n,), "p"),
+            _dev_tensor(Y, dev, (ns, n), "Y")]
+    if out is None:
+        out = torch.empty((max(nq, 1), n), dtype=torch.float64, device=f"cuda:{dev}")[:nq]
+    c = _dev_tensor(out, dev, (nq, n), "out")
+    check(lib().kx_qss_concentrations(mech.handle, n, *args, c, _stream_ptr(stream, dev)))
     return out
 
 

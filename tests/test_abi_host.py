@@ -37,7 +37,8 @@ def test_version():
     assert "gfx950" in kx.version()
 
 
-@pytest.mark.parametrize("name", ["mech9", "mech53", "mech200", "mech53x", "mech53o"])
+@pytest.mark.parametrize("name", ["mech9", "mech53", "mech200", "mech53x", "mech53o",
+                                  "mech53q"])
 def test_host_create(name, request):
     mech = request.getfixturevalue(name)
     m = kx.HostMechanism(mech)
@@ -221,3 +222,52 @@ def test_explicit_orders_validation():
     rx = [dict(type=0, reac=[(0, 1), (1, 1)], prod=[(2, 1)], A=1e12, beta=0.0, Ea=0.0, rev=0,
                ord=[(2, 0.1), (3, 0.1), (4, 0.1)])]
     _expect(tiny_mechs.build(comp, nasa, rx), kx.KX_EUNSUPPORTED, "more than 4")
+
+
+# ------------------------------------------------------------- QSS species
+TM = tiny_mechs
+
+
+def _chain(**kw):
+    m = TM.qss_chain_mechanism()
+    m.update(kw)
+    return m
+
+
+def test_qss_validation():
+    kx.HostMechanism(_chain()).close()
+    kx.HostMechanism(TM.qss_chain_mechanism((TM.Q1_,))).close()
+    _expect(_chain(qss=np.array([0, 2, 0, 0, 0], np.int32)), kx.KX_EINVAL, "0 or 1")
+    _expect(_chain(qss=np.ones(5, np.int32)), kx.KX_EINVAL, "every species is QSS")
+    # B is produced only by irreversible reactions: nothing consumes it
+    _expect(_chain(qss=np.array([0, 0, 0, 1, 0], np.int32)), kx.KX_EINVAL, "consumed by no")
+    # a collider efficiency for a QSS species makes [M] depend on it
+    m = TM.qss_chain_mechanism()
+    m["eff_sp"] = np.array([TM.Q2_], np.int32)
+    _expect(m, kx.KX_EUNSUPPORTED, "efficiency list")
+    # two QSS molecules on one side: Q1 + Q2 -> A + B
+    m = TM.qss_chain_mechanism()
+    comp, nasa = TM.QSS_COMP, TM.QSS_NASA
+    rx = [dict(type=0, reac=[(TM.QA_, 1)], prod=[(TM.Q1_, 1)], A=1e10, beta=0.0, Ea=0.0),
+          dict(type=0, reac=[(TM.Q1_, 1), (TM.Q2_, 1)], prod=[(TM.QA_, 1), (TM.QB_, 1)],
+               A=1e12, beta=0.0, Ea=0.0)]
+    bad = TM.build(comp, nasa, rx)
+    bad["qss"] = np.array([0, 1, 1, 0, 0], np.int32)
+    _expect(bad, kx.KX_EUNSUPPORTED, "two QSS molecules")
+    # a QSS species in a reaction with explicit orders
+    rx = [dict(type=0, reac=[(TM.QA_, 1)], prod=[(TM.Q1_, 1)], A=1e10, beta=0.0, Ea=0.0),
+          dict(type=0, reac=[(TM.Q1_, 1)], prod=[(TM.QB_, 1)], A=1e9, beta=0.0, Ea=0.0,
+               rev=0, ord=[(TM.Q1_, 0.5)])]
+    bad = TM.build(comp, nasa, rx)
+    bad["qss"] = np.array([0, 1, 0, 0, 0], np.int32)
+    _expect(bad, kx.KX_EUNSUPPORTED, "explicit orders")
+
+
+def test_qss_entry_points_reject_what_they_do_not_cover():
+    L = kx.lib()
+    m = kx.HostMechanism(_tiny())
+    # a host-only handle has no device tables; a mechanism without QSS species
+    # is refused by the concentration call before any device work
+    rc = L.kx_qss_concentrations(m.handle, 1, None, None, None, None, None)
+    assert rc == kx.KX_EINVAL
+    m.close()
