@@ -172,6 +172,28 @@ def other_workloads(kx, I, torch, steps, warmup):
                                   "output_GB_s": nj * 53 * 53 * 8 / (jms * 1e-3) / 1e9}
     del out, T, p, Y
     dm.close()
+    # rates of the 53-species mechanism with 6 QSS species: the QSS balances
+    # solved per point before the rates, 2^20 points
+    log("qss syn53q at 2^20 points")
+    mq = I.make_mechanism(I.MECH_53Q)
+    dq = kx.Mechanism(mq, 0)
+    nq = 1 << 20
+    (_, T, p, Y), = serve_load.make_pool(dq, 53, [nq], 31)
+    wq = torch.empty((53, nq), dtype=torch.float64, device="cuda:0")
+    for _ in range(warmup):
+        kx.production_rates(dq, T, p, Y, out=wq)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        kx.production_rates(dq, T, p, Y, out=wq)
+    ev[1].record()
+    torch.cuda.synchronize()
+    qms = ev[0].elapsed_time(ev[1]) / steps
+    res["qss_syn53q_2p20"] = {"n_points": nq, "n_qss": int(dq.n_qss), "rates_ms": qms,
+                              "Mpoints_s": nq / qms / 1e3}
+    del wq, T, p, Y
+    dq.close()
     torch.cuda.empty_cache()
     return res
 

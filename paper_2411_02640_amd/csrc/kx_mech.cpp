@@ -492,7 +492,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
             if (d->qss[k]) qidx[k] = nq++;
     std::vector<int2> qrx(std::max(nr, 1), int2{-1, -1});
     std::vector<int32_t> qrow_ptr(nq + 1, 0);
-    std::vector<int2> qrow_ent;
+    std::vector<int4> qrow_ent;
     if (nq > 0) {
         for (int s = 0; s < nr; ++s) {
             int c = 0;
@@ -503,12 +503,12 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
             if (qidx[k] < 0) continue;
             for (int s = 0; s < nr; ++s) {
                 const int nu = net_nu(d, perm[s], k);
-                if (nu != 0) qrow_ent.push_back(int2{s, nu});
+                if (nu != 0) qrow_ent.push_back(int4{s, nu, qrx[s].x, qrx[s].y});
             }
             qrow_ptr[qidx[k] + 1] = (int32_t)qrow_ent.size();
         }
     }
-    if (qrow_ent.empty()) qrow_ent.push_back(int2{0, 0});
+    if (qrow_ent.empty()) qrow_ent.push_back(int4{0, 0, -1, -1});
 
     // ---- species thermo
     std::vector<DevSpecies> spv(ns);
@@ -680,7 +680,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     v.qidx = (const int32_t *)at(o_qidx);
     v.qrx = (const int2 *)at(o_qrx);
     v.qrow_ptr = (const int32_t *)at(o_qptr);
-    v.qrow_ent = (const int2 *)at(o_qent);
+    v.qrow_ent = (const int4 *)at(o_qent);
     *out = m;
     return ok();
 }
