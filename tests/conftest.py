@@ -17,7 +17,8 @@ def pytest_configure(config):
 def _mech(name):
     from paper_2411_02640_amd import inputs as I
     spec = {"syn9": I.MECH_9, "syn53": I.MECH_53, "syn200": I.MECH_200,
-            "syn53x": I.MECH_53X, "syn53o": I.MECH_53O, "syn53q": I.MECH_53Q}[name]
+            "syn53x": I.MECH_53X, "syn53o": I.MECH_53O, "syn53q": I.MECH_53Q,
+            "syn53xq": I.MECH_53XQ}[name]
     return I.make_mechanism(spec)
 
 
@@ -49,6 +50,11 @@ def mech53o():
 @pytest.fixture(scope="session")
 def mech53q():
     return _mech("syn53q")
+
+
+@pytest.fixture(scope="session")
+def mech53xq():
+    return _mech("syn53xq")
 
 
 @pytest.fixture(scope="session")

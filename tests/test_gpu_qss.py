@@ -123,6 +123,18 @@ def test_qss_syn53q_block(kx, mech53q):
     dm.close()
 
 
+def test_qss_further_forms(kx, mech53xq):
+    """QSS species in SRI and pressure-table reactions (syn53x with 6 QSS
+    species), 1031 points at 0.05-150 atm (below, inside and above the tables)."""
+    T, p, Y = I.make_states(53, I.StateSpec(1031, seed=87, p_atm_range=(0.05, 150.0),
+                                            dirichlet_alpha=0.3))
+    _say("qss syn53xq n =", T.size)
+    dm = kx.Mechanism(mech53xq, 0)
+    w, Cq = run_qss(kx, dm, T, p, Y)
+    compare(mech53xq, w, Cq, T, p, Y, "syn53xq")
+    dm.close()
+
+
 def test_qss_full_size_sampled(kx, mech53q):
     """The 2^20-point workload in the launch configuration the benchmark times
     (the grid strides over points); the oracle checks a sample."""

@@ -695,12 +695,16 @@ def test_qss_chain_closed_form(qss):
             assert abs(w[k, 0]) <= 1e-14 * s[k, 0]
 
 
-def test_qss_balances_and_mass(mech53q):
-    """On the 53-species mechanism with 6 QSS species the solved concentrations
-    make every QSS balance vanish (the plain rates re-evaluated) and the
-    transported species conserve mass: catches an inaccurate or wrong solve."""
+@pytest.mark.parametrize("name", ["mech53q", "mech53xq"])
+def test_qss_balances_and_mass(name, request):
+    """On the 53-species mechanisms with 6 QSS species (the second with SRI,
+    chemically activated and pressure-table reactions) the solved
+    concentrations make every QSS balance vanish (the plain rates
+    re-evaluated) and the transported species conserve mass: catches an
+    inaccurate or wrong solve."""
+    mech53q = request.getfixturevalue(name)
     om = O.OracleMech(mech53q)
-    T, p, Y = _states(53, 600, seed=23)
+    T, p, Y = _states(53, 600, seed=23, p_atm=(0.05, 150.0))
     w, s, Cq = om.qss_rates(T, p, Y)
     q = np.flatnonzero(mech53q["qss"])
     assert Cq.shape == (len(q), 600) and (Cq >= 0).all()
