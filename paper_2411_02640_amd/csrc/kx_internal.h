@@ -150,8 +150,9 @@ struct MechDev {
     int32_t nq;
     const int32_t *qidx;       // [ns] QSS index of species k, -1 if transported
     const int32_t *qrow_ptr;   // [nq + 1] entries of the balance of QSS species j
-    const int4 *qrow_ent;      // {reaction slot in kernel order, net nu of j, QSS index
-                               //  among the reaction's reactants, among its products}
+    const int4 *qrow_ent;      // {LDS slot of the reaction (kernel order s, at s + s /
+                               //  chunk), net nu of j, QSS index among the reaction's
+                               //  reactants, among its products}
     const int2 *qrx;           // [nr] kernel order: QSS index among the reactants,
                                // among the products (-1: none)
 };

@@ -503,7 +503,9 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
             if (qidx[k] < 0) continue;
             for (int s = 0; s < nr; ++s) {
                 const int nu = net_nu(d, perm[s], k);
-                if (nu != 0) qrow_ent.push_back(int4{s, nu, qrx[s].x, qrx[s].y});
+                // x: the reaction's LDS slot in the QSS kernel (a zero slot
+                // follows each chunk, so reaction s sits at s + s / chunk)
+                if (nu != 0) qrow_ent.push_back(int4{s + s / chunk, nu, qrx[s].x, qrx[s].y});
             }
             qrow_ptr[qidx[k] + 1] = (int32_t)qrow_ent.size();
         }

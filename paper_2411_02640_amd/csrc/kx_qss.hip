@@ -77,7 +77,8 @@ size_t qss_lds_bytes(const MechDev &m)
 {
     const size_t ns = (size_t)m.ns, nr = (size_t)m.nr, nq = (size_t)m.nq;
     return sizeof(QPair) * (ns + 1)              // {a, C} per species (+dummy)
-           + 2 * sizeof(double) * std::max<size_t>(nr, 1)  // {F', B'}, then R
+           + 2 * sizeof(double) * (size_t)m.nchunks * (m.chunk + 1)  // {F', B'}, then R,
+                                                   // per chunk: chunk slots and a zero slot
            + sizeof(double) * (nq * (nq + 1) + nq + 4);     // [A | b], x, W-bar partials
 }
 
@@ -94,7 +95,10 @@ __global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
     const int ld = nq + 1;  // row stride of [A | b]
     QPair *sp = reinterpret_cast<QPair *>(lds);
     double2 *rec = reinterpret_cast<double2 *>(sp + ns + 1);
-    double *Am = reinterpret_cast<double *>(rec + std::max(nr, 1));
+    // chunk c owns rec[c (chunk + 1) ...]: its reactions (reaction r of the chunk
+    // at base + c + r), then at offset chunk the zero slot that the padding
+    // entries of the gather lists address (also for a partial last chunk)
+    double *Am = reinterpret_cast<double *>(rec + m.nchunks * (m.chunk + 1));
     double *x = Am + nq * ld;
     double *red = x + nq;
     const int gw = kWave * m.gpass;
@@ -135,7 +139,12 @@ __global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
         __syncthreads();
 
         // ---- phase 2: one reaction per thread
-        for (int r = tid; r < nr; r += NT) {
+        for (int c = 0; c < m.nchunks; ++c) {
+          const int base = c * m.chunk, cnt = min(m.chunk, nr - base);
+          double2 *rc = rec + base + c;
+          if (tid == 0) rc[m.chunk] = make_double2(0.0, 0.0);
+          for (int rr = tid; rr < cnt; rr += NT) {
+            const int r = base + rr;
             const DevRxn &R = m.rxn[r];
             const unsigned type = R.type, flags = R.flags;
             const bool kconst = (flags & kFlagKfConst) != 0;
@@ -197,7 +206,8 @@ __global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
                     cmod = (flags & kFlagChemAct) ? e0 * Fb * h : Pr * Fb * h;
                 }
             }
-            rec[r] = make_double2(cmod * F, cmod * B);
+            rc[rr] = make_double2(cmod * F, cmod * B);
+          }
         }
         __syncthreads();
 
@@ -245,20 +255,25 @@ __global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
 
         if (wdot) {
             // ---- phase 5: rates of progress with the QSS factors
-            for (int r = tid; r < nr; r += NT) {
-                const int2 q = m.qrx[r];
-                const double2 fb = rec[r];
-                const double cs = q.x >= 0 ? x[q.x] : 1.0, ct = q.y >= 0 ? x[q.y] : 1.0;
-                rec[r].x = fma(fb.x, cs, -fb.y * ct);
+            for (int c = 0; c < m.nchunks; ++c) {
+                const int base = c * m.chunk, cnt = min(m.chunk, nr - base);
+                for (int rr = tid; rr < cnt; rr += NT) {
+                    const int2 q = m.qrx[base + rr];
+                    double2 &f = rec[base + c + rr];
+                    const double cs = q.x >= 0 ? x[q.x] : 1.0, ct = q.y >= 0 ? x[q.y] : 1.0;
+                    f.x = fma(f.x, cs, -f.y * ct);
+                }
             }
             __syncthreads();
             // ---- phase 6: wdot_k from the gather lists, chunk by chunk
             for (int k = tid; k < ns; k += NT) {
                 double acc = 0.0;
                 for (int c = 0; c < m.nchunks; ++c) {
-                    const int base = c * m.chunk, cnt = min(m.chunk, nr - base);
+                    const int base = c * m.chunk;
                     const int npos = m.gpos[c], ngrp = npos + m.gneg[c];
                     const uint4 *ge = m.gent + ((size_t)m.goff[c] * gw + k) * 2;
+                    // list entries are byte offsets into the chunk's slots
+                    const char *cb = reinterpret_cast<const char *>(rec + base + c);
                     // four groups per trip, their list loads issued together
                     for (int it0 = 0; it0 < ngrp; it0 += 4) {
                         uint4 v[8];
@@ -277,10 +292,8 @@ __global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
                                                      v[2 * g + 1].z, v[2 * g + 1].w};
                             double s = 0.0;
 #pragma unroll
-                            for (int u = 0; u < 8; ++u) {
-                                const int r = (int)(off[u] / 16);
-                                if (r < cnt) s += rec[base + r].x;
-                            }
+                            for (int u = 0; u < 8; ++u)
+                                s += *reinterpret_cast<const double *>(cb + off[u]);
                             acc += it0 + g < npos ? s : -s;
                         }
                     }
