@@ -21,8 +21,11 @@
 //     net nu of QSS species j is not zero: the forward term goes to the column
 //     of the reaction's QSS reactant (to b if it has none), the reverse term to
 //     that of its QSS product;
-//  4. elimination without row exchanges (thread = row, one pivot per barrier),
-//     then back substitution (one unknown per barrier).  Every column of A is
+//  4. elimination without row exchanges.  Up to 7 QSS species, [A | b] sits
+//     in registers, one entry per lane (phase 3 sums each entry there), and
+//     Gauss-Jordan steps read the pivot row and column by shuffles; beyond
+//     that, rows in LDS (thread = row, one pivot per barrier) and back
+//     substitution (one unknown per barrier).  Every column of A is
 //     weakly diagonally dominant: a reaction that consumes a QSS molecule turns
 //     it into at most one other QSS molecule, so the off-diagonal entries of a
 //     column add up to at most its diagonal sink.  For such matrices
@@ -211,6 +214,41 @@ __global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
         }
         __syncthreads();
 
+        if (nq * ld <= kWave) {
+            // ---- phases 3-4 in registers (up to 7 QSS species): lane l holds
+            // entry (j, c) = (l / ld, l % ld) of [A | b], summed from row j's
+            // entries; then Gauss-Jordan on the diagonal with the pivot row and
+            // column read by cross-lane shuffles (no LDS, no barrier), and
+            // x_j = -b'_j / a'_jj
+            const bool act = tid < nq * ld;
+            const int j = act ? tid / ld : nq - 1, c = act ? tid - j * ld : 0;
+            double a = 0.0;
+            if (act) {
+                const int e0 = m.qrow_ptr[j], e1 = m.qrow_ptr[j + 1];
+                for (int e = e0; e < e1; e += 4) {
+                    int4 en[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        en[u] = e + u < e1 ? m.qrow_ent[e + u] : make_int4(0, 0, -1, -1);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (e + u >= e1) break;
+                        const double2 fb = rec[en[u].x];
+                        const double nu = (double)en[u].y;
+                        if ((en[u].z >= 0 ? en[u].z : nq) == c) a = fma(nu, fb.x, a);
+                        if ((en[u].w >= 0 ? en[u].w : nq) == c) a = fma(-nu, fb.y, a);
+                    }
+                }
+            }
+            for (int k = 0; k < nq; ++k) {
+                const double akk = __shfl(a, k * ld + k, kWave);
+                const double ajk = __shfl(a, j * ld + k, kWave);
+                const double akc = __shfl(a, k * ld + c, kWave);
+                if (act && j != k && c > k) a = fma(-(ajk / akk), akc, a);
+            }
+            const double ajj = __shfl(a, j * ld + j, kWave);
+            if (act && c == nq) x[j] = -a / ajj;
+        } else {
         // ---- phase 3: row j of [A | b]
         if (tid < nq) {
             double *row = Am + tid * ld;
@@ -249,6 +287,7 @@ __global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
             if (tid == k) x[k] = x[k] / Am[k * ld + k];
             __syncthreads();
             if (tid < k) x[tid] = fma(-Am[tid * ld + k], x[k], x[tid]);
+        }
         }
         __syncthreads();
         if (Cq && tid < nq) Cq[(int64_t)tid * n + i] = x[tid];

@@ -112,6 +112,19 @@ def test_qss_chain(kx, qss):
     dm.close()
 
 
+def test_qss_nine_species_lds_path(kx):
+    """Nine coupled QSS species (9 x 10 entries of [A | b] exceed one wave, so
+    the system is solved in LDS rather than in registers), 517 points."""
+    mech = TM.qss_long_chain(9)
+    T, p, Y = I.make_states(12, I.StateSpec(517, seed=88, p_atm_range=(0.2, 40.0),
+                                            dirichlet_alpha=1.0))
+    _say("qss long chain nq = 9, n =", T.size)
+    dm = kx.Mechanism(mech, 0)
+    w, Cq = run_qss(kx, dm, T, p, Y)
+    compare(mech, w, Cq, T, p, Y, "long chain")
+    dm.close()
+
+
 def test_qss_syn53q_block(kx, mech53q):
     """53 species with 6 QSS species, 4133 points (every point judged)."""
     T, p, Y = I.make_states(53, I.StateSpec(4133, seed=82, p_atm_range=(1.0, 40.0),

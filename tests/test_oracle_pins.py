@@ -739,3 +739,17 @@ def test_qss_entries_of_Y_are_not_read(mech53q):
     b = om.qss_rates(T, p, Y2)
     for x, y in zip(a, b):
         np.testing.assert_array_equal(x, y)
+
+
+def test_qss_long_chain_balances():
+    """Nine coupled QSS species: every balance vanishes and mass is conserved."""
+    m = TM.qss_long_chain(9)
+    om = O.OracleMech(m)
+    T, p, Y = I.make_states(12, I.StateSpec(200, seed=37, p_atm_range=(0.2, 40.0),
+                                            dirichlet_alpha=1.0))
+    w, s, Cq = om.qss_rates(T, p, Y)
+    q = np.flatnonzero(m["qss"])
+    assert Cq.shape == (9, 200) and (Cq > 0).all()
+    assert (np.abs(w[q]) <= 1e-13 * s[q]).all()
+    W = m["composition"] @ m["elem_mass"]
+    assert (np.abs((W[:, None] * w).sum(0)) <= 1e-13 * (W[:, None] * s).sum(0)).all()

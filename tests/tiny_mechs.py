@@ -185,3 +185,34 @@ def qss_chain_mechanism(qss=(Q1_, Q2_)):
     flags[list(qss)] = 1
     m["qss"] = flags
     return m
+
+
+def qss_long_chain(nq=9):
+    """A <=> Q1 <=> ... <=> Q_nq -> B (isomers), every Q_i also drained to B
+    through the bath D, and one three-body sink; Q_1..Q_nq are quasi-steady.
+    nq (nq + 1) > 64 for nq >= 8."""
+    ns = nq + 3                       # A, Q1..Qnq, B, D
+    a, b, d = 0, nq + 1, nq + 2
+    comp = [(1, 1, 0)] * (nq + 2) + [(0, 0, 2)]
+    base = np.array([3.3, 1.0e-3, -2.5e-7, 3.0e-11, -1.5e-15, 0.0, 4.0])
+    nasa = []
+    for k in range(ns):
+        row = base.copy()
+        row[5] = 4.5e3 + 900.0 * ((k * 7) % 11) if k != d else -1.0e3
+        row[6] = 4.0 + 0.1 * k
+        nasa.append(row.tolist())
+    rx = [dict(type=0, reac=[(a, 1)], prod=[(1, 1)], A=1e10, beta=0.2, Ea=5.0e3)]
+    for i in range(1, nq):
+        rx.append(dict(type=0, reac=[(i, 1)], prod=[(i + 1, 1)], A=3e11 * (1 + i % 3),
+                       beta=0.1 * (i % 2), Ea=2.0e3 + 300.0 * i))
+    rx.append(dict(type=0, reac=[(nq, 1)], prod=[(b, 1)], A=5e9, beta=0.5, Ea=1.0e3, rev=0))
+    for i in range(1, nq + 1):
+        rx.append(dict(type=0, reac=[(i, 1), (d, 1)], prod=[(b, 1), (d, 1)],
+                       A=2e12 * (1 + i % 4), beta=0.0, Ea=4.0e3 + 100.0 * i, rev=0))
+    rx.append(dict(type=1, reac=[(2, 1)], prod=[(b, 1)], A=4e15, beta=-0.5, Ea=0.0, rev=0,
+                   eff={d: 2.0}))
+    m = build(comp, nasa, rx)
+    flags = np.zeros(ns, np.int32)
+    flags[1:nq + 1] = 1
+    m["qss"] = flags
+    return m
