@@ -147,7 +147,7 @@ struct MechDev {
     const float *gfrag32, *c1frag32;
     // Quasi-steady-state species (nq = 0 when there are none).  QSS index j
     // numbers them in species order.
-    int32_t nq;
+    int32_t nq, nqent;         // QSS species, entries of their balance rows
     const int32_t *qidx;       // [ns] QSS index of species k, -1 if transported
     const int32_t *qrow_ptr;   // [nq + 1] entries of the balance of QSS species j
     const int4 *qrow_ent;      // {LDS slot of the reaction (kernel order s, at s + s /

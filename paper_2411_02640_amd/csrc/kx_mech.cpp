@@ -679,6 +679,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     v.gfrag32 = mfma ? (const float *)at(o_gf32) : nullptr;
     v.c1frag32 = mfma ? (const float *)at(o_c1f32) : nullptr;
     v.nq = nq;
+    v.nqent = nq > 0 ? qrow_ptr[nq] : 0;
     v.qidx = (const int32_t *)at(o_qidx);
     v.qrx = (const int2 *)at(o_qrx);
     v.qrow_ptr = (const int32_t *)at(o_qptr);

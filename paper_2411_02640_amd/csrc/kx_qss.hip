@@ -82,6 +82,7 @@ size_t qss_lds_bytes(const MechDev &m)
     return sizeof(QPair) * (ns + 1)              // {a, C} per species (+dummy)
            + 2 * sizeof(double) * (size_t)m.nchunks * (m.chunk + 1)  // {F', B'}, then R,
                                                    // per chunk: chunk slots and a zero slot
+           + sizeof(int4) * (size_t)m.nqent        // the balance rows' entries
            + sizeof(double) * (nq * (nq + 1) + nq + 4);     // [A | b], x, W-bar partials
 }
 
@@ -101,10 +102,14 @@ __global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
     // chunk c owns rec[c (chunk + 1) ...]: its reactions (reaction r of the chunk
     // at base + c + r), then at offset chunk the zero slot that the padding
     // entries of the gather lists address (also for a partial last chunk)
-    double *Am = reinterpret_cast<double *>(rec + m.nchunks * (m.chunk + 1));
+    int4 *qe = reinterpret_cast<int4 *>(rec + m.nchunks * (m.chunk + 1));
+    double *Am = reinterpret_cast<double *>(qe + m.nqent);
     double *x = Am + nq * ld;
     double *red = x + nq;
     const int gw = kWave * m.gpass;
+    // the entries of the balance rows are the same at every point: staged once
+    for (int e = tid; e < m.nqent; e += NT) qe[e] = m.qrow_ent[e];
+    __syncthreads();
 
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
         const double Ti = T[i], pi = P[i];
@@ -229,7 +234,7 @@ __global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
                     int4 en[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
-                        en[u] = e + u < e1 ? m.qrow_ent[e + u] : make_int4(0, 0, -1, -1);
+                        en[u] = e + u < e1 ? qe[e + u] : make_int4(0, 0, -1, -1);
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         if (e + u >= e1) break;
@@ -259,7 +264,7 @@ __global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
                 int4 en[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    en[u] = e + u < e1 ? m.qrow_ent[e + u] : make_int4(0, 0, -1, -1);
+                    en[u] = e + u < e1 ? qe[e + u] : make_int4(0, 0, -1, -1);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     if (e + u >= e1) break;
