@@ -362,7 +362,7 @@ def main():
     ap.add_argument("--serve-staged-pool", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: kx has no multi-GPU path "
               "(points shard trivially across GPUs)", file=sys.stderr)
         sys.exit(2)
 

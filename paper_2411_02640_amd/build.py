@@ -1,7 +1,7 @@
 """Compile the gfx950 library ``libkx.so`` in-tree with hipcc.
 
-Usage: ``python -m paper_2411_02640_amd.build`` (also called by the graft
-entry's ``build()``).  Every translation unit is compiled for gfx950 only,
+Usage: ``python -m paper_2411_02640_amd.build`` (also called by
+``__graft_entry__.build()`` at the repository root).  Every translation unit is compiled for gfx950 only,
 with packed-FP32 instruction selection disabled, then linked into one shared
 library next to this file.
 """
