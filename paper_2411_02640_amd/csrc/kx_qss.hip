@@ -76,6 +76,167 @@ __device__ __forceinline__ double qblend(const DevAux &ax, bool sri, double T, d
     return kexp(fma(lnB, krcp(fma(w, w, 1.0)), sri ? fma(a4, lnT, a3) : 0.0));
 }
 
+// Per-point scalars of phase 2: T, ln T, 1/T, [M] = p/(R_u T), ln p.
+struct PointConst {
+    double T, lnT, invT, Mc, lnp;
+};
+
+// Phase 2 for one reaction at one point: {F', B'} = c_i {k_f prod C', k_r prod
+// C''} with the QSS slots counting 1 (k_f by eq:arrhenius or the pressure
+// table, k_r = k_f prod a' / prod a'' by eq:K_p, c_i by eq:c_i and eq:blend).
+__device__ __forceinline__ double2 reaction_terms(const MechDev &m, const DevRxn &R,
+                                                  const QPair *sp, const PointConst &pc)
+{
+    const double Ti = pc.T, lnT = pc.lnT, invT = pc.invT, Mc = pc.Mc, lnp = pc.lnp;
+    const unsigned type = R.type, flags = R.flags;
+    const bool kconst = (flags & kFlagKfConst) != 0;
+    double xf = kconst ? R.lnA : fma(R.beta, lnT, fma(-R.ER, invT, R.lnA));
+    if (type == KX_RXN_PLOG) {
+        const DevAux &ax = m.aux[R.aux];
+        const DevPlog *pl = m.plog + ax.plog_off;
+        const int cntp = ax.plog_cnt;
+        int j = 0;
+        while (j + 1 < cntp && pl[j + 1].lnp <= lnp) ++j;
+        xf = fma(pl[j].beta, lnT, fma(-pl[j].ER, invT, pl[j].lnA));
+        if (j + 1 < cntp && lnp > pl[j].lnp) {
+            const double x2 =
+                fma(pl[j + 1].beta, lnT, fma(-pl[j + 1].ER, invT, pl[j + 1].lnA));
+            xf = fma((x2 - xf) * pl[j].inv_dlnp, lnp - pl[j].lnp, xf);
+        }
+    }
+    const double kf = kconst ? R.A : kexp(xf);
+    const QPair r0 = sp[R.roff[0] / 16], r1 = sp[R.roff[1] / 16], r2 = sp[R.roff[2] / 16];
+    const QPair p0 = sp[R.poff[0] / 16], p1 = sp[R.poff[1] / 16], p2 = sp[R.poff[2] / 16];
+    const bool rev = (flags & kFlagReversible) != 0;
+    const double kr = rev ? kf * (r0.a * r1.a * r2.a) * krcp(p0.a * p1.a * p2.a) : 0.0;
+    double F = kf * r0.C * r1.C * r2.C;
+    const double B = kr * p0.C * p1.C * p2.C;
+    if (flags & kFlagOrders) {  // no QSS species takes part (checked at create)
+        const DevAux &ax = m.aux[R.aux];
+        double S = 0.0;
+        bool zero = false;
+#pragma unroll
+        for (int e = 0; e < kMaxOrd; ++e) {
+            const double o = ax.oval[e], Ce = sp[ax.ooff[e] / 16].C;
+            if (o != 0.0) {
+                zero |= !(Ce > 0.0);
+                S = fma(o, Ce > 0.0 ? kln(Ce) : 0.0, S);
+            }
+        }
+        F = zero ? 0.0 : kf * kexp(S);
+    }
+    double cmod = 1.0;
+    if (type != KX_RXN_ELEMENTARY && type != KX_RXN_PLOG) {
+        const DevAux &ax = m.aux[R.aux];
+        double X = ax.eff_default * Mc;
+        for (int e = 0; e < kInlineEff; ++e) X = fma(ax.dalpha[e], sp[ax.eoff[e] / 16].C, X);
+        for (int e = 0; e < ax.ext_cnt; ++e) {
+            const DevEff f = m.eff[ax.ext_off + e];
+            X = fma(f.dalpha, sp[f.sp].C, X);
+        }
+        if (type == KX_RXN_THREEBODY) {
+            cmod = X;
+        } else {
+            const double d0 = fma(ax.beta0, lnT, fma(-ax.ER0, invT, ax.lnA0)) - xf;
+            const double e0 = kexp(d0);
+            const double Pr = e0 * X;
+            double Fb = 1.0;
+            if (type == KX_RXN_TROE || type == KX_RXN_SRI)
+                Fb = qblend(ax, type == KX_RXN_SRI, Ti, lnT, invT,
+                            fmax(d0 + kln(fmax(X, DBL_MIN)), -708.39641853226410622));
+            const double h = krcp(1.0 + Pr);
+            cmod = (flags & kFlagChemAct) ? e0 * Fb * h : Pr * Fb * h;
+        }
+    }
+    return make_double2(cmod * F, cmod * B);
+}
+
+// Phases 3-4 with [A | b] in registers (nq (nq + 1) <= 64): lane l holds entry
+// (j, c) = (l / (nq + 1), l % (nq + 1)), summed from row j's entries qe; then
+// Gauss-Jordan steps on the diagonal read the pivot row and column by
+// cross-lane shuffles (no LDS, no barrier), and x_j = -b'_j / a'_jj.
+__device__ __forceinline__ void solve_in_registers(const MechDev &m, const int4 *qe,
+                                                   const double2 *rec, double *x, int tid)
+{
+    const int nq = m.nq, ld = nq + 1;
+    const bool act = tid < nq * ld;
+    const int j = act ? tid / ld : nq - 1, c = act ? tid - j * ld : 0;
+    double a = 0.0;
+    if (act) {
+        const int e0 = m.qrow_ptr[j], e1 = m.qrow_ptr[j + 1];
+        for (int e = e0; e < e1; e += 4) {
+            int4 en[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                en[u] = e + u < e1 ? qe[e + u] : make_int4(0, 0, -1, -1);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (e + u >= e1) break;
+                const double2 fb = rec[en[u].x];
+                const double nu = (double)en[u].y;
+                if ((en[u].z >= 0 ? en[u].z : nq) == c) a = fma(nu, fb.x, a);
+                if ((en[u].w >= 0 ? en[u].w : nq) == c) a = fma(-nu, fb.y, a);
+            }
+        }
+    }
+    for (int k = 0; k < nq; ++k) {
+        const double akk = __shfl(a, k * ld + k, kWave);
+        const double ajk = __shfl(a, j * ld + k, kWave);
+        const double akc = __shfl(a, k * ld + c, kWave);
+        if (act && j != k && c > k) a = fma(-(ajk / akk), akc, a);
+    }
+    const double ajj = __shfl(a, j * ld + j, kWave);
+    if (act && c == nq) x[j] = -a / ajj;
+}
+
+// Phases 3-4 with the rows of [A | b] in LDS (thread = row): assembly, then
+// elimination (one pivot per barrier) and back substitution (one unknown per
+// barrier).
+__device__ __forceinline__ void solve_in_lds(const MechDev &m, const int4 *qe,
+                                             const double2 *rec, double *Am, double *x, int tid)
+{
+    const int nq = m.nq, ld = nq + 1;
+    // ---- phase 3: row j of [A | b]
+    if (tid < nq) {
+        double *row = Am + tid * ld;
+        for (int c = 0; c <= nq; ++c) row[c] = 0.0;
+        // entries four at a time, their loads issued together
+        const int e0 = m.qrow_ptr[tid], e1 = m.qrow_ptr[tid + 1];
+        for (int e = e0; e < e1; e += 4) {
+            int4 en[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                en[u] = e + u < e1 ? qe[e + u] : make_int4(0, 0, -1, -1);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (e + u >= e1) break;
+                const double2 fb = rec[en[u].x];
+                const double nu = (double)en[u].y;
+                row[en[u].z >= 0 ? en[u].z : nq] += nu * fb.x;
+                row[en[u].w >= 0 ? en[u].w : nq] -= nu * fb.y;
+            }
+        }
+        x[tid] = -row[nq];
+    }
+    // ---- phase 4: elimination, then back substitution
+    for (int k = 0; k < nq; ++k) {
+        __syncthreads();
+        if (tid > k && tid < nq) {
+            double *row = Am + tid * ld;
+            const double *pr = Am + k * ld;
+            const double f = row[k] / pr[k];
+            for (int c = k + 1; c < nq; ++c) row[c] = fma(-f, pr[c], row[c]);
+            x[tid] = fma(-f, x[k], x[tid]);
+        }
+    }
+    for (int k = nq - 1; k >= 0; --k) {
+        __syncthreads();
+        if (tid == k) x[k] = x[k] / Am[k * ld + k];
+        __syncthreads();
+        if (tid < k) x[tid] = fma(-Am[tid * ld + k], x[k], x[tid]);
+    }
+}
+
 size_t qss_lds_bytes(const MechDev &m)
 {
     const size_t ns = (size_t)m.ns, nr = (size_t)m.nr, nq = (size_t)m.nq;
@@ -146,154 +307,21 @@ __global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
         }
         __syncthreads();
 
-        // ---- phase 2: one reaction per thread
+        // ---- phase 2: one reaction per thread, chunk by chunk
+        const PointConst pc{Ti, lnT, invT, Mc, lnp};
         for (int c = 0; c < m.nchunks; ++c) {
-          const int base = c * m.chunk, cnt = min(m.chunk, nr - base);
-          double2 *rc = rec + base + c;
-          if (tid == 0) rc[m.chunk] = make_double2(0.0, 0.0);
-          for (int rr = tid; rr < cnt; rr += NT) {
-            const int r = base + rr;
-            const DevRxn &R = m.rxn[r];
-            const unsigned type = R.type, flags = R.flags;
-            const bool kconst = (flags & kFlagKfConst) != 0;
-            double xf = kconst ? R.lnA : fma(R.beta, lnT, fma(-R.ER, invT, R.lnA));
-            if (type == KX_RXN_PLOG) {
-                const DevAux &ax = m.aux[R.aux];
-                const DevPlog *pl = m.plog + ax.plog_off;
-                const int cntp = ax.plog_cnt;
-                int j = 0;
-                while (j + 1 < cntp && pl[j + 1].lnp <= lnp) ++j;
-                xf = fma(pl[j].beta, lnT, fma(-pl[j].ER, invT, pl[j].lnA));
-                if (j + 1 < cntp && lnp > pl[j].lnp) {
-                    const double x2 =
-                        fma(pl[j + 1].beta, lnT, fma(-pl[j + 1].ER, invT, pl[j + 1].lnA));
-                    xf = fma((x2 - xf) * pl[j].inv_dlnp, lnp - pl[j].lnp, xf);
-                }
-            }
-            const double kf = kconst ? R.A : kexp(xf);
-            const QPair r0 = sp[R.roff[0] / 16], r1 = sp[R.roff[1] / 16], r2 = sp[R.roff[2] / 16];
-            const QPair p0 = sp[R.poff[0] / 16], p1 = sp[R.poff[1] / 16], p2 = sp[R.poff[2] / 16];
-            const bool rev = (flags & kFlagReversible) != 0;
-            const double kr = rev ? kf * (r0.a * r1.a * r2.a) * krcp(p0.a * p1.a * p2.a) : 0.0;
-            double F = kf * r0.C * r1.C * r2.C;
-            const double B = kr * p0.C * p1.C * p2.C;
-            if (flags & kFlagOrders) {  // no QSS species takes part (checked at create)
-                const DevAux &ax = m.aux[R.aux];
-                double S = 0.0;
-                bool zero = false;
-#pragma unroll
-                for (int e = 0; e < kMaxOrd; ++e) {
-                    const double o = ax.oval[e], Ce = sp[ax.ooff[e] / 16].C;
-                    if (o != 0.0) {
-                        zero |= !(Ce > 0.0);
-                        S = fma(o, Ce > 0.0 ? kln(Ce) : 0.0, S);
-                    }
-                }
-                F = zero ? 0.0 : kf * kexp(S);
-            }
-            double cmod = 1.0;
-            if (type != KX_RXN_ELEMENTARY && type != KX_RXN_PLOG) {
-                const DevAux &ax = m.aux[R.aux];
-                double X = ax.eff_default * Mc;
-                for (int e = 0; e < kInlineEff; ++e) X = fma(ax.dalpha[e], sp[ax.eoff[e] / 16].C, X);
-                for (int e = 0; e < ax.ext_cnt; ++e) {
-                    const DevEff f = m.eff[ax.ext_off + e];
-                    X = fma(f.dalpha, sp[f.sp].C, X);
-                }
-                if (type == KX_RXN_THREEBODY) {
-                    cmod = X;
-                } else {
-                    const double d0 = fma(ax.beta0, lnT, fma(-ax.ER0, invT, ax.lnA0)) - xf;
-                    const double e0 = kexp(d0);
-                    const double Pr = e0 * X;
-                    double Fb = 1.0;
-                    if (type == KX_RXN_TROE || type == KX_RXN_SRI)
-                        Fb = qblend(ax, type == KX_RXN_SRI, Ti, lnT, invT,
-                                    fmax(d0 + kln(fmax(X, DBL_MIN)), -708.39641853226410622));
-                    const double h = krcp(1.0 + Pr);
-                    cmod = (flags & kFlagChemAct) ? e0 * Fb * h : Pr * Fb * h;
-                }
-            }
-            rc[rr] = make_double2(cmod * F, cmod * B);
-          }
+            const int base = c * m.chunk, cnt = min(m.chunk, nr - base);
+            double2 *rc = rec + base + c;
+            if (tid == 0) rc[m.chunk] = make_double2(0.0, 0.0);
+            for (int rr = tid; rr < cnt; rr += NT) rc[rr] = reaction_terms(m, m.rxn[base + rr], sp, pc);
         }
         __syncthreads();
 
-        if (nq * ld <= kWave) {
-            // ---- phases 3-4 in registers (up to 7 QSS species): lane l holds
-            // entry (j, c) = (l / ld, l % ld) of [A | b], summed from row j's
-            // entries; then Gauss-Jordan on the diagonal with the pivot row and
-            // column read by cross-lane shuffles (no LDS, no barrier), and
-            // x_j = -b'_j / a'_jj
-            const bool act = tid < nq * ld;
-            const int j = act ? tid / ld : nq - 1, c = act ? tid - j * ld : 0;
-            double a = 0.0;
-            if (act) {
-                const int e0 = m.qrow_ptr[j], e1 = m.qrow_ptr[j + 1];
-                for (int e = e0; e < e1; e += 4) {
-                    int4 en[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        en[u] = e + u < e1 ? qe[e + u] : make_int4(0, 0, -1, -1);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (e + u >= e1) break;
-                        const double2 fb = rec[en[u].x];
-                        const double nu = (double)en[u].y;
-                        if ((en[u].z >= 0 ? en[u].z : nq) == c) a = fma(nu, fb.x, a);
-                        if ((en[u].w >= 0 ? en[u].w : nq) == c) a = fma(-nu, fb.y, a);
-                    }
-                }
-            }
-            for (int k = 0; k < nq; ++k) {
-                const double akk = __shfl(a, k * ld + k, kWave);
-                const double ajk = __shfl(a, j * ld + k, kWave);
-                const double akc = __shfl(a, k * ld + c, kWave);
-                if (act && j != k && c > k) a = fma(-(ajk / akk), akc, a);
-            }
-            const double ajj = __shfl(a, j * ld + j, kWave);
-            if (act && c == nq) x[j] = -a / ajj;
-        } else {
-        // ---- phase 3: row j of [A | b]
-        if (tid < nq) {
-            double *row = Am + tid * ld;
-            for (int c = 0; c <= nq; ++c) row[c] = 0.0;
-            // entries four at a time, their loads issued together
-            const int e0 = m.qrow_ptr[tid], e1 = m.qrow_ptr[tid + 1];
-            for (int e = e0; e < e1; e += 4) {
-                int4 en[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    en[u] = e + u < e1 ? qe[e + u] : make_int4(0, 0, -1, -1);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (e + u >= e1) break;
-                    const double2 fb = rec[en[u].x];
-                    const double nu = (double)en[u].y;
-                    row[en[u].z >= 0 ? en[u].z : nq] += nu * fb.x;
-                    row[en[u].w >= 0 ? en[u].w : nq] -= nu * fb.y;
-                }
-            }
-            x[tid] = -row[nq];
-        }
-        // ---- phase 4: elimination, then back substitution
-        for (int k = 0; k < nq; ++k) {
-            __syncthreads();
-            if (tid > k && tid < nq) {
-                double *row = Am + tid * ld;
-                const double *pr = Am + k * ld;
-                const double f = row[k] / pr[k];
-                for (int c = k + 1; c < nq; ++c) row[c] = fma(-f, pr[c], row[c]);
-                x[tid] = fma(-f, x[k], x[tid]);
-            }
-        }
-        for (int k = nq - 1; k >= 0; --k) {
-            __syncthreads();
-            if (tid == k) x[k] = x[k] / Am[k * ld + k];
-            __syncthreads();
-            if (tid < k) x[tid] = fma(-Am[tid * ld + k], x[k], x[tid]);
-        }
-        }
+        // ---- phases 3-4: the QSS balances, then their solution x = C_Q
+        if (nq * ld <= kWave)
+            solve_in_registers(m, qe, rec, x, tid);
+        else
+            solve_in_lds(m, qe, rec, Am, x, tid);
         __syncthreads();
         if (Cq && tid < nq) Cq[(int64_t)tid * n + i] = x[tid];
 
