@@ -168,9 +168,11 @@ def _parse_equation(eq: str):
     return reac, prod, rev, (colliders[0] if colliders else None), (t1 or t2)
 
 
-def load(src, T_fit=(I.T_FIT_LO, I.T_FIT_HI)) -> dict:
+def load(src, T_fit=(I.T_FIT_LO, I.T_FIT_HI), qss_species=None) -> dict:
     """Mechanism dictionary (kx_mech_desc fields) from a Cantera YAML file path
-    or YAML text.  The transport fits cover T_fit (K)."""
+    or YAML text.  The transport fits cover T_fit (K).  Cantera's format has no
+    notion of quasi-steady species: `qss_species` (names) sets the descriptor's
+    qss flags (kx_mech_create checks that they form a linear QSS system)."""
     if (T_fit[0], T_fit[1]) != (I.T_FIT_LO, I.T_FIT_HI):
         raise ValueError("only the default fit range is supported")
     text = src
@@ -364,6 +366,14 @@ def load(src, T_fit=(I.T_FIT_LO, I.T_FIT_HI)) -> dict:
             cp_r[k, g] = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])))
     visc_fit, cond_fit, diff_fit = I.transport_fits(W, sigma, eps, zrot, natoms, cp_r, 1)
 
+    qss = None
+    if qss_species:
+        qss = np.zeros(ns, np.int32)
+        for nm in qss_species:
+            if nm not in index:
+                raise ValueError(f"unknown QSS species {nm!r}")
+            qss[index[nm]] = 1
+
     ord_ptr = np.searchsorted([o[0] for o in ords], np.arange(nr + 1)).astype(np.int32)
     ord_sp = np.array([o[1] for o in ords], np.int32)
     ord_val = np.array([o[2] for o in ords], np.float64)
@@ -392,6 +402,7 @@ def load(src, T_fit=(I.T_FIT_LO, I.T_FIT_HI)) -> dict:
         "ord_ptr": ord_ptr if ords else None,
         "ord_sp": ord_sp if ords else None,
         "ord_val": ord_val if ords else None,
+        "qss": qss,
         "_species_names": names, "_elements": elements, "_warnings": warnings,
     }
 

@@ -123,3 +123,15 @@ def test_rejected_inputs(old, new, words):
     assert old in text
     with pytest.raises(ValueError, match=words):
         MY.load(text.replace(old, new, 1))
+
+
+def test_qss_species_by_name():
+    """Species named as quasi-steady become the descriptor's qss flags; an
+    unknown name is refused."""
+    plain = MY.load(FIXTURE)
+    assert plain["qss"] is None
+    names = plain["_species_names"]
+    m = MY.load(FIXTURE, qss_species=[names[1], names[3]])
+    assert m["qss"].tolist() == [1 if k in (1, 3) else 0 for k in range(len(names))]
+    with pytest.raises(ValueError, match="unknown QSS species"):
+        MY.load(FIXTURE, qss_species=["no-such-species"])
