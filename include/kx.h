@@ -148,7 +148,9 @@ typedef struct {
      * of every reaction (so the balances are linear in the QSS
      * concentrations); no QSS species in an efficiency list or in a reaction
      * with explicit orders; every QSS species consumed by some reaction (a
-     * reactant, or a product of a reversible reaction, with non-zero net nu). */
+     * reactant, or a product of a reversible reaction, with non-zero net nu).
+     * The flags change kx_production_rates only: kx_transport and kx_thermo
+     * treat QSS species like the others, with their Y entries as given. */
     const int32_t *qss;           /* [Ns] 0 or 1 */
 } kx_mech_desc;
 
