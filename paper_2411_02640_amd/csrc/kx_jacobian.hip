@@ -41,7 +41,9 @@ namespace kx {
 namespace {
 
 constexpr int kJacMaxSpecies = 128;
-constexpr int kRec = 9;  // doubles per reaction record of phase 2 (the last packs indices)
+// doubles per reaction record of phase 2: the partials, then a word packing the
+// slots' species, type and flags, then the index of the reaction's DevAux
+constexpr int kRec = 10;
 
 struct JPair {
     double a, C;
@@ -259,6 +261,7 @@ __global__ __launch_bounds__(NT) void jacobian_kernel(MechDev m, int64_t n,
                 }
                 double *rr = rec + kRec * r;
                 rr[8] = __longlong_as_double((long long)pk);
+                rr[9] = __longlong_as_double((long long)R.aux);
                 rr[0] = cmod * Pd[0];
                 rr[1] = cmod * Pd[1];
                 rr[2] = cmod * Pd[2];
@@ -275,40 +278,54 @@ __global__ __launch_bounds__(NT) void jacobian_kernel(MechDev m, int64_t n,
                 const uint4 *ge = m.gent + ((size_t)m.goff[c] * gw + k) * 2;
                 double *Jk = J + k * ns;
                 double rc = 0.0;
-                for (int it = 0; it < ngrp; ++it) {
-                    const uint4 v0 = ge[(size_t)it * 2 * gw], v1 = ge[(size_t)it * 2 * gw + 1];
-                    const unsigned off[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-                    const double sg = it < npos ? 1.0 : -1.0;
-                    for (int u = 0; u < 8; ++u) {
-                        const int r = (int)(off[u] / 16);
-                        if (r >= cnt) continue;  // padding entry
-                        const double *rr = rec + kRec * r;
-                        const uint64_t pk = (uint64_t)__double_as_longlong(rr[8]);
-                        const unsigned flags = (unsigned)(pk >> 56), type = (unsigned)(pk >> 48) & 0xFFu;
-                        if (flags & kFlagOrders) {
-                            for (int e = 0; e < kMaxOrd; ++e) {
-                                const int jo = (int)((pk >> (8 * e)) & 0xFFu);
-                                if (jo < ns) Jk[jo] += sg * rr[e];
+                // four groups per trip, their list loads issued together
+                for (int it0 = 0; it0 < ngrp; it0 += 4) {
+                    uint4 v[8];
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const size_t at = (size_t)(it0 + g < ngrp ? it0 + g : it0) * 2 * gw;
+                        v[2 * g] = ge[at];
+                        v[2 * g + 1] = ge[at + 1];
+                    }
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const int it = it0 + g;
+                        if (it >= ngrp) break;
+                        const unsigned off[8] = {v[2 * g].x,     v[2 * g].y,     v[2 * g].z,
+                                                 v[2 * g].w,     v[2 * g + 1].x, v[2 * g + 1].y,
+                                                 v[2 * g + 1].z, v[2 * g + 1].w};
+                        const double sg = it < npos ? 1.0 : -1.0;
+                        for (int u = 0; u < 8; ++u) {
+                            const int r = (int)(off[u] / 16);
+                            if (r >= cnt) continue;  // padding entry
+                            const double *rr = rec + kRec * r;
+                            const uint64_t pk = (uint64_t)__double_as_longlong(rr[8]);
+                            const unsigned flags = (unsigned)(pk >> 56), type = (unsigned)(pk >> 48) & 0xFFu;
+                            if (flags & kFlagOrders) {
+                                for (int e = 0; e < kMaxOrd; ++e) {
+                                    const int jo = (int)((pk >> (8 * e)) & 0xFFu);
+                                    if (jo < ns) Jk[jo] += sg * rr[e];
+                                }
+                            } else {
+                                for (int q = 0; q < kMaxSide; ++q) {
+                                    const int jr = (int)((pk >> (8 * q)) & 0xFFu);
+                                    const int jp = (int)((pk >> (8 * (q + 3))) & 0xFFu);
+                                    if (jr < ns) Jk[jr] += sg * rr[q];
+                                    if (jp < ns) Jk[jp] -= sg * rr[3 + q];
+                                }
                             }
-                        } else {
-                            for (int q = 0; q < kMaxSide; ++q) {
-                                const int jr = (int)((pk >> (8 * q)) & 0xFFu);
-                                const int jp = (int)((pk >> (8 * (q + 3))) & 0xFFu);
-                                if (jr < ns) Jk[jr] += sg * rr[q];
-                                if (jp < ns) Jk[jp] -= sg * rr[3 + q];
+                            if (type != KX_RXN_ELEMENTARY && type != KX_RXN_PLOG) {
+                                const DevAux &ax = m.aux[(int)__double_as_longlong(rr[9])];
+                                const double D = sg * rr[6];
+                                for (int e = 0; e < kInlineEff; ++e)
+                                    if (ax.dalpha[e] != 0.0) Jk[ax.eoff[e] / 16] += D * ax.dalpha[e];
+                                for (int e = 0; e < ax.ext_cnt; ++e) {
+                                    const DevEff f = m.eff[ax.ext_off + e];
+                                    Jk[f.sp] += D * f.dalpha;
+                                }
                             }
+                            rc += sg * rr[7];
                         }
-                        if (type != KX_RXN_ELEMENTARY && type != KX_RXN_PLOG) {
-                            const DevAux &ax = m.aux[m.rxn[base + r].aux];
-                            const double D = sg * rr[6];
-                            for (int e = 0; e < kInlineEff; ++e)
-                                if (ax.dalpha[e] != 0.0) Jk[ax.eoff[e] / 16] += D * ax.dalpha[e];
-                            for (int e = 0; e < ax.ext_cnt; ++e) {
-                                const DevEff f = m.eff[ax.ext_off + e];
-                                Jk[f.sp] += D * f.dalpha;
-                            }
-                        }
-                        rc += sg * rr[7];
                     }
                 }
                 rowc[k] += rc;
