@@ -244,11 +244,11 @@ size_t qss_lds_bytes(const MechDev &m)
            + 2 * sizeof(double) * (size_t)m.nchunks * (m.chunk + 1)  // {F', B'}, then R,
                                                    // per chunk: chunk slots and a zero slot
            + sizeof(int4) * (size_t)m.nqent        // the balance rows' entries
-           + sizeof(double) * (nq * (nq + 1) + nq + 4);     // [A | b], x, W-bar partials
+           + sizeof(double) * (nq * (nq + 1) + nq);         // [A | b], x
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
+// One wave (kWave threads) per point; see launch_qss.
+__global__ __launch_bounds__(kWave) void qss_kernel(MechDev m, int64_t n,
                                                   const double *__restrict__ T,
                                                   const double *__restrict__ P,
                                                   const double *__restrict__ Y,
@@ -256,6 +256,7 @@ __global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
                                                   double *__restrict__ Cq)
 {
     extern __shared__ double lds[];
+    constexpr int NT = kWave;
     const int ns = m.ns, nr = m.nr, nq = m.nq, tid = threadIdx.x;
     const int ld = nq + 1;  // row stride of [A | b]
     QPair *sp = reinterpret_cast<QPair *>(lds);
@@ -266,7 +267,6 @@ __global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
     int4 *qe = reinterpret_cast<int4 *>(rec + m.nchunks * (m.chunk + 1));
     double *Am = reinterpret_cast<double *>(qe + m.nqent);
     double *x = Am + nq * ld;
-    double *red = x + nq;
     const int gw = kWave * m.gpass;
     // the entries of the balance rows are the same at every point: staged once
     for (int e = tid; e < m.nqent; e += NT) qe[e] = m.qrow_ent[e];
@@ -283,14 +283,6 @@ __global__ __launch_bounds__(NT) void qss_kernel(MechDev m, int64_t n,
             if (m.qidx[k] < 0) part = fma(Y[(int64_t)k * n + i], m.sp[k].inv_W, part);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
-        if (NT > kWave) {
-            if ((tid & (kWave - 1)) == 0) red[tid / kWave] = part;
-            __syncthreads();
-            double t = 0.0;
-            for (int w = 0; w < NT / kWave; ++w) t += red[w];
-            part = t;
-            __syncthreads();
-        }
         const double cf = Mc * krcp(part);
 
         // ---- phase 1: species
@@ -398,7 +390,7 @@ kx_status launch_qss(const kx_mech *mech, int64_t n, const double *T, const doub
     // barriers rather than arithmetic, so more points in flight per CU beat more
     // threads per point: 2.8x faster than 256-thread groups on 53 species with
     // 6 QSS species (measured), and a one-wave barrier costs next to nothing.
-    auto kern = qss_kernel<kWave>;
+    auto kern = qss_kernel;
     kx_status st = set_lds(kern, lds);
     if (st != KX_OK) return st;
     const unsigned grid = (unsigned)std::min<int64_t>(n, 32768);
