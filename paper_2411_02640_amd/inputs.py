@@ -386,6 +386,8 @@ MECH_53X = MechSpec(53, 266, 30, 0, 29, seed=53325, name="syn53x", n_sri=10, n_c
 MECH_53O = MechSpec(53, 266, 30, 0, 29, seed=53325, name="syn53o", n_orders=20)
 # syn53 with 6 quasi-steady-state species (the most the greedy choice finds)
 MECH_53Q = MechSpec(53, 266, 30, 0, 29, seed=53325, name="syn53q", n_qss=6)
+# syn200 with 12 QSS species
+MECH_200Q = MechSpec(200, 1200, 180, 30, 90, seed=2001500, name="syn200q", n_qss=12)
 # syn53x (SRI, chemically activated, PLOG) with the same 6 QSS species
 MECH_53XQ = MechSpec(53, 266, 30, 0, 29, seed=53325, name="syn53xq", n_sri=10, n_chemact=8,
                      n_plog=20, n_qss=6)

@@ -18,7 +18,7 @@ def _mech(name):
     from paper_2411_02640_amd import inputs as I
     spec = {"syn9": I.MECH_9, "syn53": I.MECH_53, "syn200": I.MECH_200,
             "syn53x": I.MECH_53X, "syn53o": I.MECH_53O, "syn53q": I.MECH_53Q,
-            "syn53xq": I.MECH_53XQ}[name]
+            "syn53xq": I.MECH_53XQ, "syn200q": I.MECH_200Q}[name]
     return I.make_mechanism(spec)
 
 
@@ -55,6 +55,11 @@ def mech53q():
 @pytest.fixture(scope="session")
 def mech53xq():
     return _mech("syn53xq")
+
+
+@pytest.fixture(scope="session")
+def mech200q():
+    return _mech("syn200q")
 
 
 @pytest.fixture(scope="session")

@@ -38,7 +38,7 @@ def test_version():
 
 
 @pytest.mark.parametrize("name", ["mech9", "mech53", "mech200", "mech53x", "mech53o",
-                                  "mech53q", "mech53xq"])
+                                  "mech53q", "mech53xq", "mech200q"])
 def test_host_create(name, request):
     mech = request.getfixturevalue(name)
     m = kx.HostMechanism(mech)

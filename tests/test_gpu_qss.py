@@ -125,6 +125,18 @@ def test_qss_nine_species_lds_path(kx):
     dm.close()
 
 
+def test_qss_syn200q(kx, mech200q):
+    """200 species with 12 QSS species: eight reaction chunks and the LDS
+    elimination (12 x 13 entries exceed one wave), 263 points."""
+    T, p, Y = I.make_states(200, I.StateSpec(263, seed=89, p_atm_range=(1.0, 40.0),
+                                             dirichlet_alpha=0.3))
+    _say("qss syn200q n =", T.size)
+    dm = kx.Mechanism(mech200q, 0)
+    w, Cq = run_qss(kx, dm, T, p, Y)
+    compare(mech200q, w, Cq, T, p, Y, "syn200q")
+    dm.close()
+
+
 def test_qss_syn53q_block(kx, mech53q):
     """53 species with 6 QSS species, 4133 points (every point judged)."""
     T, p, Y = I.make_states(53, I.StateSpec(4133, seed=82, p_atm_range=(1.0, 40.0),
