@@ -353,18 +353,43 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
     const char *qb = reinterpret_cast<const char *>(sq);
     (void)tp;
 
-    for (int e = lane; e < ns * TP; e += kWave) {
-        const int k = e / TP, c = e % TP;
-        Yt[k * ys + c] = (c < npts) ? Y[(int64_t)k * ld + i0 + c] : 0.0;
+    // the tile's Y, eight row loads per lane in flight before the first LDS
+    // store (a loop of load-wait-store would pay one memory latency per row)
+    constexpr int kLd = 8;
+    for (int e0 = lane; e0 < ns * TP; e0 += kLd * kWave) {
+        double v[kLd];
+#pragma unroll
+        for (int u = 0; u < kLd; ++u) {
+            const int e = e0 + u * kWave, k = e / TP, c = e % TP;
+            v[u] = (e < ns * TP && c < npts) ? Y[(int64_t)k * ld + i0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kLd; ++u) {
+            const int e = e0 + u * kWave;
+            if (e < ns * TP) Yt[(e / TP) * ys + e % TP] = v[u];
+        }
     }
     __syncthreads();
     {
         // sum_k Y_k / W_k = 1 / W-bar: lane = (point, species group); the
-        // group partials meet in the (still unused) rate-of-progress array
+        // group partials meet in the (still unused) rate-of-progress array.
+        // The 1/W_k of eight species are loaded before they are used.
         const int c = lane % TP, g = lane / TP;
         const int cc = min(c, npts - 1);  // padding points repeat the last one
         double part = 0.0;
-        for (int k = g; k < ns; k += NGW) part = fma(Yt[k * ys + cc], m.sp[k].inv_W, part);
+        for (int k0 = g; k0 < ns; k0 += kLd * NGW) {
+            double iw[kLd];
+#pragma unroll
+            for (int u = 0; u < kLd; ++u) {
+                const int k = k0 + u * NGW;
+                iw[u] = k < ns ? m.sp[k].inv_W : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kLd; ++u) {
+                const int k = k0 + u * NGW;
+                if (k < ns) part = fma(Yt[k * ys + cc], iw[u], part);
+            }
+        }
         sq[g * TP + c] = part;
     }
     __syncthreads();
