@@ -76,6 +76,29 @@ def test_mixture_thermo(mech9):
         assert cpk[k, 0] == pytest.approx(2.5 * O.RU / W[k], rel=1e-10)
 
 
+def test_mixture_enthalpy(mech53):
+    """App. A.1 h_k = H_k / W_k in erg/g: at 298.15 K it equals the generator's
+    H(298.15)/R target times R_u / W_k (independent data), and h_k(T2) - h_k(T1)
+    equals the integral of the returned cp_k over [T1, T2] (8-point
+    Gauss-Legendre, exact for the quartic cp within one NASA range).  Catches a
+    missing factor T or R_u, a per-mole result, or an h/cp mismatch."""
+    om = O.OracleMech(mech53)
+    ns = om.ns
+    W = mech53["composition"] @ mech53["elem_mass"]
+    Y = np.full((ns, 1), 1.0 / ns)
+    _, h298, _ = om.mixture_thermo(np.array([298.15]), Y)
+    np.testing.assert_allclose(h298[:, 0] * W / O.RU, mech53["_h298_over_r"], rtol=1e-12,
+                               atol=1e-7)
+    xg, wg = np.polynomial.legendre.leggauss(8)
+    for T1, T2 in ((350.0, 950.0), (1050.0, 2900.0)):
+        Tq = 0.5 * (T2 - T1) * xg + 0.5 * (T2 + T1)
+        cpq, _, _ = om.mixture_thermo(Tq, np.tile(Y, (1, Tq.size)))
+        integral = cpq @ wg * 0.5 * (T2 - T1)
+        _, hh, _ = om.mixture_thermo(np.array([T1, T2]), np.tile(Y, (1, 2)))
+        np.testing.assert_allclose(hh[:, 1] - hh[:, 0], integral, rtol=1e-11,
+                                   atol=1e-12 * np.abs(hh).max())
+
+
 # ----------------------------------------------------------------- kinetics (A.2)
 @pytest.mark.parametrize("name", ["mech9", "mech53", "mech53x", "mech53o"])
 def test_element_and_mass_conservation(name, request):
@@ -598,6 +621,91 @@ def test_equal_species_mixture():
         eta, _, D = om.pure_transport(T[i], p[i])
         assert mu[i] == pytest.approx(eta[0], rel=1e-14)
         assert Dm[0, i] == pytest.approx(D[0, 1], rel=1e-14)
+
+
+def _binary_mech():
+    """Two species with W = (2, 32) g/mol (element masses set so) and
+    T-independent fits: eta = (1, 4) 1e-4, lambda = (1, 4) 1e4, D_12 = 0.5 cm^2/s
+    at 1 atm.  The mass ratio 16 makes (W_2/W_1)^(1/4) = 2 and the viscosity
+    ratio 4 makes (eta_1/eta_2)^(1/2) = 1/2, so every Wilke factor is a short
+    closed form."""
+    comp = [(1, 0), (0, 1)]
+    nasa = [[2.5, 0, 0, 0, 0, 0, 4.0]] * 2
+    visc = np.array([[1e-4, 0, 0, 0, 0], [4e-4, 0, 0, 0, 0]])
+    cond = np.array([[1e4, 0, 0, 0, 0], [4e4, 0, 0, 0, 0]])
+    diff = np.tile([0.5, 0, 0, 0, 0], (2, 2, 1))
+    m = TM.build(comp, nasa, [], visc=visc, cond=cond, diff=diff)
+    m["elem_mass"] = np.array([2.0, 32.0])
+    return m
+
+
+# mole fractions of the two hand-worked mixtures and their mass fractions
+# (Y_k = X_k W_k / W-bar with W-bar = 17 and 24.5)
+_BIN_X = [(0.5, 0.5), (0.25, 0.75)]
+_BIN_Y = [(2.0 / 34.0, 32.0 / 34.0), (1.0 / 49.0, 48.0 / 49.0)]
+
+
+def test_two_species_wilke_by_hand():
+    """App. A.3 mixture viscosity for two unequal species, worked by hand.
+
+    phi_kj = 8^(-1/2) (1 + W_k/W_j)^(-1/2) (1 + (eta_k/eta_j)^(1/2) (W_j/W_k)^(1/4))^2:
+    phi_12 = 8^(-1/2) (17/16)^(-1/2) (1 + 1/2 * 2)^2 = 8/sqrt(34) and
+    phi_21 = 8^(-1/2) 17^(-1/2) (1 + 2 * 1/2)^2 = 2/sqrt(34).  With
+    mu = sum_k X_k eta_k / sum_j X_j phi_kj:
+      X = (1/2, 1/2): mu = eta_1/(1 + phi_12) + eta_2/(1 + phi_21);
+      X = (1/4, 3/4): mu = eta_1/(1 + 3 phi_12) + 3 eta_2/(3 + phi_21).
+    The transposed denominator sum_j X_j phi_jk, mass fractions in place of
+    mole fractions, and the appendix's printed (W_k/W_j)^(1/4) (phi_12 =
+    8^(-1/2)(17/16)^(-1/2)(5/4)^2) each miss these values by more than 5 %."""
+    m = _binary_mech()
+    om = O.OracleMech(m)
+    e1, e2 = 1e-4, 4e-4
+    p12, p21 = 8.0 / math.sqrt(34.0), 2.0 / math.sqrt(34.0)
+    want = [e1 / (1 + p12) + e2 / (1 + p21), e1 / (1 + 3 * p12) + 3 * e2 / (3 + p21)]
+    Y = np.array(_BIN_Y).T.copy()
+    T = np.array([700.0, 2100.0])
+    p = np.array([1.0, 3.0]) * O.PATM
+    mu, _, _ = om.transport(T, p, Y)
+    np.testing.assert_allclose(mu, want, rtol=1e-14)
+    assert om.wilke_phi(900.0, 0, 1) == pytest.approx(p12, rel=1e-15)
+    assert om.wilke_phi(900.0, 1, 0) == pytest.approx(p21, rel=1e-15)
+    # the readings this rules out are far from the hand values
+    transposed = [e1 / (1 + p21) + e2 / (1 + p12), e1 / (1 + 3 * p21) + 3 * e2 / (3 + p12)]
+    ywt = [y1 * e1 / (y1 + y2 * p12) + y2 * e2 / (y1 * p21 + y2) for y1, y2 in _BIN_Y]
+    p12_printed = (17.0 / 16.0) ** -0.5 * (1.25 ** 2) / math.sqrt(8.0)
+    printed = [e1 / (1 + p12_printed) + e2 / (1 + p21)]
+    for alt, ref in zip(transposed + ywt + printed, want + want + want[:1]):
+        assert abs(alt / ref - 1) > 0.05
+
+
+def test_two_species_mathur_and_binary_diffusion_by_hand():
+    """App. A.3 Mathur conductivity and eq:mix_diff for the two unequal species.
+
+    lambda = (sum X_k lambda_k + 1 / sum X_k / lambda_k) / 2 with lambda = (1, 4) 1e4:
+      X = (1/2, 1/2): (5/2 + 8/5) / 2 = 2.05 (1e4);
+      X = (1/4, 3/4): (13/4 + 16/7) / 2 = 155/56 (1e4).
+    Binary D_1m = (W-bar - X_1 W_1)/W-bar / (X_2 / D_12) = W_2 D_12 / W-bar = (1 - Y_1)
+    D_12 / (1 - X_1): with W-bar = 17, D_1m = 32/17 D_12 and D_2m = 2/17 D_12 at
+    X = (1/2, 1/2); W-bar = 24.5 gives 48/49 / (3/4) D_12 and 1/49 / (1/4) D_12.
+    Mass-fraction weights in Mathur's sums, or X_k in place of Y_k in the D_km
+    numerator, miss these by more than 10 %."""
+    m = _binary_mech()
+    om = O.OracleMech(m)
+    Y = np.array(_BIN_Y).T.copy()
+    T = np.array([800.0, 1900.0])
+    p = np.array([1.0, 4.0]) * O.PATM
+    _, lam, Dm = om.transport(T, p, Y)
+    np.testing.assert_allclose(lam, [2.05e4, 155.0 / 56.0 * 1e4], rtol=1e-14)
+    D12 = 0.5 / np.array([1.0, 4.0])  # D_kj(T, p) = D_kj(1 atm) p_atm / p
+    want_D = np.array([[32.0 / 17.0, (48.0 / 49.0) / 0.75],
+                       [2.0 / 17.0, (1.0 / 49.0) / 0.25]]) * D12
+    np.testing.assert_allclose(Dm, want_D, rtol=1e-14)
+    for (y1, y2), ref in zip(_BIN_Y, (2.05e4, 155.0 / 56.0 * 1e4)):
+        alt = 0.5 * (y1 * 1e4 + y2 * 4e4 + 1.0 / (y1 / 1e4 + y2 / 4e4))
+        assert abs(alt / ref - 1) > 0.1
+    # X_k in place of Y_k in the numerator gives D_1m = D_12 exactly
+    for ref in want_D[0] / D12:
+        assert abs(1.0 / ref - 1) > 0.1
 
 
 def test_diffusion_pressure_scaling_and_symmetry(mech53):
