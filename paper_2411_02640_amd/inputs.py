@@ -378,6 +378,9 @@ class MechSpec:
 MECH_9 = MechSpec(9, 17, 3, 0, 1, seed=9021, name="syn9")
 MECH_53 = MechSpec(53, 266, 30, 0, 29, seed=53325, name="syn53")
 MECH_200 = MechSpec(200, 1200, 180, 30, 90, seed=2001500, name="syn200")
+# 100 species / 700 reactions (the proportions of the 200-species mechanism):
+# the band of 65-128 species, where the kernels take two species per lane
+MECH_100 = MechSpec(100, 560, 84, 14, 42, seed=1000700, name="syn100")
 # syn53 with part of its reactions in the further forms: 10 SRI, 8 chemically
 # activated falloff, 20 pressure-table (PLOG) reactions
 MECH_53X = MechSpec(53, 266, 30, 0, 29, seed=53325, name="syn53x", n_sri=10, n_chemact=8,

@@ -16,7 +16,7 @@ def pytest_configure(config):
 @functools.lru_cache(maxsize=None)
 def _mech(name):
     from paper_2411_02640_amd import inputs as I
-    spec = {"syn9": I.MECH_9, "syn53": I.MECH_53, "syn200": I.MECH_200,
+    spec = {"syn9": I.MECH_9, "syn53": I.MECH_53, "syn200": I.MECH_200, "syn100": I.MECH_100,
             "syn53x": I.MECH_53X, "syn53o": I.MECH_53O, "syn53q": I.MECH_53Q,
             "syn53xq": I.MECH_53XQ, "syn200q": I.MECH_200Q}[name]
     return I.make_mechanism(spec)
@@ -35,6 +35,11 @@ def mech53():
 @pytest.fixture(scope="session")
 def mech200():
     return _mech("syn200")
+
+
+@pytest.fixture(scope="session")
+def mech100():
+    return _mech("syn100")
 
 
 @pytest.fixture(scope="session")

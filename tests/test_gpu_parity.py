@@ -98,29 +98,120 @@ def test_syn53_block(kx, mech53):
     check_transport(kx, mech53, T, p, Y, "16389 points")
 
 
-def test_syn53_full_size_sampled(kx, mech53):
-    """The 2^20-point workload in the launch configuration the benchmark times;
-    the oracle checks a sample of points (every tile boundary kind included)."""
+def test_syn53_full_size_all_points(kx, mech53):
+    """The 2^20-point workload in the launch configuration the benchmark times,
+    every point judged against the oracle (rates and transport)."""
     T, p, Y = I.make_states(53, I.STATES_53)
     n = T.size
     dm = dev_mech(kx, mech53)
     _say("full size syn53 n =", n)
     w = run_rates(kx, dm, T, p, Y)
     mu, lam, Dm = run_transport(kx, dm, T, p, Y)
-    rng = np.random.default_rng(99)
-    idx = np.unique(np.concatenate([rng.choice(n, 1500, replace=False),
-                                    [0, 1, 63, 64, 255, 256, n - 1]]))
-    Ts, ps, Ys = T[idx], p[idx], np.ascontiguousarray(Y[:, idx])
     om = O.OracleMech(mech53)
-    ref, s = om.production_rates(Ts, ps, Ys)
-    r = PM.wdot_report(w[:, idx], ref, s)
+    ref, s = om.production_rates(T, p, Y)
+    r = PM.wdot_report(w, ref, s)
     _say("  wdot", r)
     assert r["ok"], r
-    rmu, rlam, rDm = om.transport(Ts, ps, Ys)
-    for name, g, rr in (("mu", mu[idx], rmu), ("lambda", lam[idx], rlam), ("Dmix", Dm[:, idx], rDm)):
+    del ref, s, w
+    rmu, rlam, rDm = om.transport(T, p, Y)
+    for name, g, rr in (("mu", mu, rmu), ("lambda", lam, rlam), ("Dmix", Dm, rDm)):
         rep = PM.rel_report(g, rr, PM.REL_FP64)
         _say("  ", name, rep)
         assert rep["ok"], (name, rep)
+
+
+def _stratified(n, m, seed):
+    """One point from each of m equal strata of consecutive points (every tile
+    region and, the states being i.i.d., the whole state distribution)."""
+    w = n // m
+    rng = np.random.default_rng(seed)
+    return np.arange(m) * w + rng.integers(0, w, m)
+
+
+def test_syn200_full_size_stratified(kx, mech200):
+    """The 200-species workload at 2^20 points, FP64 and mixed, in the launch
+    configuration the benchmark times; a stratified subset of 2^16 points is
+    judged against the oracle (one oracle evaluation serves both precisions)."""
+    T, p, Y = I.make_states(200, I.STATES_200)
+    n = T.size
+    dm = dev_mech(kx, mech200)
+    idx = _stratified(n, 1 << 16, 17)
+    it = torch.from_numpy(idx).to(DEV)
+    Td, pd, Yd = to_dev(T, p, Y)
+    Ts, ps, Ys = T[idx], p[idx], np.ascontiguousarray(Y[:, idx])
+    del Y
+    om = O.OracleMech(mech200)
+    _say("syn200 oracle on", idx.size, "points")
+    ref, s = om.production_rates(Ts, ps, Ys)
+    rmu, rlam, rDm = om.transport(Ts, ps, Ys)
+    for prec in ("fp64", "mixed"):
+        _say("syn200 full size", prec, "n =", n)
+        w = kx.production_rates(dm, Td, pd, Yd, precision=prec)[:, it].cpu().numpy()
+        mu, lam, Dm = kx.transport(dm, Td, pd, Yd, precision=prec)
+        mu, lam, Dm = mu[it].cpu().numpy(), lam[it].cpu().numpy(), Dm[:, it].cpu().numpy()
+        torch.cuda.synchronize()
+        if prec == "fp64":
+            r = PM.wdot_report(w, ref, s)
+        else:
+            r = PM.mixed_wdot_report(w, ref, s)
+        _say("  wdot", prec, r)
+        assert r["ok"], (prec, r)
+        tol = PM.REL_FP64 if prec == "fp64" else PM.REL_MIXED
+        for name, g, rr in (("mu", mu, rmu), ("lambda", lam, rlam), ("Dmix", Dm, rDm)):
+            rep = PM.rel_report(g, rr, tol)
+            _say("  ", name, prec, rep)
+            assert rep["ok"], (name, prec, rep)
+
+
+def test_syn100_two_species_per_lane(kx, mech100):
+    """100 species / 700 reactions: the rates kernel with two species per lane
+    and the 32-point matrix-core transport tile (the 65-128-species band), FP64
+    and mixed, with a ragged tail; the Jacobian with two waves per point."""
+    T, p, Y = I.make_states(100, I.StateSpec((1 << 13) + 13, seed=71, p_atm_range=(1.0, 40.0),
+                                             dirichlet_alpha=0.3))
+    check_rates(kx, mech100, T, p, Y, "syn100")
+    check_transport(kx, mech100, T, p, Y, "syn100")
+    dm = dev_mech(kx, mech100)
+    om = O.OracleMech(mech100)
+    ref, s = om.production_rates(T, p, Y)
+    w = run_rates(kx, dm, T, p, Y, precision="mixed")
+    r = PM.mixed_wdot_report(w, ref, s)
+    _say("  mixed wdot", r)
+    assert r["ok"], r
+    mu, lam, Dm = run_transport(kx, dm, T, p, Y, precision="mixed")
+    rmu, rlam, rDm = om.transport(T, p, Y)
+    for name, g, rr in (("mu", mu, rmu), ("lambda", lam, rlam), ("Dmix", Dm, rDm)):
+        rep = PM.rel_report(g, rr, PM.REL_MIXED)
+        _say("  mixed", name, rep)
+        assert rep["ok"], (name, rep)
+    Te, pe, Ye = O.equilibrium_states(om, 512, seed=73, perturb=1e-6)
+    check_rates(kx, mech100, Te, pe, Ye, "syn100 near equilibrium")
+    _check_jacobian(kx, mech100, T[:131], p[:131], np.ascontiguousarray(Y[:, :131]), "syn100")
+
+
+def test_three_molecule_sides(kx):
+    """Reactions with three molecules on a side (AB + A <=> B + 2 A, and the
+    explicit-order and every-form reactions of the four-species mechanisms):
+    the rates kernel's third molecule slot, FP64 and mixed, at every point of
+    4096 plus a ragged tail, at 0.05-50 atm."""
+    from . import tiny_mechs as TM
+    for mech, seed in ((TM.abx_mechanism(), 81), (TM.all_forms_mechanism(), 82)):
+        nr = mech["n_reactions"]
+        sides = [int(mech["reac_nu"][mech["reac_ptr"][i]:mech["reac_ptr"][i + 1]].sum())
+                 for i in range(nr)] + \
+                [int(mech["prod_nu"][mech["prod_ptr"][i]:mech["prod_ptr"][i + 1]].sum())
+                 for i in range(nr)]
+        assert max(sides) == 3
+        mech = dict(mech, name="tiny%d" % seed)
+        T, p, Y = I.make_states(4, I.StateSpec(4096 + 29, seed=seed, p_atm_range=(0.05, 50.0),
+                                               dirichlet_alpha=1.0))
+        check_rates(kx, mech, T, p, Y, "three-molecule side")
+        dm = dev_mech(kx, mech)
+        w = run_rates(kx, dm, T, p, Y, precision="mixed")
+        ref, s = O.OracleMech(mech).production_rates(T, p, Y)
+        r = PM.mixed_wdot_report(w, ref, s)
+        _say("  mixed", r)
+        assert r["ok"], r
 
 
 def test_syn200_sampled(kx, mech200):

@@ -226,3 +226,35 @@ def test_host_staged_client(kx, mechs):
         if tr:
             for got, want in zip((mu, lam, Dm), ref[1:]):
                 assert torch.equal(got, want.cpu()), (name, i)
+
+
+def test_served_large_mechanisms_equal_direct(kx, mech100, mech200):
+    """The 100- and 200-species mechanisms served (two species per lane and four
+    per lane in the rates batch kernel; the 32- and 16-point matrix-core
+    transport tiles), both precisions, with a ragged size, in one mixed set of
+    batches: every output equals the direct call bit for bit."""
+    ms = {"syn100": (kx.Mechanism(mech100, 0), mech100),
+          "syn200": (kx.Mechanism(mech200, 0), mech200)}
+    srv = kx.Server(0, hbm_budget=4 << 30, max_slots=16)
+    try:
+        cases = []
+        for i, (name, n, prec) in enumerate([("syn100", 7001, "fp64"), ("syn200", 3001, "fp64"),
+                                             ("syn100", 129, "mixed"), ("syn200", 40003, "mixed"),
+                                             ("syn200", 1, "fp64")]):
+            dm, mech = ms[name]
+            (Td, pd, Yd), _ = _inputs(mech["n_species"], n, 500 + i)
+            cases.append((srv.submit(dm, Td, pd, Yd, transport=True, precision=prec),
+                          name, n, prec, Td, pd, Yd))
+        for t, name, n, prec, Td, pd, Yd in cases:
+            _say("request", t, name, "n =", n, prec)
+            r = srv.wait(t, WAIT_S)
+            assert r["state"] == "done", r
+            got = srv.outputs(t)
+            ref = _direct(kx, ms[name][0], Td, pd, Yd, True, prec)
+            for g, e, what in zip(got, ref, ("wdot", "mu", "lambda", "Dmix")):
+                assert _same(g, e), (name, n, prec, what)
+            srv.release(t)
+    finally:
+        srv.close()
+        for dm, _ in ms.values():
+            dm.close()
