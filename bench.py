@@ -199,9 +199,10 @@ def other_workloads(kx, I, torch, steps, warmup):
 
 
 def cpu_baseline(mech, T, p, Y, target_s=12.0, single_s=3.0):
-    """The oracle as it stands, on a bounded sample of the same states, on all
-    host threads and on one.  Returns the baseline and the oracle's outputs on
-    the first 4096 points (for the error report)."""
+    """The oracle as it stands, on a bounded sample of the same states (the
+    first n points, n chosen for about `target_s` seconds), on all host threads
+    and on one.  Returns the baseline and the oracle's outputs on the whole
+    sample (for the error report)."""
     import numpy as np
     from oracle import oracle as O
     om = O.OracleMech(mech)
@@ -209,15 +210,16 @@ def cpu_baseline(mech, T, p, Y, target_s=12.0, single_s=3.0):
     n0 = 4096
     Y0 = np.ascontiguousarray(Y[:, :n0])
     t0 = time.perf_counter()
-    ref_w, ref_s = om.production_rates(T[:n0], p[:n0], Y0)
-    ref_t = om.transport(T[:n0], p[:n0], Y0)
+    om.production_rates(T[:n0], p[:n0], Y0, with_scale=False)
+    om.transport(T[:n0], p[:n0], Y0)
     est = (time.perf_counter() - t0) / n0
     n = int(min(T.size, max(n0, target_s / max(est, 1e-9))))
     Ys = np.ascontiguousarray(Y[:, :n])
     t0 = time.perf_counter()
-    om.production_rates(T[:n], p[:n], Ys, with_scale=False)
-    om.transport(T[:n], p[:n], Ys)
+    ref_w, ref_s = om.production_rates(T[:n], p[:n], Ys)
+    ref_t = om.transport(T[:n], p[:n], Ys)
     dt = time.perf_counter() - t0
+    del Ys
     # single thread, the paper's per-core comparison basis
     n1 = int(max(256, min(n, single_s * n / dt / max(threads, 1))))
     O.set_threads(1)
@@ -228,30 +230,129 @@ def cpu_baseline(mech, T, p, Y, target_s=12.0, single_s=3.0):
     dt1 = time.perf_counter() - t1
     O.set_threads(threads)
     base = {"value": n / dt / 1e6, "unit": "Mpoints/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} points of the same workload, production rates + transport, "
-                      f"{dt:.1f} s on {threads} threads",
+            "sample": f"first {n} points of the same workload, production rates (with the "
+                      f"conditioning scale s_k) + transport, {dt:.1f} s on {threads} threads",
             "single_thread": {"value": n1 / dt1 / 1e6, "unit": "Mpoints/s", "cores": 1,
                               "sample": f"first {n1} points, {dt1:.1f} s"}}
     return base, (ref_w, ref_s) + tuple(ref_t)
 
 
-def error_report(gpu, ref):
-    """Per-output error of GPU outputs against the oracle on a sample: wdot by
-    the strict relative error and the conditioned error |d| / s_k on entries
-    above 1e-10 max|entry| of their point; transport by the relative error."""
+def error_report(gpu, ref, target):
+    """Per-output error of GPU outputs against the oracle.  wdot entries above
+    1e-10 max|entry| of their point are judged: the strict relative error (max,
+    p99.99, median, the count above `target` and, for those entries, their
+    cancellation ratio kappa = s_k / |wdot_k| with s_k = sum_i |nu_ki| |R_i|),
+    and the conditioned error |d| / s_k.  Transport outputs by the relative
+    error (max, p99.99, median, count above `target`)."""
     import numpy as np
     w, mu, lam, Dm = gpu
     rw, rs, rmu, rlam, rDm = ref
     mask = np.abs(rw) > 1e-10 * np.abs(rw).max(axis=0, keepdims=True)
+    aref = np.abs(rw)[mask]
     d = np.abs(w - rw)[mask]
-    out = {"points": int(rw.shape[1]),
-           "wdot": {"max_rel": float((d / np.abs(rw)[mask]).max()),
-                    "median_rel": float(np.median(d / np.abs(rw)[mask])),
-                    "max_conditioned": float((d / rs[mask]).max())}}
+    rel = d / aref
+    kappa = rs[mask] / aref
+    over = rel > target
+    worst = np.argsort(rel)[::-1][:5]
+    out = {"points": int(rw.shape[1]), "target": target,
+           "wdot": {"judged": int(mask.sum()), "max_rel": float(rel.max()),
+                    "p9999_rel": float(np.quantile(rel, 0.9999)),
+                    "median_rel": float(np.median(rel)),
+                    "n_above_target": int(over.sum()),
+                    "max_conditioned": float((d / rs[mask]).max()),
+                    "kappa_of_entries_above_target": (
+                        {"min": float(kappa[over].min()), "median": float(np.median(kappa[over])),
+                         "max": float(kappa[over].max())} if over.any() else None),
+                    "kappa_all_entries": {"median": float(np.median(kappa)),
+                                          "p9999": float(np.quantile(kappa, 0.9999))},
+                    "worst": [{"rel": float(rel[i]), "kappa": float(kappa[i])} for i in worst]}}
     for name, g, r in (("mu", mu, rmu), ("lambda", lam, rlam), ("Dmix", Dm, rDm)):
-        e = np.abs(g - r) / np.abs(r)
-        out[name] = {"max_rel": float(e.max()), "median_rel": float(np.median(e))}
+        e = (np.abs(g - r) / np.abs(r)).ravel()
+        out[name] = {"max_rel": float(e.max()), "p9999_rel": float(np.quantile(e, 0.9999)),
+                     "median_rel": float(np.median(e)), "n_above_target": int((e > target).sum())}
     return out
+
+
+def cfg3_mixed(kx, mech, steps, warmup):
+    """The mixed-precision workload: 2^22 points of the 53-species mechanism,
+    three quarters drawn as the FP64 workload and one quarter within 1e-6 of
+    constructed equilibrium states (8192 distinct ones, each repeated 128
+    times), randomly interleaved.  Times FP64 and mixed on these states and
+    reports the mixed (and FP64) error against the oracle on all 8192 distinct
+    near-equilibrium states and a stratified sample of 2^15 bulk points."""
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+    from paper_2411_02640_amd import inputs as I
+    sspec = I.STATES_53_MIXED
+    n = sspec.n_points
+    nq = n // 4
+    om = O.OracleMech(mech)
+    log("cfg3: near-equilibrium states")
+    ne = 8192
+    Te, pe, Ye = O.equilibrium_states(om, ne, seed=sspec.seed + 1000, perturb=1e-6)
+    log("cfg3: bulk states")
+    T1, p1, Y1 = I.make_states(53, sspec, n_points=n - nq)
+    reps = nq // ne
+    T = np.concatenate([T1, np.tile(Te, reps)])
+    p = np.concatenate([p1, np.tile(pe, reps)])
+    src = np.concatenate([np.arange(n - nq), -1 - np.tile(np.arange(ne), reps)])
+    perm = np.random.default_rng(sspec.seed).permutation(n)
+    T, p, src = T[perm], p[perm], src[perm]
+    Y = np.empty((53, n))
+    for k in range(53):
+        Y[k] = np.concatenate([Y1[k], np.tile(Ye[k], reps)])[perm]
+    del Y1
+    ns = 53
+    dm = kx.Mechanism(mech, 0)
+    Td, pd, Yd = [torch.from_numpy(a).to("cuda:0") for a in (T, p, Y)]
+    kw = dict(dtype=torch.float64, device="cuda:0")
+    outs = (torch.empty((ns, n), **kw),
+            (torch.empty(n, **kw), torch.empty(n, **kw), torch.empty((ns, n), **kw)))
+    # sample: the first occurrence of every near-equilibrium state and one
+    # bulk point from each of 2^15 strata of the bulk positions
+    bulk_pos = np.flatnonzero(src >= 0)
+    strata = np.array_split(bulk_pos, 1 << 15)
+    rng = np.random.default_rng(sspec.seed + 7)
+    bulk_idx = np.array([s[rng.integers(s.size)] for s in strata])
+    near_pos = np.flatnonzero(src < 0)
+    _, first = np.unique(src[near_pos], return_index=True)
+    near_idx = near_pos[first]
+    res = {"workload": "syn53, 2^22 points: 3/4 T ~ U[300, 2800] K, p ~ U[1, 40] atm, "
+                       "Y ~ Dirichlet(0.3); 1/4 within 1e-6 of 8192 constructed equilibrium "
+                       "states (element potentials), randomly interleaved",
+           "n_points": n, "state_seed": sspec.seed, "steps": steps}
+    sample = {}
+    for prec in ("fp64", "mixed"):
+        log(f"cfg3: {prec} timing")
+        wall, r, t = time_path(kx, dm, Td, pd, Yd, outs, steps, warmup, prec)
+        res[prec] = {"Mpoints_s": n * steps / wall / 1e6, "rates_ms": r, "transport_ms": t,
+                     "rates_ms_median": time_path.medians[0],
+                     "transport_ms_median": time_path.medians[1]}
+        w_, (mu_, lam_, Dm_) = outs
+        for part, idx in (("bulk", bulk_idx), ("near_equilibrium", near_idx)):
+            it = torch.from_numpy(idx).to("cuda:0")
+            sample[(prec, part)] = (w_[:, it].cpu().numpy(), mu_[it].cpu().numpy(),
+                                    lam_[it].cpu().numpy(), Dm_[:, it].cpu().numpy())
+    del outs, Td, pd, Yd
+    dm.close()
+    torch.cuda.empty_cache()
+    res["speedup_mixed_vs_fp64"] = res["mixed"]["Mpoints_s"] / res["fp64"]["Mpoints_s"]
+    res["rates_speedup_mixed_vs_fp64"] = res["fp64"]["rates_ms"] / res["mixed"]["rates_ms"]
+    res["transport_speedup_mixed_vs_fp64"] = (res["fp64"]["transport_ms"] /
+                                              res["mixed"]["transport_ms"])
+    log("cfg3: oracle on the sample")
+    errors = {}
+    for part, idx in (("bulk", bulk_idx), ("near_equilibrium", near_idx)):
+        Ts, ps, Ys = T[idx], p[idx], np.ascontiguousarray(Y[:, idx])
+        ref_w, ref_s = om.production_rates(Ts, ps, Ys)
+        ref = (ref_w, ref_s) + tuple(om.transport(Ts, ps, Ys))
+        errors[part] = {"mixed": error_report(sample[("mixed", part)], ref, 1e-5),
+                        "fp64": error_report(sample[("fp64", part)], ref, 1e-12)}
+    res["error_vs_oracle"] = errors
+    res["criterion"] = ("mixed wdot passes when |d| <= 1e-5 s_k on every judged entry "
+                        "(conditioned error); the plain relative error is reported beside it")
+    return res
 
 
 def serve_bench(kx, args):
@@ -353,8 +454,8 @@ def main():
                     help="skip the 2^22, syn200 and point-count sweep timings")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB elementwise copy first (counter calibration)")
-    ap.add_argument("--serve-requests", type=int, default=400)
-    ap.add_argument("--serve-warmup", type=int, default=40)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-pool", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=int, default=48)
@@ -389,13 +490,11 @@ def main():
     log(f"fp64: {args.warmup} warmup + {args.steps} timed steps, n = {n}")
     wall, r_ms, t_ms = time_path(kx, dm, Td, pd, Yd, outs, args.steps, args.warmup, "fp64")
     r_med, t_med = time_path.medians
-    sample = 4096
 
-    def head(o):  # first `sample` points of the outputs, on the host
+    def host(o):  # the outputs on the host (judged against the oracle later)
         w_, (mu_, lam_, Dm_) = o
-        return (w_[:, :sample].cpu().numpy(), mu_[:sample].cpu().numpy(),
-                lam_[:sample].cpu().numpy(), Dm_[:, :sample].cpu().numpy())
-    gpu64 = head(outs)
+        return (w_.cpu().numpy(), mu_.cpu().numpy(), lam_.cpu().numpy(), Dm_.cpu().numpy())
+    gpu64 = host(outs)
     ms_step = wall / args.steps * 1e3
     value = n * args.steps / wall / 1e6
     log(f"fp64 {value:.1f} Mpoints/s (rates {r_ms:.3f} ms, transport {t_ms:.3f} ms)")
@@ -404,7 +503,7 @@ def main():
     if not args.no_mixed:
         log("mixed precision")
         mwall, mr, mt = time_path(kx, dm, Td, pd, Yd, outs, args.steps, args.warmup, "mixed")
-        gpumx = head(outs)
+        gpumx = host(outs)
         mixed = {"value": n * args.steps / mwall / 1e6, "unit": "Mpoints/s",
                  "ms_per_step": mwall / args.steps * 1e3,
                  "rates_kernel_ms": mr, "transport_kernel_ms": mt,
@@ -431,6 +530,20 @@ def main():
                 "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": profiled_traffic(dom),
                 "flops_per_point": fl, "points_per_launch": n,
                 "hbm_gbs_compulsory": by * n / (ms * 1e-3) / 1e9}
+    # the same work with the elementary functions priced at their measured
+    # cost on this GPU (the library's own sequences, in FP64 FMA issue time):
+    # T_min = flops / peak is the least time the FP64 units need for it
+    log("elementary-function prices")
+    mp = opcount.measure_prices()
+    fl_m = opcount.flops_priced(ops[dom], mp["prices"])
+    tmin_ms = fl_m * n / (FP64_VALU_PEAK_TFLOPS * 1e12) * 1e3
+    roofline.update({"prices_model": dict(opcount.PRICE), "prices_measured": mp["prices"],
+                     "mixed_prices_measured": mp["mixed_prices"],
+                     "fma_tflops_measured": mp["fma_tflops_measured"],
+                     "flops_per_point_measured_prices": fl_m, "tmin_ms": tmin_ms,
+                     "tmin_frac": tmin_ms / ms})
+    log(f"prices {json.dumps(mp['prices'])}; T_min {tmin_ms:.3f} ms = "
+        f"{tmin_ms / ms:.3f} of the {dom} kernel time")
     other = [k for k in kern if k != dom][0]
     oms, ofl, oby = kern[other]
     ofl = float(ofl)
@@ -448,16 +561,26 @@ def main():
         log("serving")
         served = serve_bench(kx, args)
 
-    cpu = errors = None
+    cpu = errors = mixed3 = None
     if not args.no_cpu_baseline:
+        # the legs that run the oracle: the CPU baseline, the error of both
+        # paths on its sample, and the mixed-precision workload's accuracy
         log("cpu baseline (oracle)")
+        del Td, pd, Yd, outs
+        torch.cuda.empty_cache()
         cpu, ref = cpu_baseline(mech, T, p, Y)
         log(f"oracle {cpu['value']:.4f} Mpoints/s on {cpu['cores']} threads, "
             f"{cpu['single_thread']['value']:.5f} on one")
-        errors = {"fp64": error_report(gpu64, ref)}
+        ns_ = ref[0].shape[1]
+        cut = lambda g: (g[0][:, :ns_], g[1][:ns_], g[2][:ns_], g[3][:, :ns_])
+        errors = {"fp64": error_report(cut(gpu64), ref, 1e-12)}
         if mixed is not None:
-            errors["mixed"] = error_report(gpumx, ref)
+            errors["mixed"] = error_report(cut(gpumx), ref, 1e-5)
+        del ref, gpu64
         log("errors vs oracle", json.dumps(errors))
+        if not args.no_mixed:
+            mixed3 = cfg3_mixed(kx, mech, args.steps, args.warmup)
+            log("cfg3", json.dumps({k: mixed3[k] for k in ("fp64", "mixed")}))
 
     line = {
         "metric": "Mpoints/s wdot+transport (53 sp) FP64 vs mixed; served p50/p99 latency",
@@ -474,7 +597,8 @@ def main():
         "rates_kernel_ms": r_ms, "transport_kernel_ms": t_ms,
         "rates_kernel_ms_median": r_med, "transport_kernel_ms_median": t_med,
         "error_vs_oracle": errors,
-        "roofline": roofline, "cpu_baseline": cpu, "mixed": mixed, "served": served,
+        "roofline": roofline, "cpu_baseline": cpu, "mixed": mixed,
+        "mixed_workload_2p22": mixed3, "served": served,
         "other_workloads": extra,
     }
     print(json.dumps(line), flush=True)

@@ -62,9 +62,9 @@ enum {
 /* Precision flag of the _ex entry points. */
 enum {
     KX_FP64 = 0,   /* every operation in IEEE double precision */
-    KX_MIXED = 1   /* FP32 bulk with FP64 Gibbs / K_c, the near-equilibrium
-                      bracket and a compensated FP64 wdot sum (see
-                      kx_production_rates_ex) */
+    KX_MIXED = 1   /* FP32 for the exponentials' reduced arguments, the falloff
+                      blend and the transport fits and pair sums; FP64 for the
+                      rest (see kx_production_rates_ex and kx_transport_ex) */
 };
 
 /* Reaction types (App. A.2). */
@@ -203,12 +203,19 @@ kx_status kx_production_rates(const kx_mech *mech, int64_t n, const double *T,
                               const double *p, const double *Y, double *wdot,
                               hipStream_t stream);
 
-/* As kx_production_rates with a precision flag.  KX_MIXED evaluates the
- * Arrhenius, third-body and falloff arithmetic in FP32 (the Arrhenius
- * exponent argument is formed and range-reduced in FP64), while the species
- * Gibbs energies, K_c, the bracket of forward minus reverse terms and the
- * compensated wdot sum stay in FP64.  Inputs and outputs are FP64 either way.
- * KX_MIXED on a mechanism with QSS species returns KX_EUNSUPPORTED. */
+/* As kx_production_rates with a precision flag.  KX_MIXED changes three steps
+ * to FP32: the exponentials of the forward rate constants (eq:arrhenius) and of
+ * the falloff ratio k_0/k_inf, whose arguments are formed and reduced by n ln 2
+ * in FP64 so that only e^r, |r| <= ln2/2, is evaluated in FP32 (about 1e-7
+ * relative); and the Troe / SRI blending factor F (eq:blend).  Everything else
+ * stays FP64: the species Gibbs energies and K_c factors, the third-body sums,
+ * the products of concentrations, the bracket of forward minus reverse terms,
+ * and the wdot sum (Neumaier-compensated across groups of eight terms).  The
+ * result is within 1e-5 of the FP64 value relative to s_k = sum_i |nu_ki|
+ * |R_i| (the magnitude of the terms that cancel into wdot_k); where s_k >>
+ * |wdot_k| the plain relative error can exceed 1e-5.  Inputs and outputs are
+ * FP64 either way.  KX_MIXED on a mechanism with QSS species returns
+ * KX_EUNSUPPORTED. */
 kx_status kx_production_rates_ex(const kx_mech *mech, int64_t n, const double *T,
                                  const double *p, const double *Y, double *wdot,
                                  int32_t precision, hipStream_t stream);
@@ -221,9 +228,12 @@ kx_status kx_transport(const kx_mech *mech, int64_t n, const double *T, const do
                        const double *Y, double *mu, double *lambda, double *Dmix,
                        hipStream_t stream);
 
-/* As kx_transport with a precision flag.  KX_MIXED evaluates the fits and the
- * mixing sums in FP32 with FP32 accumulation; the D_km numerator
- * (W-bar - X_k W_k)/W-bar is formed in FP64. */
+/* As kx_transport with a precision flag.  KX_MIXED evaluates the pure-species
+ * fits, the Wilke factors and the pair sums (sum_j X_j phi_kj, sum_j X_j/D_kj)
+ * in FP32 with FP32 accumulation; the mole fractions, W-bar, Mathur's two sums
+ * over species, the final sum over species of mu and the D_km numerator
+ * (W-bar - X_k W_k)/W-bar stay FP64.  Each output is within 1e-5 relative of
+ * the FP64 value. */
 kx_status kx_transport_ex(const kx_mech *mech, int64_t n, const double *T, const double *p,
                           const double *Y, double *mu, double *lambda, double *Dmix,
                           int32_t precision, hipStream_t stream);

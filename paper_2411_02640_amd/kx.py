@@ -18,7 +18,9 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libkx.so")
+# KX_LIBRARY names another build of the same library (the thread-sanitizer
+# build of the host code, for instance); the default is the in-tree libkx.so.
+LIB_PATH = os.environ.get("KX_LIBRARY") or os.path.join(HERE, "libkx.so")
 
 KX_OK, KX_EINVAL, KX_ENOMEM, KX_EDEVICE, KX_EUNSUPPORTED, KX_EAGAIN = 0, -1, -2, -3, -4, -5
 KX_FP64, KX_MIXED = 0, 1

@@ -11,6 +11,12 @@ model's, stated here so that the roofline fraction can be reproduced:
     exp, exp10: 24    log, log10: 24    division, reciprocal: 8
     sqrt, 1/sqrt: 8
 
+`measure_prices` measures the same classes on the GPU as the library
+evaluates them (its exponential, logarithm, reciprocal and reciprocal square
+root sequences), in FP64 FMA issue time; with those prices the count gives
+T_min = flops / peak, the least time the FP64 vector units need for the
+work the method requires.
+
 Counts are per point; a launch processes n points.
 """
 from __future__ import annotations
@@ -18,6 +24,59 @@ from __future__ import annotations
 import numpy as np
 
 PRICE = {"exp": 24, "log": 24, "div": 8, "sqrt": 8}
+
+# Probe ops of libkx_micro.so (kx_micro.hip) by price class; a division is the
+# library's reciprocal times the numerator, a square root its reciprocal
+# square root times the argument (one more multiply each).
+_PROBE = {"add": 0, "fma": 1, "exp": 2, "log": 3, "rcp": 4, "rsqrt": 5, "exp_mixed": 6,
+          "exp32": 7, "rcp32": 8, "fma32": 9}
+
+
+def measure_prices(iters: int = 400, blocks: int = 256 * 16, reps: int = 5) -> dict:
+    """Price of each elementary function as the library evaluates it on this
+    GPU, in flops (the issue time of FP64 FMAs, 2 flops each): every probe
+    advances eight independent values per lane through one operation on a
+    grid filling every SIMD; the loop's bookkeeping add is timed alone and
+    subtracted.  Needs a GPU and libkx_micro.so."""
+    import ctypes
+    import os
+
+    import torch
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkx_micro.so")
+    if not os.path.exists(path):
+        raise RuntimeError("libkx_micro.so is not built (python -m paper_2411_02640_amd.build)")
+    lib = ctypes.CDLL(path)
+    lib.kx_micro_time.restype = ctypes.c_int
+    lib.kx_micro_time.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    out = torch.empty(blocks * 256, dtype=torch.float64, device="cuda:0")
+    ms = {}
+    for name, op in _PROBE.items():
+        t = ctypes.c_double()
+        rc = lib.kx_micro_time(op, iters, blocks, reps, ctypes.c_void_p(out.data_ptr()),
+                               ctypes.byref(t))
+        if rc != 0:
+            raise RuntimeError(f"kx_micro_time({name}) failed: {rc}")
+        ms[name] = t.value
+    torch.cuda.synchronize()
+    unit = ms["fma"] - ms["add"]
+    fl = lambda k: 2.0 * (ms[k] - ms["add"]) / unit
+    prices = {"exp": fl("exp"), "log": fl("log"), "div": fl("rcp") + 1.0,
+              "sqrt": fl("rsqrt") + 1.0}
+    mixed = {"exp_mixed": fl("exp_mixed"), "exp32": fl("exp32"), "div32": fl("rcp32") + 1.0,
+             "fma32": fl("fma32")}
+    # achieved FP64 FMA rate of the probe (a check of the 78.6 TFLOP/s peak)
+    n_fma = blocks * 256 * iters * 8
+    rate = 2.0 * n_fma / ((ms["fma"] - ms["add"]) * 1e-3) / 1e12
+    return {"prices": prices, "mixed_prices": mixed, "probe_ms": ms,
+            "fma_tflops_measured": rate}
+
+
+def flops_priced(counts: dict, prices: dict) -> float:
+    """flops of a count with the given prices of the elementary functions."""
+    return (2 * counts["fma"] + counts["mul"] + counts["add"]
+            + prices["exp"] * counts["exp"] + prices["log"] * counts["log"]
+            + prices["div"] * counts["div"] + prices["sqrt"] * counts["sqrt"])
 
 
 def rates_ops(mech: dict) -> dict:

@@ -120,9 +120,19 @@ def test_slot_limit(m53):
 
 
 def test_batches_are_homogeneous(m53, m9):
-    s = kx.Server(hbm_budget=1 << 32, max_slots=64, simulate=True)
+    """60 requests of two mechanisms and both precisions queue behind a
+    finished request that holds the whole arena; releasing it admits them in
+    one pass, and they run as one batch per (mechanism, precision) group
+    (independent of how fast the submitting thread is)."""
+    n_blk = 1 << 20
+    s = kx.Server(hbm_budget=footprint(m53.n_species, n_blk, False), max_slots=64,
+                  simulate=True)
+    blocker = s.submit(m53, n=n_blk)
+    assert s.wait(blocker, 10.0)["state"] == "done"
     spec = [(m53 if i % 3 else m9, "fp64" if i % 2 else "mixed") for i in range(60)]
     ts = [s.submit(m, n=5_000, precision=p) for m, p in spec]
+    assert s.stats()["queued"] == 60
+    s.release(blocker)
     groups = {}
     for (m, p), t in zip(spec, ts):
         r = s.wait(t, 10.0)
@@ -130,7 +140,7 @@ def test_batches_are_homogeneous(m53, m9):
         groups.setdefault(r["t_launch"], set()).add((m.handle.value, p))
         s.release(t)
     assert all(len(g) == 1 for g in groups.values())
-    assert s.stats()["batches"] < 60
+    assert s.stats()["batches"] <= 1 + 4
     s.close()
 
 
@@ -193,4 +203,45 @@ def test_latency_timestamps(m53):
     assert r["t_arrival"] <= r["t_admit"] <= r["t_launch"] <= r["t_done"]
     assert r["t_done"] - r["t_launch"] >= 200_000 * 5e-9 * 0.9
     s.release(t)
+    s.close()
+
+
+def test_concurrent_clients(m53, m9):
+    """Four client threads submit, poll, wait for, cancel and release requests
+    at the same time as the scheduler runs (the ctypes calls release the GIL,
+    so the library sees concurrent callers); every request ends DONE or
+    CANCELLED and the arena is empty at the end."""
+    import threading
+    s = kx.Server(hbm_budget=64 << 20, max_slots=8, simulate=True)
+    errors = []
+
+    def client(c):
+        try:
+            ts = []
+            for i in range(30):
+                m = m53 if (i + c) % 2 else m9
+                ts.append(s.submit(m, n=2_000 + 500 * i, transport=bool(i % 3 == 0),
+                                   precision="mixed" if i % 4 == 0 else "fp64"))
+                s.poll(ts[-1])
+                if i % 7 == 3:
+                    try:
+                        s.cancel(ts[-1])
+                    except kx.KxError:
+                        pass  # already launched
+            for t in ts:
+                r = s.wait(t, 30.0)
+                assert r["state"] in ("done", "cancelled"), r
+                s.release(t)
+        except Exception as e:  # noqa: BLE001 -- reported by the main thread
+            errors.append(e)
+
+    th = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    st = s.stats()
+    assert st["submitted"] == 120 and st["completed"] + st["cancelled"] == 120
+    assert st["arena_in_use"] == 0 and st["in_flight"] == 0
     s.close()
