@@ -376,6 +376,8 @@ def serve_bench(kx, args):
                                    SERVE_SEED * 1000 + spec.n_species)
     srv = kx.Server(0, hbm_budget=args.serve_budget_gb << 30, max_slots=args.serve_slots)
     try:
+        for m in mechs.values():   # resident tables and captured graphs before any request
+            srv.add_mech(m)
         nw, nm = args.serve_warmup, args.serve_requests
         # warm every (mechanism, precision, ops) graph on every stream
         SL.run_stream(srv, mechs, pools, SL.make_stream(4 * nw, pools, SERVE_SEED + 1), None, 0)
@@ -436,6 +438,7 @@ def serve_bench(kx, args):
             "direct_sequential_Mpoints_s": sum(pools[nm_][i][0] for nm_, i, _, _ in cap_stream)
                                            / seq_s / 1e6,
             "levels": levels, "batches": st["batches"], "graph_launches": st["graph_launches"],
+            "resident_mechs": st["resident_mechs"], "resident_bytes": st["resident_bytes"],
             "host_staged": dict(staged, workload="the same mix with inputs and outputs in "
                                 "pinned host memory: inputs copied to the device at arrival, "
                                 "latency to outputs copied back to the host")}

@@ -277,14 +277,15 @@ kx_status kx_qss_concentrations(const kx_mech *mech, int64_t n, const double *T,
 /* ------------------------------------------------------------------------
  * Serving: a continuous-batching request server (project addition; the paper
  * notes that GPUs reach their throughput only with >~1e5 points, so small
- * requests are batched).  A server owns an HBM arena of `hbm_budget` bytes for
- * request outputs; a scheduler thread admits queued requests in arrival order
- * whenever a slot and arena space are free, groups admitted requests by
- * (mechanism, precision) into batches of up to 64, and runs each batch as
- * work-stealing kernels over a device work list, replayed from a HIP graph,
- * on one of several streams -- batches of different groups overlap on the
- * device.  Every request is cut into the same tiles as a direct call, so its
- * outputs are bit-identical alone and in a batch.
+ * requests are batched).  A server owns an HBM arena of `hbm_budget` bytes that
+ * holds the tables of its resident mechanisms (kx_server_add_mech) and the
+ * outputs of admitted requests; a scheduler thread admits queued requests in
+ * arrival order whenever a slot and arena space are free, groups admitted
+ * requests by (mechanism, precision) into batches of up to 64, and runs each
+ * batch as work-stealing kernels over a device work list, replayed from a HIP
+ * graph, on one of several streams -- batches of different groups overlap on
+ * the device.  Every request is cut into the same tiles as a direct call, so
+ * its outputs are bit-identical alone and in a batch.
  * ------------------------------------------------------------------------ */
 typedef struct kx_server kx_server;
 typedef int64_t kx_ticket;
@@ -306,6 +307,12 @@ typedef struct {
                                  DONE, CANCELLED or FAILED */
     double arrival_s;         /* arrival time on kx_server_clock() for latency
                                  accounting; < 0 means "now" */
+    hipEvent_t inputs_ready;  /* NULL: the inputs are complete when kx_submit is
+                                 called (the stream that wrote them synchronised).
+                                 Otherwise an event recorded after the work that
+                                 writes them: the server's streams wait for it
+                                 before reading them.  It must stay valid until the
+                                 request is DONE, CANCELLED or FAILED. */
 } kx_request;
 
 typedef struct {
@@ -320,7 +327,8 @@ typedef struct {
     int64_t submitted, completed, cancelled, failed;
     int64_t queued, in_flight;          /* now */
     int64_t batches, graph_launches;
-    int64_t arena_in_use, arena_capacity;
+    int64_t arena_in_use, arena_capacity;  /* bytes; in use includes resident tables */
+    int64_t resident_mechs, resident_bytes;
 } kx_server_stats;
 
 /* Monotonic clock (seconds) used for all server time stamps. */
@@ -339,9 +347,24 @@ kx_status kx_server_create(int device, int64_t hbm_budget, int32_t max_slots, in
  * Pointers from kx_result become invalid. */
 kx_status kx_server_destroy(kx_server *srv);
 
-/* Queue a request.  KX_EINVAL for a bad request; KX_ENOMEM if its output
- * footprint n * 8 * (Ns [wdot] + (Ns + 2) [transport]) exceeds the whole
- * budget; KX_EUNSUPPORTED for a mechanism with QSS species (call
+/* Make `mech` resident on the server: its device tables (kx_mech_info's
+ * device_bytes, rounded up to 256) are copied into the server's arena, where
+ * they stay until kx_server_destroy and count against the HBM budget, and the
+ * launch graphs of its batches (both precisions, both op sets, every stream)
+ * are captured now rather than by its first requests.  Requests may name only
+ * resident mechanisms.  Adding a mechanism twice is a no-op.  KX_ENOMEM if the
+ * tables do not fit in the arena's free space; KX_EINVAL for a NULL argument
+ * or a mechanism without tables on the server's device (a host-only handle is
+ * accepted by a KX_SERVER_SIMULATE server, which charges its bytes without a
+ * copy); KX_EUNSUPPORTED for a mechanism with QSS species.  Blocks until the
+ * copy and the captures are done.  `mech` must outlive the server (it keys the
+ * requests that name it). */
+kx_status kx_server_add_mech(kx_server *srv, const kx_mech *mech);
+
+/* Queue a request.  KX_EINVAL for a bad request or a mechanism that is not
+ * resident (kx_server_add_mech); KX_ENOMEM if its output footprint
+ * n * 8 * (Ns [wdot] + (Ns + 2) [transport]) exceeds the budget left after the
+ * resident tables; KX_EUNSUPPORTED for a mechanism with QSS species (call
  * kx_production_rates for those).  n == 0 completes immediately. */
 kx_status kx_submit(kx_server *srv, const kx_request *req, kx_ticket *ticket);
 

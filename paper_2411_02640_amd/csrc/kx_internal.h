@@ -221,4 +221,11 @@ kx_status launch_transport_batch(const MechDev &m, const WorkList *wl, int *coun
 // Sets the transport batch kernel's dynamic-LDS limit (before graph capture).
 kx_status prepare_transport_batch(const MechDev &m, int precision);
 kx_status launch_zero(int *p, int count, hipStream_t s);
+// Counters a batch uses: one per XCD for the rates tiles, one for transport.
+constexpr int kXcds = 8;
+constexpr int kBatchCounters = kXcds + 1;
+// The device tables of `m` as they read from a byte-identical copy placed at
+// `base`: every table pointer moved from m->blob to base.  False if some
+// pointer still addresses the original tables (a field this function misses).
+bool rebase_tables(const kx_mech *m, const void *base, MechDev *out);
 }  // namespace kx

@@ -688,4 +688,32 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     return ok();
 }
 
+bool rebase_tables(const kx_mech *m, const void *base, MechDev *out)
+{
+    MechDev v = m->dev;
+    const char *old = static_cast<const char *>(m->blob);
+    const char *nb = static_cast<const char *>(base);
+#define KX_REBASE(f) \
+    v.f = m->dev.f ? reinterpret_cast<decltype(v.f)>(nb + (reinterpret_cast<const char *>(m->dev.f) - old)) \
+                   : nullptr
+    KX_REBASE(rxn); KX_REBASE(aux); KX_REBASE(eff); KX_REBASE(plog); KX_REBASE(sp);
+    KX_REBASE(gpos); KX_REBASE(gneg); KX_REBASE(goff); KX_REBASE(gent);
+    KX_REBASE(W); KX_REBASE(visc); KX_REBASE(cond); KX_REBASE(wq); KX_REBASE(wilke);
+    KX_REBASE(dfit); KX_REBASE(ddiag);
+    KX_REBASE(visc32); KX_REBASE(cond32); KX_REBASE(wq32); KX_REBASE(wilke32);
+    KX_REBASE(dfit32); KX_REBASE(ddiag32);
+    KX_REBASE(gfrag); KX_REBASE(c1frag); KX_REBASE(gfrag32); KX_REBASE(c1frag32);
+    KX_REBASE(qidx); KX_REBASE(qrow_ptr); KX_REBASE(qrow_ent); KX_REBASE(qrx);
+#undef KX_REBASE
+    // every table pointer must have moved: no 8-byte word of the result may
+    // still address the original tables
+    uintptr_t words[sizeof(MechDev) / sizeof(uintptr_t)];
+    std::memcpy(words, &v, sizeof words);
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(old), hi = lo + (uintptr_t)m->bytes;
+    for (uintptr_t w : words)
+        if (w >= lo && w < hi) return false;
+    *out = v;
+    return true;
+}
+
 }  // namespace kx

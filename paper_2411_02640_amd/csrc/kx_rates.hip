@@ -570,26 +570,40 @@ __global__ __launch_bounds__(kWave, SPL == 1 ? 4 : (SPL == 2 ? 3 : 2)) void rate
         rates_tile<MIXED, SPL, false>(m, n, i0, np, tp, T, P, Y, wdot);
 }
 
-// Batched requests: workgroups take tiles from a shared counter until the
-// batch's tiles are exhausted (every workgroup exits once the counter passes
-// the tile count).  Tile t belongs to the last item whose first tile is <= t.
+// Batched requests.  The batch's tiles are split into kXcds contiguous ranges,
+// one per XCD (workgroup b runs on XCD b mod kXcds); a workgroup takes tiles
+// of its own XCD's range from that range's counter, so neighbouring tiles --
+// which share cache lines of Y and wdot -- meet in the same L2 as in a direct
+// launch, and then helps with the other ranges in turn.  Every workgroup
+// exits after the last range is exhausted.  Tile t belongs to the last item
+// whose first tile is <= t.
 template <bool MIXED, int SPL>
 __global__ __launch_bounds__(kWave, SPL == 1 ? 4 : (SPL == 2 ? 3 : 2)) void rates_batch_kernel(MechDev m,
                                                             const WorkList *__restrict__ wl,
                                                             int *__restrict__ counter, int tp)
 {
     const int ntiles = wl->ntiles[0];
-    for (;;) {
-        int t = 0;
-        if (threadIdx.x == 0) t = atomicAdd(counter, 1);
-        t = __shfl(t, 0, kWave);
-        if (t >= ntiles) break;
-        int r = 0;
-        while (r + 1 < wl->nitems && wl->start[0][r + 1] <= t) ++r;
-        const WorkItem it = wl->items[r];
-        const int64_t i0 = (int64_t)(t - wl->start[0][r]) * tp;
-        rates_tile<MIXED, SPL, false>(m, it.n, i0, (int)min((int64_t)tp, it.n - i0), tp, it.T, it.p,
-                               it.Y, it.wdot);
+    const int x0 = (int)(blockIdx.x % kXcds);
+    const bool direct = lds_base() == 0;
+    for (int step = 0; step < kXcds; ++step) {
+        const int x = (x0 + step) % kXcds;
+        const int lo = (int)((int64_t)ntiles * x / kXcds);
+        const int hi = (int)((int64_t)ntiles * (x + 1) / kXcds);
+        for (;;) {
+            int t = 0;
+            if (threadIdx.x == 0) t = atomicAdd(counter + x, 1);
+            t = lo + __shfl(t, 0, kWave);
+            if (t >= hi) break;
+            int r = 0;
+            while (r + 1 < wl->nitems && wl->start[0][r + 1] <= t) ++r;
+            const WorkItem it = wl->items[r];
+            const int64_t i0 = (int64_t)(t - wl->start[0][r]) * tp;
+            const int np = (int)min((int64_t)tp, it.n - i0);
+            if (direct)
+                rates_tile<MIXED, SPL, true>(m, it.n, i0, np, tp, it.T, it.p, it.Y, it.wdot);
+            else
+                rates_tile<MIXED, SPL, false>(m, it.n, i0, np, tp, it.T, it.p, it.Y, it.wdot);
+        }
     }
 }
 

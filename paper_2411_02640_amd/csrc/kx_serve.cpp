@@ -1,7 +1,10 @@
 // kx_serve.cpp -- continuous-batching request server.
 //
-// Requests (device-resident inputs, any resident mechanism, op and precision)
-// are queued in arrival order.  A scheduler thread
+// Mechanisms are made resident with kx_server_add_mech: their device tables
+// are copied into the server's arena (so they count against its HBM budget)
+// and the launch graphs of their batches are captured at once.  Requests
+// (device-resident inputs, any resident mechanism, op and precision) are
+// queued in arrival order.  A scheduler thread
 //   1. retires finished batches (event query) and marks their requests DONE;
 //   2. admits queued requests in order while a slot is free and the output
 //      arena has room for the request's outputs (admission by HBM footprint);
@@ -15,6 +18,9 @@
 //      addresses and the grids do not depend on the batch.
 // Batches of different groups run on different streams and overlap on the
 // device; requests that arrive meanwhile join the next batch of their group.
+// The scheduler holds the server lock only while it changes request state:
+// work-list copies, graph launches and event records run without it, so
+// clients submitting and polling are not held up by HIP calls.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -106,12 +112,18 @@ struct Req {
 
 using GraphKey = std::tuple<uint64_t, int, int>;  // (mechanism uid, precision, ops)
 
+// A mechanism resident on the server: its tables copied into the arena.
+struct ServedMech {
+    MechDev dev;             // table pointers into the server's copy
+    size_t off = 0, bytes = 0;
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     WorkList *d_wl = nullptr;   // device work list
     WorkList *h_wl = nullptr;   // pinned staging
-    int *d_counter = nullptr;   // two tile counters (rates, transport)
+    int *d_counter = nullptr;   // kBatchCounters tile counters (rates per XCD, transport)
     bool busy = false;
     double sim_done_at = 0;
     std::vector<Req *> reqs;
@@ -140,6 +152,9 @@ struct kx_server {
     bool stop = false;
     kx_ticket next_id = 1;
     kx_server_stats stats{};
+    std::unordered_map<const kx_mech *, ServedMech> mechs;  // resident mechanisms
+    size_t resident_bytes = 0;
+    std::mutex add_mu;  // serialises kx_server_add_mech
 };
 
 namespace kx {
@@ -166,23 +181,25 @@ void place_outputs(kx_server *s, Req *q)
     }
 }
 
-kx_status build_graph(kx_server *s, Slot &sl, const kx_mech *m, int prec, int ops,
+// Capture the launch sequence of one batch of (mechanism, precision, ops) on
+// slot `sl`'s work list and counters; captured on `cap` (any idle stream: the
+// graph does not belong to a stream).
+kx_status build_graph(const MechDev &dev, Slot &sl, int prec, int ops, hipStream_t cap,
                       hipGraphExec_t *out)
 {
     // kernel attributes are set outside the capture
-    kx_status pst = prepare_rates_batch(m->dev, prec);
-    if (pst == KX_OK && (ops & KX_OP_TRANSPORT)) pst = prepare_transport_batch(m->dev, prec);
+    kx_status pst = prepare_rates_batch(dev, prec);
+    if (pst == KX_OK && (ops & KX_OP_TRANSPORT)) pst = prepare_transport_batch(dev, prec);
     if (pst != KX_OK) return pst;
-    hipError_t e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    kx_status st = launch_zero(sl.d_counter, 2, sl.stream);
-    if (st == KX_OK)
-        st = launch_rates_batch(m->dev, sl.d_wl, sl.d_counter, prec, kRatesGrid, sl.stream);
+    kx_status st = launch_zero(sl.d_counter, kBatchCounters, cap);
+    if (st == KX_OK) st = launch_rates_batch(dev, sl.d_wl, sl.d_counter, prec, kRatesGrid, cap);
     if (st == KX_OK && (ops & KX_OP_TRANSPORT))
-        st = launch_transport_batch(m->dev, sl.d_wl, sl.d_counter + 1, prec, kTransportGrid,
-                                    sl.stream);
+        st = launch_transport_batch(dev, sl.d_wl, sl.d_counter + kXcds, prec, kTransportGrid,
+                                    cap);
     hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(sl.stream, &g);
+    e = hipStreamEndCapture(cap, &g);
     if (st != KX_OK) {
         if (g) hipGraphDestroy(g);
         return st;
@@ -191,18 +208,13 @@ kx_status build_graph(kx_server *s, Slot &sl, const kx_mech *m, int prec, int op
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-    (void)s;
     return KX_OK;
 }
 
-// Launch one batch on an idle slot.  Called with the lock held.
-void launch_batch(kx_server *s, Slot &sl, std::vector<Req *> &batch)
+// Mark a batch as launched on slot `sl`.  Called with the lock held.
+void begin_batch(kx_server *s, Slot &sl, std::vector<Req *> &batch)
 {
     const double t = now_s();
-    const kx_mech *m = batch[0]->r.mech;
-    const int prec = batch[0]->r.precision;
-    int ops = 0;
-    for (Req *q : batch) ops |= q->r.ops;
     for (Req *q : batch) {
         q->state = KX_REQ_RUNNING;
         q->t_launch = t;
@@ -214,13 +226,26 @@ void launch_batch(kx_server *s, Slot &sl, std::vector<Req *> &batch)
         double work = 0;
         for (Req *q : batch) work += (double)q->r.n * ((q->r.ops & KX_OP_TRANSPORT) ? 2 : 1);
         sl.sim_done_at = t + work * kSimSecondsPerPoint;
-        return;
     }
+}
+
+// Enqueue a begun batch on its slot's stream: work list, waits on the inputs'
+// events, graph replay, completion event.  Called WITHOUT the lock: it reads
+// only the requests of this batch (fixed while they run) and the slot, which
+// no other thread touches while it is busy.  Returns whether the graph was
+// launched (false: nothing usable was enqueued).
+bool enqueue_batch(kx_server *s, Slot &sl, const ServedMech &sm, hipGraphExec_t graph,
+                   hipGraphExec_t *new_graph, bool *used_graph)
+{
+    const std::vector<Req *> &batch = sl.reqs;
+    const int prec = batch[0]->r.precision;
+    int ops = 0;
+    for (Req *q : batch) ops |= q->r.ops;
     WorkList &w = *sl.h_wl;
     std::memset(&w, 0, sizeof w);
     w.nitems = (int)batch.size();
-    const int tpr = rates_tile_points(m->dev);
-    const int tpt = transport_tile_points(m->dev, prec);
+    const int tpr = rates_tile_points(sm.dev);
+    const int tpt = transport_tile_points(sm.dev, prec);
     int tr = 0, tt = 0;
     for (size_t r = 0; r < batch.size(); ++r) {
         const Req *q = batch[r];
@@ -241,46 +266,55 @@ void launch_batch(kx_server *s, Slot &sl, std::vector<Req *> &batch)
     w.start[0][batch.size()] = w.ntiles[0] = tr;
     w.start[1][batch.size()] = w.ntiles[1] = tt;
 
-    bool ok_launch = false;
-    hipError_t e = hipMemcpyAsync(sl.d_wl, sl.h_wl, sizeof(WorkList), hipMemcpyHostToDevice,
-                                  sl.stream);
-    if (e == hipSuccess) {
-        const GraphKey key{m->uid, prec, ops};
-        auto it = sl.graphs.find(key);
-        if (it == sl.graphs.end()) {
-            hipGraphExec_t ex = nullptr;
-            if (build_graph(s, sl, m, prec, ops, &ex) == KX_OK) it = sl.graphs.emplace(key, ex).first;
+    bool ok_launch = true;
+    for (const Req *q : batch)
+        if (ok_launch && q->r.inputs_ready)
+            ok_launch = hipStreamWaitEvent(sl.stream, q->r.inputs_ready, 0) == hipSuccess;
+    if (ok_launch)
+        ok_launch = hipMemcpyAsync(sl.d_wl, sl.h_wl, sizeof(WorkList), hipMemcpyHostToDevice,
+                                   sl.stream) == hipSuccess;
+    *used_graph = false;
+    *new_graph = nullptr;
+    if (ok_launch) {
+        if (!graph) {
+            // captured when the mechanism was added; built here only if that
+            // failed (the caller files it under the lock)
+            if (build_graph(sm.dev, sl, prec, ops, sl.stream, new_graph) == KX_OK)
+                graph = *new_graph;
         }
-        if (it != sl.graphs.end()) {
-            ok_launch = hipGraphLaunch(it->second, sl.stream) == hipSuccess;
-            if (ok_launch) s->stats.graph_launches++;
+        if (graph) {
+            ok_launch = hipGraphLaunch(graph, sl.stream) == hipSuccess;
+            *used_graph = ok_launch;
         } else {
             // direct launches (graph capture unavailable)
-            ok_launch = prepare_rates_batch(m->dev, prec) == KX_OK &&
-                        prepare_transport_batch(m->dev, prec) == KX_OK &&
-                        launch_zero(sl.d_counter, 2, sl.stream) == KX_OK &&
-                        launch_rates_batch(m->dev, sl.d_wl, sl.d_counter, prec, kRatesGrid,
+            ok_launch = prepare_rates_batch(sm.dev, prec) == KX_OK &&
+                        prepare_transport_batch(sm.dev, prec) == KX_OK &&
+                        launch_zero(sl.d_counter, kBatchCounters, sl.stream) == KX_OK &&
+                        launch_rates_batch(sm.dev, sl.d_wl, sl.d_counter, prec, kRatesGrid,
                                            sl.stream) == KX_OK &&
                         (!(ops & KX_OP_TRANSPORT) ||
-                         launch_transport_batch(m->dev, sl.d_wl, sl.d_counter + 1, prec,
+                         launch_transport_batch(sm.dev, sl.d_wl, sl.d_counter + kXcds, prec,
                                                 kTransportGrid, sl.stream) == KX_OK);
         }
     }
     if (ok_launch) ok_launch = hipEventRecord(sl.done, sl.stream) == hipSuccess;
-    if (!ok_launch) {
-        // nothing usable was enqueued: fail the batch now (the stream is drained
-        // before the slot is reused)
-        hipStreamSynchronize(sl.stream);
-        for (Req *q : batch) {
-            q->state = KX_REQ_FAILED;
-            q->t_done = now_s();
-            s->in_flight--;
-            s->stats.failed++;
-        }
-        sl.reqs.clear();
-        sl.busy = false;
-        s->cv_done.notify_all();
+    if (!ok_launch) hipStreamSynchronize(sl.stream);  // drained before the slot is reused
+    (void)s;
+    return ok_launch;
+}
+
+// Fail a batch whose launch did not go through.  Called with the lock held.
+void fail_batch(kx_server *s, Slot &sl)
+{
+    for (Req *q : sl.reqs) {
+        q->state = KX_REQ_FAILED;
+        q->t_done = now_s();
+        s->in_flight--;
+        s->stats.failed++;
     }
+    sl.reqs.clear();
+    sl.busy = false;
+    s->cv_done.notify_all();
 }
 
 void scheduler(kx_server *s)
@@ -348,8 +382,27 @@ void scheduler(kx_server *s)
                         rest.push_back(q);
                 }
                 s->admitted.swap(rest);
-                launch_batch(s, sl, batch);
-                if (sl.busy) any_busy = true;
+                begin_batch(s, sl, batch);
+                any_busy = true;
+                if (s->simulate) continue;
+                // resident mechanisms are never removed, so the record stays
+                // valid (map nodes do not move); the slot's graphs are read and
+                // filed under the lock only
+                const ServedMech &sm = s->mechs.at(m);
+                int ops = 0;
+                for (Req *q : batch) ops |= q->r.ops;
+                const GraphKey key{m->uid, prec, ops};
+                auto git = sl.graphs.find(key);
+                hipGraphExec_t graph = git == sl.graphs.end() ? nullptr : git->second;
+                lk.unlock();
+                bool used_graph = false;
+                hipGraphExec_t new_graph = nullptr;
+                const bool launched = enqueue_batch(s, sl, sm, graph, &new_graph, &used_graph);
+                lk.lock();
+                if (new_graph && !sl.graphs.emplace(key, new_graph).second)
+                    hipGraphExecDestroy(new_graph);
+                if (used_graph) s->stats.graph_launches++;
+                if (!launched) fail_batch(s, sl);
             }
         }
         // Nothing running and nothing launchable: requests still queued wait for
@@ -370,6 +423,8 @@ kx_server_stats snapshot(kx_server *s)
     st.in_flight = s->in_flight;
     st.arena_in_use = (int64_t)s->arena.used();
     st.arena_capacity = (int64_t)s->arena.capacity();
+    st.resident_mechs = (int64_t)s->mechs.size();
+    st.resident_bytes = (int64_t)s->resident_bytes;
     return st;
 }
 
@@ -424,7 +479,7 @@ kx_status kx_server_create(int device, int64_t hbm_budget, int32_t max_slots, in
             okc = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
                   hipMalloc((void **)&sl.d_wl, sizeof(WorkList)) == hipSuccess &&
-                  hipMalloc((void **)&sl.d_counter, 2 * sizeof(int)) == hipSuccess &&
+                  hipMalloc((void **)&sl.d_counter, kBatchCounters * sizeof(int)) == hipSuccess &&
                   hipHostMalloc((void **)&sl.h_wl, sizeof(WorkList), hipHostMallocDefault) ==
                       hipSuccess;
         }
@@ -489,6 +544,67 @@ kx_status kx_server_destroy(kx_server *s)
     return ok();
 }
 
+kx_status kx_server_add_mech(kx_server *s, const kx_mech *m)
+{
+    if (!s || !m) return fail(KX_EINVAL, "kx_server_add_mech: NULL argument");
+    if (!s->simulate && (!m->blob || m->device != s->device))
+        return fail(KX_EINVAL, "kx_server_add_mech: mechanism has no tables on the server's device");
+    if (m->dev.nq > 0)
+        return fail(KX_EUNSUPPORTED, "kx_server_add_mech: mechanisms with QSS species are not served");
+    std::lock_guard<std::mutex> add_lk(s->add_mu);
+    const size_t bytes = round256((size_t)m->bytes);
+    size_t off = 0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) return fail(KX_EINVAL, "kx_server_add_mech: server is shutting down");
+        if (s->mechs.count(m)) return ok();
+        if (!s->arena.alloc(bytes, &off))
+            return fail(KX_ENOMEM, "kx_server_add_mech: the mechanism's tables (" +
+                                       std::to_string(bytes) + " bytes) do not fit in the "
+                                       "server's free HBM budget");
+    }
+    ServedMech sm;
+    sm.off = off;
+    sm.bytes = bytes;
+    sm.dev = m->dev;
+    std::vector<std::pair<Slot *, std::pair<GraphKey, hipGraphExec_t>>> graphs;
+    kx_status st = KX_OK;
+    if (!s->simulate) {
+        int prev = 0;
+        hipGetDevice(&prev);
+        hipSetDevice(s->device);
+        char *dst = s->arena_base + off;
+        hipError_t e = hipMemcpy(dst, m->blob, (size_t)m->bytes, hipMemcpyDeviceToDevice);
+        if (e != hipSuccess) st = hip_fail(e, "kx_server_add_mech: table copy");
+        if (st == KX_OK && !rebase_tables(m, dst, &sm.dev))
+            st = fail(KX_EINVAL, "kx_server_add_mech: internal error: table pointers not moved");
+        // every (stream, precision, ops) graph of this mechanism, captured now
+        hipStream_t cap = nullptr;
+        if (st == KX_OK && (e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess)
+            st = hip_fail(e, "kx_server_add_mech: hipStreamCreate");
+        for (Slot &sl : s->slots)
+            for (int prec : {(int)KX_FP64, (int)KX_MIXED})
+                for (int ops : {(int)KX_OP_RATES, (int)(KX_OP_RATES | KX_OP_TRANSPORT)}) {
+                    if (st != KX_OK) break;
+                    hipGraphExec_t ex = nullptr;
+                    st = build_graph(sm.dev, sl, prec, ops, cap, &ex);
+                    if (st == KX_OK) graphs.push_back({&sl, {GraphKey{m->uid, prec, ops}, ex}});
+                }
+        if (cap) hipStreamDestroy(cap);
+        hipSetDevice(prev);
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (st != KX_OK) {
+        for (auto &g : graphs) hipGraphExecDestroy(g.second.second);
+        s->arena.release(off, bytes);
+        return st;
+    }
+    for (auto &g : graphs) g.first->graphs.emplace(g.second.first, g.second.second);
+    s->mechs.emplace(m, sm);
+    s->resident_bytes += bytes;
+    return ok();
+}
+
 kx_status kx_submit(kx_server *s, const kx_request *r, kx_ticket *ticket)
 {
     if (!s || !r || !ticket) return fail(KX_EINVAL, "kx_submit: NULL argument");
@@ -505,8 +621,6 @@ kx_status kx_submit(kx_server *s, const kx_request *r, kx_ticket *ticket)
     if (r->mech->dev.nq > 0)
         return fail(KX_EUNSUPPORTED, "kx_submit: mechanisms with QSS species are not served");
     const size_t bytes = r->n > 0 ? footprint(*r, r->mech->n_species) : 0;
-    if (bytes > s->arena.capacity())
-        return fail(KX_ENOMEM, "kx_submit: request outputs exceed the server's HBM budget");
     Req *q = new Req;
     q->r = *r;
     q->bytes = bytes;
@@ -516,6 +630,16 @@ kx_status kx_submit(kx_server *s, const kx_request *r, kx_ticket *ticket)
         if (s->stop) {
             delete q;
             return fail(KX_EINVAL, "kx_submit: server is shutting down");
+        }
+        if (!s->mechs.count(r->mech)) {
+            delete q;
+            return fail(KX_EINVAL, "kx_submit: mechanism is not resident on this server "
+                                   "(kx_server_add_mech)");
+        }
+        if (bytes > s->arena.capacity() - s->resident_bytes) {
+            delete q;
+            return fail(KX_ENOMEM, "kx_submit: request outputs exceed the server's HBM budget "
+                                   "left after its resident mechanisms");
         }
         q->id = s->next_id++;
         s->reqs[q->id] = q;

@@ -273,7 +273,7 @@ REQ_STATES = {0: "queued", 1: "admitted", 2: "running", 3: "done", 4: "cancelled
 class _Request(C.Structure):
     _fields_ = [("mech", C.c_void_p), ("ops", C.c_int32), ("precision", C.c_int32),
                 ("n", C.c_int64), ("T", C.c_void_p), ("p", C.c_void_p), ("Y", C.c_void_p),
-                ("arrival_s", C.c_double)]
+                ("arrival_s", C.c_double), ("inputs_ready", C.c_void_p)]
 
 
 class _Result(C.Structure):
@@ -286,7 +286,8 @@ class _Result(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("submitted", "completed", "cancelled", "failed",
                                          "queued", "in_flight", "batches", "graph_launches",
-                                         "arena_in_use", "arena_capacity")]
+                                         "arena_in_use", "arena_capacity",
+                                         "resident_mechs", "resident_bytes")]
 
 
 def _serve_lib():
@@ -297,6 +298,7 @@ def _serve_lib():
         L.kx_server_clock.restype = C.c_double
         L.kx_server_create.argtypes = [C.c_int, i64, i32, i32, C.POINTER(vp)]
         L.kx_server_destroy.argtypes = [vp]
+        L.kx_server_add_mech.argtypes = [vp, vp]
         L.kx_submit.argtypes = [vp, C.POINTER(_Request), C.POINTER(i64)]
         L.kx_poll.argtypes = [vp, i64, C.POINTER(_Result)]
         L.kx_wait.argtypes = [vp, i64, C.c_double, C.POINTER(_Result)]
@@ -305,7 +307,7 @@ def _serve_lib():
         L.kx_release.argtypes = [vp, i64]
         L.kx_server_stats_get.argtypes = [vp, C.POINTER(_Stats)]
         for name in ("kx_mech_create_host", "kx_server_create", "kx_server_destroy",
-                     "kx_submit", "kx_poll", "kx_wait", "kx_cancel", "kx_result_copy",
+                     "kx_server_add_mech", "kx_submit", "kx_poll", "kx_wait", "kx_cancel", "kx_result_copy",
                      "kx_release", "kx_server_stats_get"):
             getattr(L, name).restype = C.c_int32
         L._serve_ready = True
@@ -355,11 +357,24 @@ class Server:
         self.simulate = simulate
         self._inputs = {}   # ticket -> (mech, tensors) kept alive until release
         self._meta = {}
+        self._resident = {}  # handle value -> mechanism (kept alive with the server)
+
+    def add_mech(self, mech: Mechanism) -> None:
+        """Make a mechanism resident (kx_server_add_mech): its tables are copied
+        into the server's HBM budget and its launch graphs captured."""
+        if mech.handle.value in self._resident:
+            return
+        check(_serve_lib().kx_server_add_mech(self.handle, mech.handle))
+        self._resident[mech.handle.value] = mech
 
     def submit(self, mech: Mechanism, T=None, p=None, Y=None, n: int | None = None,
                transport: bool = False, precision: str = "fp64",
-               arrival: float | None = None) -> int:
+               arrival: float | None = None, inputs_ready=None) -> int:
+        """Queue a request.  A mechanism not yet resident is added first
+        (add_mech).  inputs_ready: a torch.cuda.Event recorded after the work
+        that writes T, p, Y (None: they are complete now)."""
         L = _serve_lib()
+        self.add_mech(mech)
         r = _Request()
         r.mech = mech.handle.value
         r.ops = KX_OP_RATES | (KX_OP_TRANSPORT if transport else 0)
@@ -371,6 +386,7 @@ class Server:
             r.Y = _dev_tensor(Y, self.device, (mech.n_species, n), "Y").value
         r.n = int(n)
         r.arrival_s = -1.0 if arrival is None else float(arrival)
+        r.inputs_ready = inputs_ready.cuda_event if inputs_ready is not None else None
         t = C.c_int64()
         check(L.kx_submit(self.handle, C.byref(r), C.byref(t)))
         self._inputs[t.value] = (mech, T, p, Y)
@@ -446,6 +462,7 @@ class Server:
             check(_serve_lib().kx_server_destroy(self.handle))
             self.handle = None
             self._inputs.clear()
+            self._resident.clear()
 
     def __del__(self):
         try:

@@ -62,6 +62,11 @@ def _footprint(ns, n, transport):
     return (n * 8 * d + 255) // 256 * 256
 
 
+def _resident(*dms):
+    """Arena bytes the resident tables of these mechanisms take."""
+    return sum((dm.device_bytes + 255) // 256 * 256 for dm in dms)
+
+
 def test_served_equals_direct_mixed_batches(kx, mechs):
     """24 requests over two mechanisms, both precisions, both op sets and
     ragged sizes are queued behind a finished request that holds the arena;
@@ -85,8 +90,12 @@ def test_served_equals_direct_mixed_batches(kx, mechs):
     budget = max(total, _footprint(ns53, n_blk, False))
     assert budget - _footprint(ns53, n_blk, False) < first
     (Tb, pb, Yb), _ = _inputs(ns53, n_blk, 99)
-    srv = kx.Server(0, hbm_budget=budget, max_slots=64)
+    res = _resident(mechs["syn9"][0], mechs["syn53"][0])
+    srv = kx.Server(0, hbm_budget=budget + res, max_slots=64)
     try:
+        srv.add_mech(mechs["syn9"][0])
+        srv.add_mech(mechs["syn53"][0])
+        assert srv.stats()["resident_bytes"] == res
         blocker = srv.submit(mechs["syn53"][0], Tb, pb, Yb)
         assert srv.wait(blocker, WAIT_S)["state"] == "done"
         reqs = [(srv.submit(mechs[c[0]][0], *c[4:], transport=c[2], precision=c[3]), c)
@@ -107,7 +116,7 @@ def test_served_equals_direct_mixed_batches(kx, mechs):
         assert st["completed"] == len(cases) + 1 and st["failed"] == 0
         # one batch per (mechanism, precision) group after the blocker
         assert st["batches"] <= 1 + 4
-        assert st["arena_in_use"] == 0
+        assert st["arena_in_use"] == res
     finally:
         srv.close()
 
@@ -138,7 +147,7 @@ def test_budget_pressure_and_cancel(kx, mechs):
     dm, mech = mechs["syn53"]
     ns, n = mech["n_species"], 30000
     fp = (n * 8 * ns + 255) // 256 * 256
-    srv = kx.Server(0, hbm_budget=2 * fp, max_slots=16)
+    srv = kx.Server(0, hbm_budget=2 * fp + _resident(dm), max_slots=16)
     try:
         (Td, pd, Yd), _ = _inputs(ns, n, 21)
         ref = _direct(kx, dm, Td, pd, Yd, False, "fp64")[0]
@@ -160,7 +169,8 @@ def test_budget_pressure_and_cancel(kx, mechs):
         srv.release(d)
         srv.release(c)
         st = srv.stats()
-        assert st["cancelled"] == 1 and st["completed"] == 3 and st["arena_in_use"] == 0
+        assert st["cancelled"] == 1 and st["completed"] == 3
+        assert st["arena_in_use"] == _resident(dm)
     finally:
         srv.close()
 
@@ -258,3 +268,35 @@ def test_served_large_mechanisms_equal_direct(kx, mech100, mech200):
         srv.close()
         for dm, _ in ms.values():
             dm.close()
+
+
+def test_inputs_ready_event(kx, mechs):
+    """A request whose inputs are still being written on another stream when it
+    is submitted: the server waits for the event recorded after that work, and
+    the outputs equal the direct call on the finished inputs."""
+    dm, mech = mechs["syn53"]
+    ns, n = mech["n_species"], 200_000
+    (Td, pd, Yd), _ = _inputs(ns, n, 77)
+    ref = _direct(kx, dm, Td, pd, Yd, True, "fp64")
+    T2, p2, Y2 = torch.empty_like(Td), torch.empty_like(pd), torch.empty_like(Yd)
+    side = torch.cuda.Stream()
+    ready = torch.cuda.Event()
+    srv = kx.Server(0, hbm_budget=1 << 30, max_slots=8)
+    try:
+        srv.add_mech(dm)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            # slow enough that the server would read unfinished inputs
+            for _ in range(20):
+                Y2.copy_(Yd)
+            T2.copy_(Td)
+            p2.copy_(pd)
+            ready.record(side)
+        t = srv.submit(dm, T2, p2, Y2, transport=True, inputs_ready=ready)
+        assert srv.wait(t, WAIT_S)["state"] == "done"
+        got = srv.outputs(t)
+        for g, e in zip(got, ref):
+            assert torch.equal(g, e)
+        srv.release(t)
+    finally:
+        srv.close()

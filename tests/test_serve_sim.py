@@ -24,6 +24,11 @@ def footprint(ns, n, transport):
     return (n * 8 * d + 255) // 256 * 256
 
 
+def resident(*mechs):
+    """Arena bytes the resident tables of these mechanisms take."""
+    return sum((m.device_bytes + 255) // 256 * 256 for m in mechs)
+
+
 def test_all_complete_and_release(m53):
     s = kx.Server(hbm_budget=1 << 30, max_slots=8, simulate=True)
     ts = [s.submit(m53, n=100_000, transport=(i % 2 == 0)) for i in range(20)]
@@ -32,21 +37,21 @@ def test_all_complete_and_release(m53):
         s.release(t)
     st = s.stats()
     assert st["submitted"] == 20 and st["completed"] == 20 and st["in_flight"] == 0
-    assert st["arena_in_use"] == 0 and 1 <= st["batches"] <= 20
+    assert st["arena_in_use"] == resident(m53) and 1 <= st["batches"] <= 20
     s.close()
 
 
 def test_fifo_admission_under_memory_pressure(m53):
     n = 50_000
     fp = footprint(m53.n_species, n, False)
-    s = kx.Server(hbm_budget=2 * fp, max_slots=16, simulate=True)
+    s = kx.Server(hbm_budget=2 * fp + resident(m53), max_slots=16, simulate=True)
     ts = [s.submit(m53, n=n) for _ in range(6)]
     admits = []
     for t in ts:
         r = s.wait(t, 10.0)
         assert r["state"] == "done"
         admits.append(r["t_admit"])
-        assert s.stats()["arena_in_use"] <= 2 * fp
+        assert s.stats()["arena_in_use"] <= 2 * fp + resident(m53)
         s.release(t)
     assert admits == sorted(admits)
     s.close()
@@ -55,7 +60,7 @@ def test_fifo_admission_under_memory_pressure(m53):
 def test_blocked_queue_cancel_and_timeout(m53):
     n = 10_000
     fp = footprint(m53.n_species, n, True)
-    s = kx.Server(hbm_budget=fp, max_slots=4, simulate=True)
+    s = kx.Server(hbm_budget=fp + resident(m53), max_slots=4, simulate=True)
     a = s.submit(m53, n=n, transport=True)
     assert s.wait(a, 10.0)["state"] == "done"          # holds the whole arena
     b = s.submit(m53, n=n, transport=True)
@@ -80,14 +85,16 @@ def test_blocked_queue_cancel_and_timeout(m53):
     s.release(b)
     s.release(c)
     st = s.stats()
-    assert st["cancelled"] == 1 and st["completed"] == 2 and st["arena_in_use"] == 0
+    assert st["cancelled"] == 1 and st["completed"] == 2
+    assert st["arena_in_use"] == resident(m53)
     s.close()
 
 
 def test_strict_fifo_no_overtaking(m53):
     big, small = 40_000, 1_000
     fpb = footprint(m53.n_species, big, False)
-    s = kx.Server(hbm_budget=fpb + footprint(m53.n_species, small, False), max_slots=8,
+    s = kx.Server(hbm_budget=fpb + footprint(m53.n_species, small, False) + resident(m53),
+                  max_slots=8,
                   simulate=True)
     a = s.submit(m53, n=big)
     assert s.wait(a, 10.0)["state"] == "done"
@@ -125,8 +132,10 @@ def test_batches_are_homogeneous(m53, m9):
     one pass, and they run as one batch per (mechanism, precision) group
     (independent of how fast the submitting thread is)."""
     n_blk = 1 << 20
-    s = kx.Server(hbm_budget=footprint(m53.n_species, n_blk, False), max_slots=64,
-                  simulate=True)
+    s = kx.Server(hbm_budget=footprint(m53.n_species, n_blk, False) + resident(m53, m9),
+                  max_slots=64, simulate=True)
+    s.add_mech(m53)
+    s.add_mech(m9)
     blocker = s.submit(m53, n=n_blk)
     assert s.wait(blocker, 10.0)["state"] == "done"
     spec = [(m53 if i % 3 else m9, "fp64" if i % 2 else "mixed") for i in range(60)]
@@ -158,6 +167,7 @@ def test_zero_points_and_oversize(m53):
 def test_invalid_requests(m53):
     L = kx._serve_lib()
     s = kx.Server(hbm_budget=1 << 20, max_slots=4, simulate=True)
+    s.add_mech(m53)
     import ctypes as C
     t = C.c_int64()
 
@@ -186,7 +196,8 @@ def test_invalid_requests(m53):
 
 def test_destroy_cancels_queued(m53):
     n = 10_000
-    s = kx.Server(hbm_budget=footprint(m53.n_species, n, False), max_slots=4, simulate=True)
+    s = kx.Server(hbm_budget=footprint(m53.n_species, n, False) + resident(m53), max_slots=4,
+                  simulate=True)
     a = s.submit(m53, n=n)
     s.wait(a, 10.0)
     ts = [s.submit(m53, n=n) for _ in range(3)]
@@ -243,5 +254,41 @@ def test_concurrent_clients(m53, m9):
     assert not errors, errors
     st = s.stats()
     assert st["submitted"] == 120 and st["completed"] + st["cancelled"] == 120
-    assert st["arena_in_use"] == 0 and st["in_flight"] == 0
+    assert st["arena_in_use"] == resident(m53, m9) and st["in_flight"] == 0
+    s.close()
+
+
+def test_resident_mechanisms_charge_the_budget(m53, m9):
+    """kx_server_add_mech charges a mechanism's tables to the arena once; a
+    request must name a resident mechanism, and its outputs must fit in what
+    the resident tables leave of the budget."""
+    import ctypes as C
+    L = kx._serve_lib()
+    r53 = resident(m53)
+    n = 10_000
+    budget = r53 + footprint(m53.n_species, n, False)
+    s = kx.Server(hbm_budget=budget, max_slots=4, simulate=True)
+    st = s.stats()
+    assert st["resident_mechs"] == 0 and st["arena_in_use"] == 0
+    s.add_mech(m53)
+    s.add_mech(m53)                                   # a no-op the second time
+    st = s.stats()
+    assert st["resident_mechs"] == 1 and st["resident_bytes"] == r53
+    assert st["arena_in_use"] == r53
+    # a mechanism that is not resident is refused at submit
+    r = kx._Request()
+    r.mech, r.ops, r.precision, r.n, r.arrival_s = m9.handle.value, 1, 0, 10, -1.0
+    t = C.c_int64()
+    assert L.kx_submit(s.handle, C.byref(r), C.byref(t)) == kx.KX_EINVAL
+    # the largest request that fits beside the tables runs and, while it holds
+    # its outputs, leaves no room for another mechanism's tables
+    a = s.submit(m53, n=n)
+    assert s.wait(a, 10.0)["state"] == "done"
+    assert L.kx_server_add_mech(s.handle, m9.handle) == kx.KX_ENOMEM
+    s.release(a)
+    # one more point than fits beside the tables is refused at submit
+    with pytest.raises(kx.KxError) as ei:
+        s.submit(m53, n=n + 64)
+    assert ei.value.code == kx.KX_ENOMEM
+    assert s.stats()["arena_in_use"] == r53
     s.close()
