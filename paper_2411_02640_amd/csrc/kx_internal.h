@@ -21,6 +21,7 @@ constexpr int kMaxSpecies = 256;     // species per mechanism (4 per lane)
 constexpr int kMaxFitOrder = 8;
 constexpr int kWave = 64;
 constexpr int kMaxQss = 64;          // QSS species per mechanism (one wave of rows)
+constexpr int kChunkMax = 192;       // reactions per chunk of the gather lists, at most
 
 // Reaction flags.
 enum : uint8_t {

@@ -432,7 +432,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     // eight 32-bit LDS offsets (32 bytes per lane, so lane k reads it with a
     // pair of coalesced 16-byte loads).  The rates of progress of two points sit
     // side by side in LDS, so one offset addresses both.
-    const int chunk = std::max(kWave, std::min(192, (nr + kWave - 1) / kWave * kWave));
+    const int chunk = std::max(kWave, std::min(kChunkMax, (nr + kWave - 1) / kWave * kWave));
     const int nchunks = std::max(1, (nr + chunk - 1) / chunk);
     // species per lane of the species phases: 1, 2 or 4 (the kernels are
     // instantiated for these), so lists are laid out for 64 * gpass lanes

@@ -8,8 +8,10 @@
 // independent work that the VALU, not latency, sets the rate), on a grid that
 // fills every SIMD.  A loop that applies only the bookkeeping add is timed
 // too, and the price of an operation is
-//     2 * (t_op - t_add) / (t_fma - t_add)   flops,
-// i.e. the issue time of the operation in FP64 FMAs (2 flops each).
+//     2 * (t_op - t_add) / t_fma               flops,
+// i.e. the issue time of the operation in FP64 FMAs (2 flops each); an FP64
+// add issues like an FMA, so the add probe removes the bookkeeping and the FMA
+// probe (one FMA per step) is the unit.
 //
 // This file is a measuring tool: it is built into its own library, which the
 // benchmark loads; the chemistry library does not contain it.
@@ -33,7 +35,7 @@ enum Op {
     kOpExpMixed = 6, // v = e^v - 2 with the FP64 argument reduced and e^r in FP32
     kOpExp32 = 7,    // FP32: v = __expf(v) - 2
     kOpRcp32 = 8,    // FP32: v = 1 / v + 1/2 (correctly rounded division)
-    kOpFma32 = 9,    // FP32: v = v * c + d
+    kOpFma32 = 9,    // FP32: v = v * c + d (also the bookkeeping of the FP32 probes)
 };
 
 __device__ __forceinline__ double exp_mixed_probe(double x)

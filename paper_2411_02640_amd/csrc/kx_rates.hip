@@ -174,12 +174,19 @@ __device__ __forceinline__ double third_body(const MechDev &m, const DevAux &ax,
     return X;
 }
 
-// Rate of progress R_i = c_i k_f A' (B' - B'') of one reaction (lane-private).
-template <bool MIXED>
-__device__ __forceinline__ double rate_of_progress(const MechDev &m, const RxnWords &w,
-                                                   const char *__restrict__ pb, double Ti,
-                                                   double lnT, double invT, double Mconc,
-                                                   double lnp)
+// The per-point values phase 2 needs.
+struct PtVals {
+    double T, lnT, invT, M, lnp;
+};
+
+// Rates of progress R_i = c_i k_f A' (B' - B'') of one reaction at the NPT
+// points of this lane (lane-private).  The record is decoded once; the LDS
+// reads of every point are issued before the first exponential, and the
+// points' exponentials are independent, so their chains interleave.
+template <bool MIXED, int NPT>
+__device__ __forceinline__ void rates_of_progress(const MechDev &m, const RxnWords &w,
+                                                  const char *const (&pb)[NPT],
+                                                  const PtVals (&q)[NPT], double (&R)[NPT])
 {
     const double lnA = as_double(w.w0.x, w.w0.y);
     const double beta = as_double(w.w0.z, w.w0.w);
@@ -188,84 +195,123 @@ __device__ __forceinline__ double rate_of_progress(const MechDev &m, const RxnWo
     const unsigned type = w.w2.w & 0xFFu;
     const unsigned flags = (w.w2.w >> 8) & 0xFFu;
     const unsigned aux = w.w2.w >> 16;
+    const unsigned o0 = w.w2.x & 0xFFFFu, o1 = w.w2.x >> 16;
+    const unsigned o3 = w.w2.y >> 16, o4 = w.w2.z & 0xFFFFu;
 
     // exponent of k_f (eq:k_f); k_f = A without an exponential when beta = E_R = 0
     // (such reactions are sorted together, so the branch is mostly wave-uniform),
     // or interpolated in ln p for a pressure-table reaction
     const bool kconst = (flags & kFlagKfConst) != 0;
-    double xf = kconst ? lnA : fma(beta, lnT, fma(-ER, invT, lnA));
+    double xf[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j)
+        xf[j] = kconst ? lnA : fma(beta, q[j].lnT, fma(-ER, q[j].invT, lnA));
     if (type == KX_RXN_PLOG) {
         const DevAux &ax = m.aux[aux];
-        xf = plog_exponent(m.plog + ax.plog_off, ax.plog_cnt, lnT, invT, lnp);
+#pragma unroll
+        for (int j = 0; j < NPT; ++j)
+            xf[j] = plog_exponent(m.plog + ax.plog_off, ax.plog_cnt, q[j].lnT, q[j].invT,
+                                  q[j].lnp);
     }
-    // the LDS reads go before the exponential so that their latency hides behind it
-    const Pair r0 = load_pair(pb, w.w2.x & 0xFFFFu);
-    const Pair r1 = load_pair(pb, w.w2.x >> 16);
-    const double bp0 = load_b(pb, w.w2.y >> 16), bp1 = load_b(pb, w.w2.z & 0xFFFFu);
-    double kf = A;
-    if (!kconst) kf = MIXED ? exp_mixed(xf) : kexp(xf);
-    double Ap = r0.a * r1.a;
-    double Bp = r0.b * r1.b;
-    double Bpp = bp0 * bp1;
+    // the LDS reads go before the exponentials so that their latency hides behind them
+    Pair r0[NPT], r1[NPT];
+    double bp0[NPT], bp1[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        r0[j] = load_pair(pb[j], o0);
+        r1[j] = load_pair(pb[j], o1);
+        bp0[j] = load_b(pb[j], o3);
+        bp1[j] = load_b(pb[j], o4);
+    }
+    double kf[NPT], Ap[NPT], Bp[NPT], Bpp[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        kf[j] = A;
+        if (!kconst) kf[j] = MIXED ? exp_mixed(xf[j]) : kexp(xf[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        Ap[j] = r0[j].a * r1[j].a;
+        Bp[j] = r0[j].b * r1[j].b;
+        Bpp[j] = bp0[j] * bp1[j];
+    }
     // third molecule slots: skipped by the whole wave when none of its
     // reactions has three molecules on a side (the dummy species gives 1)
     const unsigned o2 = w.w2.y & 0xFFFFu, o5 = w.w2.z >> 16;
     const unsigned dummy = 16u * (unsigned)m.ns;
     if (__builtin_amdgcn_ballot_w64(o2 != dummy || o5 != dummy) != 0) {
-        const Pair r2 = load_pair(pb, o2);
-        Ap *= r2.a;
-        Bp *= r2.b;
-        Bpp *= load_b(pb, o5);
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const Pair r2 = load_pair(pb[j], o2);
+            Ap[j] *= r2.a;
+            Bp[j] *= r2.b;
+            Bpp[j] *= load_b(pb[j], o5);
+        }
     }
     if (flags & kFlagOrders) {
         // explicit forward orders (irreversible): prod_k C_k^o_k, C_k = a_k b_k
         const DevAux &ax = m.aux[aux];
-        double s = 0.0;
-        bool zero = false;
 #pragma unroll
-        for (int e = 0; e < kMaxOrd; ++e) {
-            const double o = ax.oval[e];
-            if (o != 0.0) {
-                const Pair q = load_pair(pb, ax.ooff[e]);
-                const double C = q.a * q.b;
-                zero = zero || !(C > 0.0);
-                s = fma(o, kln(fmax(C, DBL_MIN)), s);
-            }
-        }
-        Ap = zero ? 0.0 : kexp(s);
-        Bp = 1.0;
-        Bpp = 0.0;
-    }
-    double c = 1.0;
-    if (type != KX_RXN_ELEMENTARY && type != KX_RXN_PLOG) {
-        const DevAux &ax = m.aux[aux];
-        const double X = third_body(m, ax, pb, Mconc);
-        c = X;
-        if (type != KX_RXN_THREEBODY) {
-            // P_r = k_0 [X] / k_inf = e0 [X] with e0 = exp(x_0 - x_inf) (no division)
-            const double d0 = fma(ax.beta0, lnT, fma(-ax.ER0, invT, ax.lnA0)) - xf;
-            const double e0 = MIXED ? exp_mixed(d0) : kexp(d0);
-            const double Pr = e0 * X;
-            double F = 1.0;
-            if (type == KX_RXN_TROE || type == KX_RXN_SRI) {
-                const bool sri = type == KX_RXN_SRI;
-                if (MIXED) {
-                    F = (double)blend_F32(ax, sri, (float)Ti, (float)lnT, (float)invT,
-                                          log10_wide(Pr));
-                } else {
-                    // ln max(P_r, DBL_MIN) without forming the logarithm of P_r
-                    const double lnPr = fmax(d0 + kln(fmax(X, DBL_MIN)), -708.39641853226410622);
-                    F = blend_F64(ax, sri, Ti, lnT, invT, lnPr);
+        for (int j = 0; j < NPT; ++j) {
+            double s = 0.0;
+            bool zero = false;
+#pragma unroll
+            for (int e = 0; e < kMaxOrd; ++e) {
+                const double o = ax.oval[e];
+                if (o != 0.0) {
+                    const Pair qq = load_pair(pb[j], ax.ooff[e]);
+                    const double C = qq.a * qq.b;
+                    zero = zero || !(C > 0.0);
+                    s = fma(o, kln(fmax(C, DBL_MIN)), s);
                 }
             }
-            // eq:c_i: P_r/(1+P_r) F; chemically activated: F/(1+P_r) with k_0 =
-            // e0 k_inf in r_i, i.e. c k_inf = e0 F/(1+P_r) k_inf
-            const double g = krcp(1.0 + Pr) * F;
-            c = (flags & kFlagChemAct) ? e0 * g : Pr * g;
+            Ap[j] = zero ? 0.0 : kexp(s);
+            Bp[j] = 1.0;
+            Bpp[j] = 0.0;
+        }
+    }
+    double c[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) c[j] = 1.0;
+    if (type != KX_RXN_ELEMENTARY && type != KX_RXN_PLOG) {
+        const DevAux &ax = m.aux[aux];
+        double X[NPT];
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            X[j] = third_body(m, ax, pb[j], q[j].M);
+            c[j] = X[j];
+        }
+        if (type != KX_RXN_THREEBODY) {
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                // P_r = k_0 [X] / k_inf = e0 [X] with e0 = exp(x_0 - x_inf) (no division)
+                const double d0 =
+                    fma(ax.beta0, q[j].lnT, fma(-ax.ER0, q[j].invT, ax.lnA0)) - xf[j];
+                const double e0 = MIXED ? exp_mixed(d0) : kexp(d0);
+                const double Pr = e0 * X[j];
+                double F = 1.0;
+                if (type == KX_RXN_TROE || type == KX_RXN_SRI) {
+                    const bool sri = type == KX_RXN_SRI;
+                    if (MIXED) {
+                        F = (double)blend_F32(ax, sri, (float)q[j].T, (float)q[j].lnT,
+                                              (float)q[j].invT, log10_wide(Pr));
+                    } else {
+                        // ln max(P_r, DBL_MIN) without forming the logarithm of P_r
+                        const double lnPr =
+                            fmax(d0 + kln(fmax(X[j], DBL_MIN)), -708.39641853226410622);
+                        F = blend_F64(ax, sri, q[j].T, q[j].lnT, q[j].invT, lnPr);
+                    }
+                }
+                // eq:c_i: P_r/(1+P_r) F; chemically activated: F/(1+P_r) with k_0 =
+                // e0 k_inf in r_i, i.e. c k_inf = e0 F/(1+P_r) k_inf
+                const double g = krcp(1.0 + Pr) * F;
+                c[j] = (flags & kFlagChemAct) ? e0 * g : Pr * g;
+            }
         }
     }
     const double rev = (flags & kFlagReversible) ? 1.0 : 0.0;
-    return c * kf * Ap * fma(-rev, Bpp, Bp);
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) R[j] = c[j] * kf[j] * Ap[j] * fma(-rev, Bpp[j], Bp[j]);
 }
 
 // Gibbs energy g = G/RT of one species at one temperature (eq:Ck with the
@@ -294,6 +340,18 @@ __device__ __forceinline__ void accumulate(double &acc, double &cmp, double t)
 // of more than 128 species, whose Y tile would otherwise crowd the LDS.
 __host__ __device__ constexpr int rates_tile_points_for(int spl) { return spl == 4 ? 2 : 8; }
 
+// Points per step: four for mechanisms of up to 128 species (each lane of the
+// reaction phase evaluates its reaction at two points, so a reaction record is
+// read and decoded once per two rates of progress), two above (the per-point
+// LDS arrays of a 4-point step would crowd the LDS).
+__host__ __device__ constexpr int rates_step_points_for(int spl) { return spl == 4 ? 2 : 4; }
+
+// Byte distance between the two halves of the rate-of-progress array of a
+// 4-point step: slot s of the chunk holds R at points 0 and 1 at 16 s and at
+// points 2 and 3 at kSqHalf + 16 s, so one gather offset addresses both halves
+// (the second through the LDS instruction's immediate offset).
+constexpr int kSqHalf = 16 * (kChunkMax + 1);
+
 // Per-point constants of a tile, computed once per point (lane = point).
 struct PointConst {
     double T, lnT, invT, M;  // temperature, ln T, 1/T, [M] = p / RT
@@ -301,22 +359,23 @@ struct PointConst {
     double lnp, pad;         // ln p (pressure-table reactions)
 };
 
-// LDS layout of one workgroup (one wave):
-//   sq    [chunk + 1][2]    rates of progress of the current chunk for the two
-//                           points of a step, side by side (slot `chunk` is zero
-//                           and absorbs the gather padding); at byte 0 so that
-//                           the gather offsets are LDS addresses
-//   pairs [2][ns + 1] {a, b} per point (entry ns is the dummy species, {1, 1})
+// LDS layout of one workgroup (one wave), PS = points per step:
+//   sq    rates of progress of the current chunk for the points of a step:
+//         PS = 2: [chunk + 1][2], the two points side by side;
+//         PS = 4: two such arrays kSqHalf bytes apart (points 0, 1 and 2, 3);
+//         slot `chunk` is zero and absorbs the gather padding; at byte 0 so that
+//         the gather offsets are LDS addresses
+//   pairs [PS][ns + 1] {a, b} per point (entry ns is the dummy species, {1, 1})
 //   pc    [tp]              PointConst of the tile's points
 //   Yt    [ns][tp + 1]      Y tile in, wdot tile out (coalesced row loads/stores)
-// One tile of `npts` (<= tp, tp even) points starting at point i0 of arrays
-// whose species rows have stride ld, two points per step:
-//   phase 1 -- lane = species, both points;
-//   phase 2 -- lane = (reaction, point): lanes 2r and 2r+1 take reaction r for
-//              the two points, so a group of 32 falloff reactions fills a whole
-//              64-lane iteration;
-//   phase 3 -- lane = species, both points: one 16-byte LDS read per list entry
-//              returns the rate of progress of the reaction at both points.
+// One tile of `npts` (<= tp) points starting at point i0 of arrays whose
+// species rows have stride ld, PS points per step:
+//   phase 1 -- lane = species, every point of the step;
+//   phase 2 -- lane = (reaction, point): lanes 2r and 2r+1 take reaction r, lane
+//              2r + j for the points j (and j + 2 when PS = 4) of the step, so a
+//              group of 32 falloff reactions fills a whole 64-lane iteration;
+//   phase 3 -- lane = species: one 16-byte LDS read per list entry (two when
+//              PS = 4) returns the rate of progress of the reaction at the points.
 // A 16-byte LDS read at a byte address (the gather lists hold addresses
 // relative to the dynamic LDS, which starts at 0 when the kernel has no static
 // LDS; rates_tile<..., true> is only entered after checking that).
@@ -342,13 +401,15 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
 {
     extern __shared__ double lds[];
     constexpr int TP = rates_tile_points_for(SPL);  // == tp
+    constexpr int PS = rates_step_points_for(SPL);  // points per step
+    constexpr int NPT = PS / 2;                     // points per lane in phase 2
     constexpr int NGW = kWave / TP;                 // species groups of the W-bar pass
     const int ns = m.ns;
     const int ys = TP + 1;
     const int lane = threadIdx.x;
     double *sq = lds;
-    double *pairs = sq + 2 * (m.chunk + 1);
-    PointConst *pc = reinterpret_cast<PointConst *>(pairs + 4 * (ns + 1));
+    double *pairs = sq + (PS == 4 ? 2 * kSqHalf / 8 : 2 * (m.chunk + 1));
+    PointConst *pc = reinterpret_cast<PointConst *>(pairs + 2 * PS * (ns + 1));
     double *Yt = reinterpret_cast<double *>(pc + TP);
     const char *qb = reinterpret_cast<const char *>(sq);
     (void)tp;
@@ -412,27 +473,35 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
         pc[lane] = q;
     }
     __syncthreads();
-    if (lane < 2) {
+    if (lane < PS) {
         pairs[2 * ns + 2 * (ns + 1) * lane] = 1.0;
         pairs[2 * ns + 2 * (ns + 1) * lane + 1] = 1.0;
+    }
+    if (lane < 2) {
         sq[2 * m.chunk + lane] = 0.0;
+        if (PS == 4) sq[kSqHalf / 8 + 2 * m.chunk + lane] = 0.0;
     }
 
-    const int jl = lane & 1;   // point of this lane in phase 2
+    const int jl = lane & 1;   // point of this lane in phase 2 (and jl + 2)
     const int rl = lane >> 1;  // reaction slot of this lane in phase 2
-    const char *pbl = reinterpret_cast<const char *>(pairs + 2 * (ns + 1) * jl);
+    const char *pbl[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j)
+        pbl[j] = reinterpret_cast<const char *>(pairs + 2 * (ns + 1) * (jl + 2 * j));
     const int gw = kWave * m.gpass;
-    for (int pl = 0; pl < npts; pl += 2) {
-        // ---- phase 1: species (both points per lane)
-        const PointConst p2[2] = {pc[pl], pc[pl + 1]};
+    for (int pl = 0; pl < npts; pl += PS) {
+        // ---- phase 1: species (every point of the step per lane)
+        PointConst ps[PS];
+#pragma unroll
+        for (int j = 0; j < PS; ++j) ps[j] = pc[pl + j];
 #pragma unroll
         for (int s = 0; s < SPL; ++s) {
             const int k = lane + kWave * s;
             if (k < ns) {
                 const DevSpecies &S = m.sp[k];
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const PointConst &q = p2[j];
+                for (int j = 0; j < PS; ++j) {
+                    const PointConst &q = ps[j];
                     const double ak = q.P0 * kexp(-gibbs(S, q.T, q.lnT, q.invT));
                     const double Ck = Yt[k * ys + pl + j] * S.inv_W * q.cf;
                     double *pr = pairs + 2 * (ns + 1) * j + 2 * k;
@@ -442,14 +511,20 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
             }
         }
         wave_sync();
-        // the point of this lane in phase 2
-        const PointConst &ql = pc[pl + jl];
-        const double Tl = ql.T, lnTl = ql.lnT, invTl = ql.invT, Ml = ql.M, lnpl = ql.lnp;
+        // the points of this lane in phase 2
+        PtVals qv[NPT];
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const PointConst &q = pc[pl + jl + 2 * j];  // LDS (a lane-dependent index)
+            qv[j] = PtVals{q.T, q.lnT, q.invT, q.M, q.lnp};
+        }
 
         // ---- phases 2 and 3, one chunk of reactions at a time
-        double acc[SPL][2], cmp[SPL][2];
+        double acc[SPL][PS], cmp[SPL][PS];
 #pragma unroll
-        for (int s = 0; s < SPL; ++s) acc[s][0] = acc[s][1] = cmp[s][0] = cmp[s][1] = 0.0;
+        for (int s = 0; s < SPL; ++s)
+#pragma unroll
+            for (int j = 0; j < PS; ++j) acc[s][j] = cmp[s][j] = 0.0;
         for (int c = 0; c < m.nchunks; ++c) {
             const int base = c * m.chunk;
             const int cnt = min(m.chunk, m.nr - base);
@@ -471,7 +546,10 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
                     w.w1 = rsrc[3 * rn + 1];
                     w.w2 = rsrc[3 * rn + 2];
                 }
-                sq[2 * r + jl] = rate_of_progress<MIXED>(m, cur, pbl, Tl, lnTl, invTl, Ml, lnpl);
+                double R[NPT];
+                rates_of_progress<MIXED, NPT>(m, cur, pbl, qv, R);
+                sq[2 * r + jl] = R[0];
+                if (PS == 4) sq[kSqHalf / 8 + 2 * r + jl] = R[NPT - 1];
             }
             wave_sync();
             const int npos = m.gpos[c], ngrp = npos + m.gneg[c];
@@ -479,31 +557,38 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
 #pragma unroll
             for (int s = 0; s < SPL; ++s) {
                 const uint4 *g = ge + 2 * kWave * s;
-                // one group: eight entries summed plainly (the mixed path
-                // compensates the running sum across groups); all eight reads
-                // are issued before the first sum (left to itself the scheduler
-                // waits for each read in turn)
+                // one group: eight entries summed plainly per point (the mixed
+                // path compensates the running sum across groups); all reads of
+                // a group (or of each half of it, for four points) are issued
+                // before the first sum (left to itself the scheduler waits for
+                // each read in turn)
                 auto group = [&](const uint4 &v0, const uint4 &v1, int it) {
                     const unsigned off[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-                    double2 q2[8];
+                    double gs[PS];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        q2[u] = DIRECT ? lds_read16(off[u])
-                                       : *reinterpret_cast<const double2 *>(qb + off[u]);
-                    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // DS reads
-                    __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);  // VALU
-                    double g0 = q2[0].x, g1 = q2[0].y;
+                    for (int h = 0; h < PS / 2; ++h) {
+                        double2 q2[8];
 #pragma unroll
-                    for (int u = 1; u < 8; ++u) {
-                        g0 += q2[u].x;
-                        g1 += q2[u].y;
+                        for (int u = 0; u < 8; ++u)
+                            q2[u] = DIRECT ? lds_read16(off[u] + h * kSqHalf)
+                                           : *reinterpret_cast<const double2 *>(
+                                                 qb + off[u] + h * kSqHalf);
+                        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // DS reads
+                        __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);  // VALU
+                        double g0 = q2[0].x, g1 = q2[0].y;
+#pragma unroll
+                        for (int u = 1; u < 8; ++u) {
+                            g0 += q2[u].x;
+                            g1 += q2[u].y;
+                        }
+                        gs[2 * h] = g0;
+                        gs[2 * h + 1] = g1;
                     }
-                    if (it >= npos) {
-                        g0 = -g0;
-                        g1 = -g1;
+#pragma unroll
+                    for (int j = 0; j < PS; ++j) {
+                        const double t = it >= npos ? -gs[j] : gs[j];
+                        accumulate<MIXED>(acc[s][j], cmp[s][j], t);
                     }
-                    accumulate<MIXED>(acc[s][0], cmp[s][0], g0);
-                    accumulate<MIXED>(acc[s][1], cmp[s][1], g1);
                 };
                 // two groups per trip with alternating offset registers (the
                 // next group's offsets in flight, and no copies between trips)
@@ -527,12 +612,15 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
             }
             wave_sync();
         }
+        // the rates of progress were stored as points (0, 1) and (2, 3); the
+        // accumulators follow the same order
 #pragma unroll
         for (int s = 0; s < SPL; ++s) {
             const int k = lane + kWave * s;
             if (k < ns) {
-                Yt[k * ys + pl] = MIXED ? acc[s][0] + cmp[s][0] : acc[s][0];
-                Yt[k * ys + pl + 1] = MIXED ? acc[s][1] + cmp[s][1] : acc[s][1];
+#pragma unroll
+                for (int j = 0; j < PS; ++j)
+                    Yt[k * ys + pl + j] = MIXED ? acc[s][j] + cmp[s][j] : acc[s][j];
             }
         }
     }
@@ -555,8 +643,12 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nblk)
     return x * q + min(x, r) + b / kXcd;
 }
 
-template <bool MIXED, int SPL>
-__global__ __launch_bounds__(kWave, SPL == 1 ? 4 : (SPL == 2 ? 3 : 2)) void rates_kernel(MechDev m, int64_t n,
+// DIRECT: the gather lists' offsets are LDS addresses, which holds when the
+// kernel has no static LDS (its dynamic LDS then starts at address 0); the
+// host checks the kernel's static LDS size and launches the DIRECT = false
+// instance otherwise.
+template <bool MIXED, int SPL, bool DIRECT>
+__global__ __launch_bounds__(kWave, SPL == 1 ? 3 : 2) void rates_kernel(MechDev m, int64_t n,
                                                       const double *__restrict__ T,
                                                       const double *__restrict__ P,
                                                       const double *__restrict__ Y,
@@ -564,10 +656,7 @@ __global__ __launch_bounds__(kWave, SPL == 1 ? 4 : (SPL == 2 ? 3 : 2)) void rate
 {
     const int64_t i0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * tp;
     const int np = (int)min((int64_t)tp, n - i0);
-    if (lds_base() == 0)
-        rates_tile<MIXED, SPL, true>(m, n, i0, np, tp, T, P, Y, wdot);
-    else
-        rates_tile<MIXED, SPL, false>(m, n, i0, np, tp, T, P, Y, wdot);
+    rates_tile<MIXED, SPL, DIRECT>(m, n, i0, np, tp, T, P, Y, wdot);
 }
 
 // Batched requests.  The batch's tiles are split into kXcds contiguous ranges,
@@ -577,40 +666,40 @@ __global__ __launch_bounds__(kWave, SPL == 1 ? 4 : (SPL == 2 ? 3 : 2)) void rate
 // launch, and then helps with the other ranges in turn.  Every workgroup
 // exits after the last range is exhausted.  Tile t belongs to the last item
 // whose first tile is <= t.
-template <bool MIXED, int SPL>
-__global__ __launch_bounds__(kWave, SPL == 1 ? 4 : (SPL == 2 ? 3 : 2)) void rates_batch_kernel(MechDev m,
+template <bool MIXED, int SPL, bool DIRECT>
+__global__ __launch_bounds__(kWave, SPL == 1 ? 3 : 2) void rates_batch_kernel(MechDev m,
                                                             const WorkList *__restrict__ wl,
                                                             int *__restrict__ counter, int tp)
 {
     const int ntiles = wl->ntiles[0];
     const int x0 = (int)(blockIdx.x % kXcds);
-    const bool direct = lds_base() == 0;
     for (int step = 0; step < kXcds; ++step) {
         const int x = (x0 + step) % kXcds;
         const int lo = (int)((int64_t)ntiles * x / kXcds);
         const int hi = (int)((int64_t)ntiles * (x + 1) / kXcds);
+        int tn = 0;
+        if (threadIdx.x == 0) tn = atomicAdd(counter + x, 1);
         for (;;) {
-            int t = 0;
-            if (threadIdx.x == 0) t = atomicAdd(counter + x, 1);
-            t = lo + __shfl(t, 0, kWave);
+            const int t = lo + __builtin_amdgcn_readfirstlane(tn);  // lane 0's ticket
             if (t >= hi) break;
+            // the next ticket is taken now, so its round trip overlaps this tile
+            if (threadIdx.x == 0) tn = atomicAdd(counter + x, 1);
             int r = 0;
             while (r + 1 < wl->nitems && wl->start[0][r + 1] <= t) ++r;
             const WorkItem it = wl->items[r];
             const int64_t i0 = (int64_t)(t - wl->start[0][r]) * tp;
             const int np = (int)min((int64_t)tp, it.n - i0);
-            if (direct)
-                rates_tile<MIXED, SPL, true>(m, it.n, i0, np, tp, it.T, it.p, it.Y, it.wdot);
-            else
-                rates_tile<MIXED, SPL, false>(m, it.n, i0, np, tp, it.T, it.p, it.Y, it.wdot);
+            rates_tile<MIXED, SPL, DIRECT>(m, it.n, i0, np, tp, it.T, it.p, it.Y, it.wdot);
         }
     }
 }
 
 size_t rates_lds_bytes(const MechDev &m, int tp)
 {
-    return sizeof(double) * (2 * (size_t)(m.chunk + 1) + 4 * (size_t)(m.ns + 1) +
-                             8 * (size_t)tp + (size_t)m.ns * (tp + 1));
+    const int ps = rates_step_points_for(m.gpass);
+    const size_t sq = ps == 4 ? 2 * (size_t)kSqHalf / 8 : 2 * (size_t)(m.chunk + 1);
+    return sizeof(double) * (sq + 2 * (size_t)ps * (m.ns + 1) + 8 * (size_t)tp +
+                             (size_t)m.ns * (tp + 1));
 }
 
 }  // namespace
@@ -629,6 +718,17 @@ kx_status set_lds(K kern, size_t lds)
 
 // species per lane of the species and gather phases
 int rates_spl(const MechDev &m) { return m.gpass <= 1 ? 1 : (m.gpass <= 2 ? 2 : 4); }
+
+// The instance to launch: the DIRECT one when it has no static LDS.
+template <class K>
+K pick_direct(K direct, K indirect)
+{
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, (const void *)direct) == hipSuccess && a.sharedSizeBytes == 0)
+        return direct;
+    return indirect;
+}
+
 }  // namespace
 
 kx_status launch_rates(const kx_mech *mech, int64_t n, const double *T, const double *p,
@@ -644,7 +744,9 @@ kx_status launch_rates(const kx_mech *mech, int64_t n, const double *T, const do
     const int spl = rates_spl(m);
     auto pick = [&](auto mixed) {
         constexpr bool M = decltype(mixed)::value;
-        return spl == 1 ? rates_kernel<M, 1> : (spl == 2 ? rates_kernel<M, 2> : rates_kernel<M, 4>);
+        return spl == 1 ? pick_direct(rates_kernel<M, 1, true>, rates_kernel<M, 1, false>)
+                        : (spl == 2 ? pick_direct(rates_kernel<M, 2, true>, rates_kernel<M, 2, false>)
+                                    : pick_direct(rates_kernel<M, 4, true>, rates_kernel<M, 4, false>));
     };
     auto kern = precision == KX_MIXED ? pick(std::true_type{}) : pick(std::false_type{});
     kx_status st = set_lds(kern, lds);
@@ -662,8 +764,12 @@ auto pick_batch(const MechDev &m, int precision)
     const int spl = rates_spl(m);
     auto pick = [&](auto mixed) {
         constexpr bool M = decltype(mixed)::value;
-        return spl == 1 ? rates_batch_kernel<M, 1>
-                        : (spl == 2 ? rates_batch_kernel<M, 2> : rates_batch_kernel<M, 4>);
+        return spl == 1
+                   ? pick_direct(rates_batch_kernel<M, 1, true>, rates_batch_kernel<M, 1, false>)
+                   : (spl == 2 ? pick_direct(rates_batch_kernel<M, 2, true>,
+                                             rates_batch_kernel<M, 2, false>)
+                               : pick_direct(rates_batch_kernel<M, 4, true>,
+                                             rates_batch_kernel<M, 4, false>));
     };
     return precision == KX_MIXED ? pick(std::true_type{}) : pick(std::false_type{});
 }

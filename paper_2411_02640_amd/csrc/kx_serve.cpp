@@ -44,6 +44,10 @@ constexpr int kStreams = 4;
 constexpr int kRatesGrid = 4096;      // one-wave workgroups of the rates batch kernel (16 per CU)
 constexpr int kTransportGrid = 1024;  // 256-lane workgroups of the transport batch kernel
 constexpr double kSimSecondsPerPoint = 5e-9;
+// A batch of at least this many points fills the GPU on its own: two such
+// batches are not run at the same time (they would only compete for the CUs,
+// and their kernels' caches and LDS), while smaller batches overlap anything.
+constexpr int64_t kBigBatchPoints = 1 << 17;
 
 double now_s()
 {
@@ -125,6 +129,7 @@ struct Slot {
     WorkList *h_wl = nullptr;   // pinned staging
     int *d_counter = nullptr;   // kBatchCounters tile counters (rates per XCD, transport)
     bool busy = false;
+    bool big = false;           // the running batch has >= kBigBatchPoints points
     double sim_done_at = 0;
     std::vector<Req *> reqs;
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -221,6 +226,9 @@ void begin_batch(kx_server *s, Slot &sl, std::vector<Req *> &batch)
     }
     sl.reqs = batch;
     sl.busy = true;
+    int64_t pts = 0;
+    for (Req *q : batch) pts += q->r.n;
+    sl.big = pts >= kBigBatchPoints;
     s->stats.batches++;
     if (s->simulate) {
         double work = 0;
@@ -369,11 +377,34 @@ void scheduler(kx_server *s)
                 s->admitted.push_back(q);
                 s->in_flight++;
             }
-            // 3. one batch per idle stream, oldest group first
+            // 3. one batch per idle stream, oldest group first; a big batch
+            // waits while another big batch runs (younger groups' small batches
+            // may go ahead of it)
             for (Slot &sl : s->slots) {
                 if (sl.busy || s->admitted.empty()) continue;
-                const kx_mech *m = s->admitted.front()->r.mech;
-                const int prec = s->admitted.front()->r.precision;
+                bool big_running = false;
+                for (const Slot &o : s->slots) big_running = big_running || (o.busy && o.big);
+                const kx_mech *m = nullptr;
+                int prec = 0;
+                std::vector<std::pair<const kx_mech *, int>> tried;
+                for (const Req *q : s->admitted) {
+                    const std::pair<const kx_mech *, int> g{q->r.mech, q->r.precision};
+                    if (std::find(tried.begin(), tried.end(), g) != tried.end()) continue;
+                    tried.push_back(g);
+                    int64_t pts = 0;
+                    int cnt = 0;
+                    for (const Req *o : s->admitted)
+                        if (cnt < kMaxBatch && o->r.mech == g.first && o->r.precision == g.second) {
+                            pts += o->r.n;
+                            ++cnt;
+                        }
+                    if (pts < kBigBatchPoints || !big_running) {
+                        m = g.first;
+                        prec = g.second;
+                        break;
+                    }
+                }
+                if (!m) break;  // only big batches are waiting, behind a big one
                 std::vector<Req *> batch, rest;
                 for (Req *q : s->admitted) {
                     if ((int)batch.size() < kMaxBatch && q->r.mech == m && q->r.precision == prec)

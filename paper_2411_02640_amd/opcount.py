@@ -35,9 +35,10 @@ _PROBE = {"add": 0, "fma": 1, "exp": 2, "log": 3, "rcp": 4, "rsqrt": 5, "exp_mix
 def measure_prices(iters: int = 400, blocks: int = 256 * 16, reps: int = 5) -> dict:
     """Price of each elementary function as the library evaluates it on this
     GPU, in flops (the issue time of FP64 FMAs, 2 flops each): every probe
-    advances eight independent values per lane through one operation on a
-    grid filling every SIMD; the loop's bookkeeping add is timed alone and
-    subtracted.  Needs a GPU and libkx_micro.so."""
+    advances eight independent values per lane through one operation and one
+    bookkeeping add on a grid filling every SIMD; the add alone is timed and
+    subtracted, and the time of the FMA probe is the unit.  Needs a GPU and
+    libkx_micro.so."""
     import ctypes
     import os
 
@@ -59,15 +60,20 @@ def measure_prices(iters: int = 400, blocks: int = 256 * 16, reps: int = 5) -> d
             raise RuntimeError(f"kx_micro_time({name}) failed: {rc}")
         ms[name] = t.value
     torch.cuda.synchronize()
-    unit = ms["fma"] - ms["add"]
+    # an FP64 add issues like an FMA: the add probe is one bookkeeping add per
+    # step, the other FP64 probes are one operation + that add per step
+    unit = ms["fma"]
     fl = lambda k: 2.0 * (ms[k] - ms["add"]) / unit
     prices = {"exp": fl("exp"), "log": fl("log"), "div": fl("rcp") + 1.0,
               "sqrt": fl("rsqrt") + 1.0}
-    mixed = {"exp_mixed": fl("exp_mixed"), "exp32": fl("exp32"), "div32": fl("rcp32") + 1.0,
-             "fma32": fl("fma32")}
+    # FP32 probes: one operation + one FP32 add per step; an FP32 FMA issues
+    # like an FP64 one on gfx950 (packed FP32 is not used)
+    fl32 = lambda k: 2.0 * (ms[k] - ms["fma32"]) / unit
+    mixed = {"exp_mixed": fl("exp_mixed"), "exp32": fl32("exp32"), "div32": fl32("rcp32") + 1.0,
+             "fma32": 2.0 * ms["fma32"] / unit}
     # achieved FP64 FMA rate of the probe (a check of the 78.6 TFLOP/s peak)
     n_fma = blocks * 256 * iters * 8
-    rate = 2.0 * n_fma / ((ms["fma"] - ms["add"]) * 1e-3) / 1e12
+    rate = 2.0 * n_fma / (ms["fma"] * 1e-3) / 1e12
     return {"prices": prices, "mixed_prices": mixed, "probe_ms": ms,
             "fma_tflops_measured": rate}
 
