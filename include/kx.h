@@ -396,6 +396,38 @@ kx_status kx_release(kx_server *srv, kx_ticket ticket);
 
 kx_status kx_server_stats_get(kx_server *srv, kx_server_stats *stats);
 
+/* ------------------------------------------------------------------------
+ * Batched evaluation without allocation.  For callers that cannot allocate
+ * device or pinned memory while they run: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  It runs the request
+ * server's batch kernels (the same tiles, so every item's outputs are
+ * bit-identical to kx_production_rates / kx_transport and to a served request
+ * on the same inputs) over up to KX_BATCH_MAX_ITEMS point sets of one
+ * mechanism, without a server: the work list and tile counters live in a
+ * fixed device array of the library (about 5 KB per device, held until the
+ * process ends), written by a setup kernel on `stream` (no memset, no
+ * host-to-device copy).  Calls that overlap on one device race for that
+ * array: issue them on one stream, or order them.
+ * ------------------------------------------------------------------------ */
+#define KX_BATCH_MAX_ITEMS 32
+
+typedef struct {
+    int64_t n;                        /* points of this item (0: skipped) */
+    const double *T, *p, *Y;          /* DEVICE inputs, layout as kx_production_rates */
+    double *wdot;                     /* DEVICE output [Ns][n] */
+    double *mu, *lambda, *Dmix;       /* DEVICE outputs [n], [n], [Ns][n]; read only with
+                                         KX_OP_TRANSPORT */
+} kx_batch_item;
+
+/* Evaluate `ops` (KX_OP_RATES, optionally | KX_OP_TRANSPORT) in `precision` for
+ * `nitems` items of `mech`, enqueued on `stream`.  Allocates nothing: no
+ * hipMalloc, hipFree or allocating library routine is called.  KX_EINVAL for
+ * nitems outside 0..KX_BATCH_MAX_ITEMS, an item with n < 0 or a NULL array it
+ * needs, bad ops or precision, or more than 2^31 - 1 tiles in one call;
+ * KX_EUNSUPPORTED for a mechanism with QSS species. */
+kx_status kx_batch_noalloc(const kx_mech *mech, int32_t ops, int32_t precision, int32_t nitems,
+                           const kx_batch_item *items, hipStream_t stream);
+
 /* Human-readable description of the calling thread's most recent failure
  * ("" if none).  The pointer stays valid until the thread's next kx_* call. */
 const char *kx_last_error(void);

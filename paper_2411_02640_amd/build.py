@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libkx.so")
 SOURCES = ["kx_api.cpp", "kx_mech.cpp", "kx_serve.cpp", "kx_rates.hip", "kx_transport.hip",
-           "kx_jacobian.hip", "kx_qss.hip"]
+           "kx_jacobian.hip", "kx_qss.hip", "kx_batch.hip"]
 MICRO_SOURCE = "kx_micro.hip"
 MICRO_LIB = os.path.join(HERE, "libkx_micro.so")
 ARCH = "gfx950"

@@ -222,6 +222,11 @@ kx_status launch_transport_batch(const MechDev &m, const WorkList *wl, int *coun
 // Sets the transport batch kernel's dynamic-LDS limit (before graph capture).
 kx_status prepare_transport_batch(const MechDev &m, int precision);
 kx_status launch_zero(int *p, int count, hipStream_t s);
+// Persistent grids of the batch kernels: one-wave workgroups of the rates batch
+// kernel (16 per CU, at least as many as fit) and 256-lane workgroups of the
+// transport batch kernel.
+constexpr int kRatesBatchGrid = 4096;
+constexpr int kTransportBatchGrid = 1024;
 // Counters a batch uses: one per XCD for the rates tiles, one for transport.
 constexpr int kXcds = 8;
 constexpr int kBatchCounters = kXcds + 1;

@@ -41,8 +41,6 @@ namespace kx {
 namespace {
 
 constexpr int kStreams = 4;
-constexpr int kRatesGrid = 4096;      // one-wave workgroups of the rates batch kernel (16 per CU)
-constexpr int kTransportGrid = 1024;  // 256-lane workgroups of the transport batch kernel
 constexpr double kSimSecondsPerPoint = 5e-9;
 // A batch of at least this many points fills the GPU on its own: two such
 // batches are not run at the same time (they would only compete for the CUs,
@@ -199,9 +197,9 @@ kx_status build_graph(const MechDev &dev, Slot &sl, int prec, int ops, hipStream
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     kx_status st = launch_zero(sl.d_counter, kBatchCounters, cap);
-    if (st == KX_OK) st = launch_rates_batch(dev, sl.d_wl, sl.d_counter, prec, kRatesGrid, cap);
+    if (st == KX_OK) st = launch_rates_batch(dev, sl.d_wl, sl.d_counter, prec, kRatesBatchGrid, cap);
     if (st == KX_OK && (ops & KX_OP_TRANSPORT))
-        st = launch_transport_batch(dev, sl.d_wl, sl.d_counter + kXcds, prec, kTransportGrid,
+        st = launch_transport_batch(dev, sl.d_wl, sl.d_counter + kXcds, prec, kTransportBatchGrid,
                                     cap);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cap, &g);
@@ -298,11 +296,11 @@ bool enqueue_batch(kx_server *s, Slot &sl, const ServedMech &sm, hipGraphExec_t 
             ok_launch = prepare_rates_batch(sm.dev, prec) == KX_OK &&
                         prepare_transport_batch(sm.dev, prec) == KX_OK &&
                         launch_zero(sl.d_counter, kBatchCounters, sl.stream) == KX_OK &&
-                        launch_rates_batch(sm.dev, sl.d_wl, sl.d_counter, prec, kRatesGrid,
+                        launch_rates_batch(sm.dev, sl.d_wl, sl.d_counter, prec, kRatesBatchGrid,
                                            sl.stream) == KX_OK &&
                         (!(ops & KX_OP_TRANSPORT) ||
                          launch_transport_batch(sm.dev, sl.d_wl, sl.d_counter + kXcds, prec,
-                                                kTransportGrid, sl.stream) == KX_OK);
+                                                kTransportBatchGrid, sl.stream) == KX_OK);
         }
     }
     if (ok_launch) ok_launch = hipEventRecord(sl.done, sl.stream) == hipSuccess;

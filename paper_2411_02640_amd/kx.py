@@ -290,6 +290,59 @@ class _Stats(C.Structure):
                                          "resident_mechs", "resident_bytes")]
 
 
+BATCH_MAX_ITEMS = 32
+
+
+class _BatchItem(C.Structure):
+    _fields_ = [("n", C.c_int64), ("T", C.c_void_p), ("p", C.c_void_p), ("Y", C.c_void_p),
+                ("wdot", C.c_void_p), ("mu", C.c_void_p), ("lam", C.c_void_p),
+                ("Dmix", C.c_void_p)]
+
+
+def batch_noalloc(mech: Mechanism, items, transport: bool = False, precision: str = "fp64",
+                  outs=None, stream=None):
+    """kx_batch_noalloc: rates (and transport) of several point sets of one
+    mechanism in one launch sequence that allocates nothing in the library.
+    items: list of (T, p, Y) device tensors; outs: optional list of
+    (wdot, mu, lambda, Dmix) tensors per item (the transport ones may be None
+    without transport), allocated here by torch when not given.  Returns the
+    list of output tuples."""
+    L = lib()
+    if not getattr(L, "_batch_ready", False):
+        L.kx_batch_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                       C.POINTER(_BatchItem), C.c_void_p]
+        L.kx_batch_noalloc.restype = C.c_int32
+        L._batch_ready = True
+    ns = mech.n_species
+    kw = dict(dtype=torch.float64, device=f"cuda:{mech.device}")
+    arr = (_BatchItem * max(1, len(items)))()
+    res = []
+    for r, (T, p, Y) in enumerate(items):
+        n = T.shape[0]
+        if outs is not None:
+            w, mu, lam, Dm = outs[r]
+        else:
+            w = torch.empty((ns, n), **kw)
+            mu = lam = Dm = None
+            if transport:
+                mu, lam, Dm = torch.empty(n, **kw), torch.empty(n, **kw), torch.empty((ns, n), **kw)
+        ptr = lambda t, shape, name: _dev_tensor(t, mech.device, shape, name).value
+        arr[r].n = n
+        arr[r].T = ptr(T, (n,), "T")
+        arr[r].p = ptr(p, (n,), "p")
+        arr[r].Y = ptr(Y, (ns, n), "Y")
+        arr[r].wdot = ptr(w, (ns, n), "wdot")
+        if transport:
+            arr[r].mu = ptr(mu, (n,), "mu")
+            arr[r].lam = ptr(lam, (n,), "lambda")
+            arr[r].Dmix = ptr(Dm, (ns, n), "Dmix")
+        res.append((w, mu, lam, Dm))
+    ops = KX_OP_RATES | (KX_OP_TRANSPORT if transport else 0)
+    check(L.kx_batch_noalloc(mech.handle, ops, PRECISION[precision], len(items), arr,
+                             _stream_ptr(stream, mech.device)))
+    return res
+
+
 def _serve_lib():
     L = lib()
     if not getattr(L, "_serve_ready", False):
