@@ -543,6 +543,7 @@ def main():
     roofline.update({"prices_model": dict(opcount.PRICE), "prices_measured": mp["prices"],
                      "mixed_prices_measured": mp["mixed_prices"],
                      "fma_tflops_measured": mp["fma_tflops_measured"],
+                     "price_probe_ms": mp["probe_ms"],
                      "flops_per_point_measured_prices": fl_m, "tmin_ms": tmin_ms,
                      "tmin_frac": tmin_ms / ms})
     log(f"prices {json.dumps(mp['prices'])}; T_min {tmin_ms:.3f} ms = "
