@@ -77,6 +77,16 @@ template <> __device__ __forceinline__ float rsqrt_acc<float>(float x) { return 
 template <class F> __device__ __forceinline__ F rcp_acc(F x);
 template <> __device__ __forceinline__ double rcp_acc<double>(double x) { return krcp(x); }
 template <> __device__ __forceinline__ float rcp_acc<float>(float x) { return 1.0f / x; }
+// Reciprocal in the matrix-core kernel's epilogue: FP64 as rcp_acc; FP32 from
+// v_rcp_f32 with one Newton step (about 1 ulp, without the IEEE division's
+// scaling and fix-up steps).
+template <class F> __device__ __forceinline__ F rcp_mfma(F x);
+template <> __device__ __forceinline__ double rcp_mfma<double>(double x) { return krcp(x); }
+template <> __device__ __forceinline__ float rcp_mfma<float>(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
 
 template <class F> struct Tabs;
 template <> struct Tabs<double> {
@@ -304,8 +314,13 @@ __host__ __device__ constexpr size_t mfma_lds_bytes_np(int kstep)
            (size_t)((kBlock / NP) * 3 > 16 ? (kBlock / NP) * 3 : 16) * NP * sizeof(double);
 }
 
+// `tid` is threadIdx.x; the batch kernel passes it through an opaque move in
+// each trip of its tile loop, so that the tile's lane-dependent addresses are
+// not hoisted out of the loop (kept live across tiles they cost the kernel
+// its occupancy).
 template <class F, int NP, int ORDER>
-__device__ __forceinline__ void transport_mfma_tile(const MechDev &m, int64_t n, int64_t base,
+__device__ __forceinline__ void transport_mfma_tile(int tid, const MechDev &m, int64_t n,
+                                                    int64_t base,
                                                     const double *__restrict__ T,
                                                     const double *__restrict__ Pp,
                                                     const double *__restrict__ Y,
@@ -321,7 +336,7 @@ __device__ __forceinline__ void transport_mfma_tile(const MechDev &m, int64_t n,
     constexpr int LD = NP + kMfmaPad;    // LDS row stride of the tiles
     const int ns = m.ns, order = ORDER > 0 ? ORDER : m.fit_order;
     const int KS = m.kstep, MB = m.mblk, Kp = 4 * KS;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int t = tid, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
 
     extern __shared__ double smem_d[];
     F *Xs = reinterpret_cast<F *>(smem_d);
@@ -466,34 +481,53 @@ __device__ __forceinline__ void transport_mfma_tile(const MechDev &m, int64_t n,
                 }
             }
         }
-        // ---- epilogue of this row block: element r of lane l is (k, point)
+        // ---- epilogue of this row block: element e of lane l is (k, point).
+        // The Wilke denominator with sigma_k = 1/rho_k is
+        //   A + sigma (2B + sigma C) = (A rho^2 + 2 B rho + C) / rho^2,
+        // and the viscosity term X_k eta_k / den with eta_k = (W_k^(1/4) / rho_k)^2
+        // becomes X_k W_k^(1/2) / (A rho^2 + 2 B rho + C): one reciprocal per
+        // element, of a sum of positive terms.  In FP64, Z_k = X_k from the tile
+        // and the row factor is W_k^(1/2); the mixed path (FP32 tile) forms
+        // Z_k = Y_k W-bar' = X_k W_k in FP64 from the input, so its row factor
+        // is W_k^(-1/2) and the D_km numerator W-bar - X_k W_k is W-bar - Z_k.
+        constexpr bool F64 = std::is_same<F, double>::value;
+        int krow[4];
+        F rf[4];
+        double wk[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            krow[e] = 16 * mb + MF::row(lane, e);
+            const int kc = min(krow[e], ns - 1);
+            const F q = Tb::wq(m)[kc];
+            rf[e] = F64 ? q * q : (F)1 / (q * q);
+            wk[e] = F64 ? m.W[kc] : 1.0;
+        }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int pp = 16 * nb + col;
             const int64_t i = base + pp;
             const MfmaPoint P = pt[pp];
-            const int64_t ic = min(i, n - 1);
+            double yk[4];
+            if (!F64) {
+                const int64_t ic = min(i, n - 1);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) yk[e] = Y[(int64_t)min(krow[e], ns - 1) * n + ic];
+            }
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int k = 16 * mb + MF::row(lane, e);
+                const int k = krow[e];
                 if (k >= ns) continue;
                 const F rho = Rs[(size_t)k * LD + pp];
-                const F sig = rcp_acc(rho);
-                const F wsig = Tb::wq(m)[k] * sig;  // sqrt(eta_k)
-                const F den = A[nb][e] + sig * ((F)2 * B[nb][e] + sig * C[nb][e]);
-                // X_k in FP64 for the D_km numerator (W-bar - X_k W_k) / W-bar (the
-                // FP64 tile holds it already; the mixed path recomputes it)
-                const double Xk = std::is_same<F, double>::value
-                                      ? (double)Xs[(size_t)k * LD + pp]
-                                      : Y[(int64_t)k * n + ic] * m.sp[k].inv_W * P.xf;
-                mup[nb] = fma(Xk, (double)(wsig * wsig * rcp_acc(den)), mup[nb]);
+                const F den = fma(fma(A[nb][e], rho, (F)2 * B[nb][e]), rho, C[nb][e]);
+                const double Zk = F64 ? (double)Xs[(size_t)k * LD + pp] : yk[e] * P.xf;
+                mup[nb] = fma(Zk, (double)(rf[e] * rcp_mfma(den)), mup[nb]);
                 double D;
                 if (S[nb][e] == (F)0) {
                     // no other species present: D_km -> D_kk
                     const F gk = horner_v<ORDER>(Tb::ddiag(m) + k * order, (F)P.u, order);
                     D = 1.0 / ((double)gk * P.pr);
                 } else {
-                    D = (P.wbar - Xk * m.W[k]) * krcp(P.wbar * (double)S[nb][e] * P.pr);
+                    D = (P.wbar - Zk * wk[e]) * krcp(P.wbar * (double)S[nb][e] * P.pr);
                 }
                 if (i < n) Dmix[(int64_t)k * n + i] = D;
             }
@@ -522,7 +556,8 @@ __global__ __launch_bounds__(kBlock) void transport_mfma_kernel(MechDev m, int64
                                                                 double *__restrict__ lam,
                                                                 double *__restrict__ Dmix)
 {
-    transport_mfma_tile<F, NP, ORDER>(m, n, (int64_t)blockIdx.x * NP, T, Pp, Y, mu, lam, Dmix);
+    transport_mfma_tile<F, NP, ORDER>(threadIdx.x, m, n, (int64_t)blockIdx.x * NP, T, Pp, Y, mu,
+                                      lam, Dmix);
 }
 
 template <class F, int NP, int ORDER>
@@ -534,13 +569,17 @@ __global__ __launch_bounds__(kBlock) void transport_mfma_batch_kernel(
     for (;;) {
         if (threadIdx.x == 0) tile = atomicAdd(counter, 1);
         __syncthreads();
-        const int t = tile;
+        // wave-uniform (the compiler then keeps the item's pointers in scalar
+        // registers; read as a per-lane value they cost the tile its occupancy)
+        const int t = __builtin_amdgcn_readfirstlane(tile);
         __syncthreads();
         if (t >= ntiles) break;
         int r = 0;
         while (r + 1 < wl->nitems && wl->start[1][r + 1] <= t) ++r;
         const WorkItem it = wl->items[r];
-        transport_mfma_tile<F, NP, ORDER>(m, it.n, (int64_t)(t - wl->start[1][r]) * NP, it.T,
+        int tid;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+        transport_mfma_tile<F, NP, ORDER>(tid, m, it.n, (int64_t)(t - wl->start[1][r]) * NP, it.T,
                                           it.p, it.Y, it.mu, it.lam, it.Dmix);
     }
 }
@@ -569,7 +608,7 @@ __global__ __launch_bounds__(kBlock) void transport_batch_kernel(MechDev m,
     for (;;) {
         if (threadIdx.x == 0) tile = atomicAdd(counter, 1);
         __syncthreads();
-        const int t = tile;
+        const int t = __builtin_amdgcn_readfirstlane(tile);  // wave-uniform
         __syncthreads();
         if (t >= ntiles) break;
         int r = 0;
