@@ -77,13 +77,14 @@ def copy_probe(torch, gib=1):
     del src, dst
 
 
-def time_path(kx, dm, Td, pd, Yd, outs, steps, warmup, precision):
+def time_path(kx, dm, Td, pd, Yd, outs, steps, warmup, precision, symmetric=False):
     """Time `steps` steps; returns wall seconds and per-kernel mean ms."""
     import torch
     wdot, (mu, lam, Dm) = outs
     for _ in range(warmup):
         kx.production_rates(dm, Td, pd, Yd, out=wdot, precision=precision)
-        kx.transport(dm, Td, pd, Yd, out=(mu, lam, Dm), precision=precision)
+        kx.transport(dm, Td, pd, Yd, out=(mu, lam, Dm), precision=precision,
+                     symmetric=symmetric)
     torch.cuda.synchronize()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     t0 = time.perf_counter()
@@ -91,7 +92,8 @@ def time_path(kx, dm, Td, pd, Yd, outs, steps, warmup, precision):
         ev[k][0].record()
         kx.production_rates(dm, Td, pd, Yd, out=wdot, precision=precision)
         ev[k][1].record()
-        kx.transport(dm, Td, pd, Yd, out=(mu, lam, Dm), precision=precision)
+        kx.transport(dm, Td, pd, Yd, out=(mu, lam, Dm), precision=precision,
+                     symmetric=symmetric)
         ev[k][2].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -112,7 +114,7 @@ def other_workloads(kx, I, torch, steps, warmup):
     import dataclasses
     from paper_2411_02640_amd import serve_load
 
-    def run(mech, n, seed, nsteps):
+    def run(mech, n, seed, nsteps, symmetric=False):
         dm = kx.Mechanism(mech, 0)
         ns = int(mech["n_species"])
         (_, T, p, Y), = serve_load.make_pool(dm, ns, [n], seed)
@@ -122,7 +124,7 @@ def other_workloads(kx, I, torch, steps, warmup):
         entry = {"n_points": n, "n_species": ns, "n_reactions": int(mech["n_reactions"]),
                  "steps": nsteps}
         for prec in ("fp64", "mixed"):
-            wall, r, t = time_path(kx, dm, T, p, Y, outs, nsteps, warmup, prec)
+            wall, r, t = time_path(kx, dm, T, p, Y, outs, nsteps, warmup, prec, symmetric)
             entry[prec] = {"Mpoints_s": n * nsteps / wall / 1e6, "rates_ms": r,
                            "transport_ms": t, "rates_ms_median": time_path.medians[0],
                            "transport_ms_median": time_path.medians[1]}
@@ -141,6 +143,14 @@ def other_workloads(kx, I, torch, steps, warmup):
     log("syn200 at 2^20 points (D_kj fits)")
     m200d = I.make_mechanism(dataclasses.replace(I.MECH_200, diff_fit_kind=0))
     res["syn200_2p20_dfit"] = run(m200d, 1 << 20, 13, steps)
+    # the same tables with each unordered pair's D_kj fit evaluated once
+    # (KX_DKJ_SYMMETRIC), and both variants on the 53-species D_kj tables
+    log("syn200 at 2^20 points (D_kj fits, symmetric pairs)")
+    res["syn200_2p20_dfit_symmetric"] = run(m200d, 1 << 20, 13, steps, symmetric=True)
+    m53d = I.make_mechanism(dataclasses.replace(I.MECH_53, diff_fit_kind=0))
+    log("syn53 at 2^20 points (D_kj fits, full and symmetric pairs)")
+    res["syn53_2p20_dfit"] = run(m53d, 1 << 20, 14, steps)
+    res["syn53_2p20_dfit_symmetric"] = run(m53d, 1 << 20, 14, steps, symmetric=True)
     sweep = []
     for e in range(10, 25, 2):
         n = 1 << e

@@ -67,6 +67,16 @@ enum {
                       rest (see kx_production_rates_ex and kx_transport_ex) */
 };
 
+/* Option of kx_transport_ex, OR-ed into its precision argument: for tables of
+ * D_kj fits (diff_fit_kind 0) evaluate each unordered pair's fit once and let
+ * its 1/D_kj enter both S_k and S_j (D_kj = D_jk; §2.2.2, §2.3.2), keeping the
+ * sums of every species per point in LDS: one wave per 64 points, ns * 64
+ * values of LDS (KX_EUNSUPPORTED beyond 160 KB, i.e. more than 320 species in
+ * FP64).  Ignored for tables of 1/D_kj fits, whose sums run on the matrix
+ * cores (or, below 24 species, on the vector units without a reciprocal per
+ * pair). */
+enum { KX_DKJ_SYMMETRIC = 0x100 };
+
 /* Reaction types (App. A.2). */
 enum {
     KX_RXN_ELEMENTARY = 0, /* c_i = 1 */
@@ -228,7 +238,8 @@ kx_status kx_transport(const kx_mech *mech, int64_t n, const double *T, const do
                        const double *Y, double *mu, double *lambda, double *Dmix,
                        hipStream_t stream);
 
-/* As kx_transport with a precision flag.  KX_MIXED evaluates the pure-species
+/* As kx_transport with a precision flag (optionally | KX_DKJ_SYMMETRIC).
+ * KX_MIXED evaluates the pure-species
  * fits, the Wilke factors and the pair sums (sum_j X_j phi_kj, sum_j X_j/D_kj)
  * in FP32 with FP32 accumulation; the mole fractions, W-bar, Mathur's two sums
  * over species, the final sum over species of mu and the D_km numerator

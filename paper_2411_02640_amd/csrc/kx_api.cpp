@@ -128,7 +128,8 @@ kx_status kx_transport_ex(const kx_mech *mech, int64_t n, const double *T, const
 {
     kx_status st = check_common(mech, n, "kx_transport");
     if (st != KX_OK) return st;
-    if (precision != KX_FP64 && precision != KX_MIXED)
+    const int32_t prec = precision & ~KX_DKJ_SYMMETRIC;
+    if (prec != KX_FP64 && prec != KX_MIXED)
         return fail(KX_EINVAL, "kx_transport: unknown precision");
     if (n == 0) return ok();
     if (!T || !p || !Y || !mu || !lambda || !Dmix)

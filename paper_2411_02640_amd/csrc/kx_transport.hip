@@ -260,6 +260,134 @@ __device__ __forceinline__ void transport_tile(const MechDev &m, int64_t n, int6
 }
 
 // ---------------------------------------------------------------------------
+// Symmetric evaluation of the D_kj fits (§2.2.2, §2.3.2: D_kj = D_jk, so half
+// of the polynomial evaluations can be skipped).  With tables of D_kj fits
+// (kind 0) every pair costs a polynomial and a reciprocal; here each unordered
+// pair {k, j} is evaluated once and its 1/D_kj enters both sums
+// S_k = sum_{j != k} X_j / D_kj and S_j.  One wave per workgroup, one point per
+// lane (64 points).  S_j of a pair belongs to a species whose row is finished
+// later, so the sums of every species are kept per lane in LDS (ns x 64
+// values; each lane its own column).  The k rows are taken KB at a time with
+// S_k in registers: pairs (k, j) with j before the block were added to S_k's
+// LDS entry when j's block ran, pairs inside the block update the block's
+// registers, and pairs with j after the block add X_k / D_kj to S_j's entry.
+// The Wilke sums take the ordered pairs (phi_kj != phi_jk) as the full kernel.
+template <class F, int ORDER, int KB>
+__global__ __launch_bounds__(kWave) void transport_sym_kernel(MechDev m, int64_t n,
+                                                              const double *__restrict__ T,
+                                                              const double *__restrict__ Pp,
+                                                              const double *__restrict__ Y,
+                                                              double *__restrict__ mu,
+                                                              double *__restrict__ lam,
+                                                              double *__restrict__ Dmix)
+{
+    using Tb = Tabs<F>;
+    extern __shared__ double smem_d[];
+    F *sj = reinterpret_cast<F *>(smem_d);  // [ns][kWave]: S_j of this lane's point
+    const int lane = threadIdx.x;
+    const int ns = m.ns, order = m.fit_order;
+    const int64_t ir = (int64_t)blockIdx.x * kWave + lane;
+    const bool act = ir < n;
+    const int64_t i = act ? ir : n - 1;
+    const double Ti = T[i];
+    const F u = (F)((kln(Ti) - m.fit_L0) * m.inv_fit_h);
+    const double pr = Pp[i] / kPatm;
+    auto Yat = [&](int k) { return Y[(int64_t)k * n + i]; };
+
+    // X_k = (Y_k / W_k) xf; W-bar = sum_k X_k W_k; Mathur conductivity
+    double xf, wbar = 0.0;
+    {
+        double sYW = 0.0;
+        for (int k = 0; k < ns; ++k) sYW = fma(Yat(k), m.sp[k].inv_W, sYW);
+        xf = 1.0 / sYW;
+        F s1 = (F)0, s2 = (F)0;
+        for (int k = 0; k < ns; ++k) {
+            const double X = Yat(k) * m.sp[k].inv_W * xf;
+            const F lk = horner<ORDER>(Tb::cond(m) + k * order, u, order);
+            s1 = fma((F)X, lk, s1);
+            s2 = fma((F)X, rcp_acc(lk), s2);
+            wbar = fma(X, m.W[k], wbar);
+            sj[k * kWave + lane] = (F)0;
+        }
+        if (act) lam[i] = (double)((F)0.5 * (s1 + rcp_acc(s2)));
+    }
+
+    F visc = (F)0;
+    const int nkb = (ns + KB - 1) / KB;
+    for (int kb = 0; kb < nkb; ++kb) {
+        const int k0 = kb * KB, k1 = min(k0 + KB, ns);
+        const int tb = k0 / kKB, toff = k0 % kKB;
+        F sig[KB], den[KB], acc[KB], xk[KB];
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+            const int k = k0 + kk;
+            const bool valid = k < ns;
+            const int kc = valid ? k : 0;
+            const F ek = horner<ORDER>(Tb::visc(m) + kc * order, u, order);
+            sig[kk] = valid ? ek * rsqrt_acc(ek) * rcp_acc(Tb::wq(m)[kc]) : (F)0;
+            den[kk] = (F)0;
+            acc[kk] = valid ? sj[kc * kWave + lane] : (F)0;
+            xk[kk] = valid ? (F)(Yat(kc) * m.sp[kc].inv_W * xf) : (F)0;
+        }
+        const F *c1b = Tb::wilke(m) + (size_t)tb * ns * kKB + toff;
+        const F *dfb = Tb::dfit(m) + ((size_t)tb * ns * kKB + toff) * order;
+        // pairs inside the block: (k0 + a, k0 + b), a < b
+#pragma unroll
+        for (int a = 0; a < KB; ++a)
+#pragma unroll
+            for (int b = a + 1; b < KB; ++b)
+                if (k0 + b < ns) {
+                    const F f = horner<ORDER>(dfb + ((size_t)(k0 + b) * kKB + a) * order, u,
+                                              order);
+                    const F g = rcp_fast(f);
+                    acc[a] = fma(xk[b], g, acc[a]);
+                    acc[b] = fma(xk[a], g, acc[b]);
+                }
+        for (int j = 0; j < ns; ++j) {
+            const F wj = Tb::wq(m)[j];
+            const F Xj = (F)(Yat(j) * m.sp[j].inv_W * xf);
+            const F rho = wj * rsqrt_acc(horner<ORDER>(Tb::visc(m) + j * order, u, order));
+            const F *c1 = c1b + (size_t)j * kKB;
+#pragma unroll
+            for (int kk = 0; kk < KB; ++kk) {
+                // Wilke: X_j phi_kj = c1 X_j (1 + sigma_k rho_j)^2, every ordered pair
+                const F t = fma(sig[kk], rho, (F)1);
+                den[kk] = fma(c1[kk], Xj * t * t, den[kk]);
+            }
+            if (j >= k1) {
+                const F *df = dfb + (size_t)j * kKB * order;
+                F s = (F)0;
+#pragma unroll
+                for (int kk = 0; kk < KB; ++kk) {
+                    const F g = rcp_fast(horner<ORDER>(df + kk * order, u, order));
+                    acc[kk] = fma(Xj, g, acc[kk]);
+                    s = fma(xk[kk], g, s);  // xk = 0 past the last species
+                }
+                sj[j * kWave + lane] += s;
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+            const int k = k0 + kk;
+            if (k < ns) {
+                const double Xk = Yat(k) * m.sp[k].inv_W * xf;
+                const F ek = horner<ORDER>(Tb::visc(m) + k * order, u, order);
+                visc = fma((F)Xk * ek, rcp_acc(den[kk]), visc);
+                double D;
+                if (acc[kk] == (F)0) {
+                    const F f = horner<ORDER>(Tb::ddiag(m) + k * order, u, order);
+                    D = (double)f / pr;
+                } else {
+                    D = (wbar - Xk * m.W[k]) / (wbar * (double)acc[kk] * pr);
+                }
+                if (act) Dmix[(int64_t)k * n + i] = D;
+            }
+        }
+    }
+    if (act) mu[i] = (double)visc;
+}
+
+// ---------------------------------------------------------------------------
 // Matrix-core form (tables holding fits of 1/D_kj, the form the paper's
 // generated code evaluates).  With g_kj(u) = 1/D_kj(1 atm) = sum_n d_kjn u^n,
 //     S_k = sum_{j != k} X_j g_kj = sum_n sum_j d_kjn (u^n X_j),
@@ -739,8 +867,27 @@ kx_status prepare_transport_batch(const MechDev &m, int precision)
 namespace {
 template <class F>
 kx_status go_transport(const MechDev &m, int64_t n, const double *T, const double *p,
-                       const double *Y, double *mu, double *lam, double *Dmix, hipStream_t s)
+                       const double *Y, double *mu, double *lam, double *Dmix, bool sym,
+                       hipStream_t s)
 {
+    if (sym && m.diff_kind == 0) {
+        // one wave per 64 points, the per-lane sums of every species in LDS
+        const size_t lds = (size_t)m.ns * kWave * sizeof(F);
+        if (lds > 160 * 1024) return fail(KX_EUNSUPPORTED, "transport: symmetric D_kj sums "
+                                                           "of this many species exceed the LDS");
+        constexpr int KB = 8;
+        auto k = m.fit_order == 5 ? transport_sym_kernel<F, 5, KB> : transport_sym_kernel<F, 0, KB>;
+        hipError_t e = hipFuncSetAttribute((const void *)k,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute (symmetric transport)");
+        const int64_t nblk = (n + kWave - 1) / kWave;
+        if (nblk > 0x7fffffff) return fail(KX_EINVAL, "transport: n too large");
+        hipLaunchKernelGGL(k, dim3((unsigned)nblk), dim3(kWave), lds, s, m, n, T, p, Y, mu, lam,
+                           Dmix);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "symmetric transport kernel launch");
+        return ok();
+    }
     if (use_mfma(m)) {
         size_t lds = 0;
         kx_status st = mfma_prepare<F, false>(m, &lds);
@@ -800,9 +947,10 @@ kx_status launch_transport(const kx_mech *mech, int64_t n, const double *T, cons
                            const double *Y, double *mu, double *lam, double *Dmix,
                            int precision, hipStream_t s)
 {
-    if (precision == KX_MIXED)
-        return go_transport<float>(mech->dev, n, T, p, Y, mu, lam, Dmix, s);
-    return go_transport<double>(mech->dev, n, T, p, Y, mu, lam, Dmix, s);
+    const bool sym = (precision & KX_DKJ_SYMMETRIC) != 0;
+    if ((precision & ~KX_DKJ_SYMMETRIC) == KX_MIXED)
+        return go_transport<float>(mech->dev, n, T, p, Y, mu, lam, Dmix, sym, s);
+    return go_transport<double>(mech->dev, n, T, p, Y, mu, lam, Dmix, sym, s);
 }
 
 kx_status launch_transport_batch(const MechDev &m, const WorkList *wl, int *counter,

@@ -201,8 +201,14 @@ def production_rates(mech: Mechanism, T, p, Y, out=None, precision: str = "fp64"
     return out
 
 
-def transport(mech: Mechanism, T, p, Y, out=None, precision: str = "fp64", stream=None):
-    """(mu[n], lambda[n], Dmix[Ns, n]) for device tensors T, p, Y."""
+KX_DKJ_SYMMETRIC = 0x100
+
+
+def transport(mech: Mechanism, T, p, Y, out=None, precision: str = "fp64", stream=None,
+              symmetric: bool = False):
+    """(mu[n], lambda[n], Dmix[Ns, n]) for device tensors T, p, Y.  symmetric:
+    for tables of D_kj fits, evaluate each unordered pair once
+    (KX_DKJ_SYMMETRIC)."""
     n = T.shape[0]
     ns = mech.n_species
     dev = mech.device
@@ -214,8 +220,8 @@ def transport(mech: Mechanism, T, p, Y, out=None, precision: str = "fp64", strea
     mu, lam, Dm = out
     ptrs = [_dev_tensor(mu, dev, (n,), "mu"), _dev_tensor(lam, dev, (n,), "lambda"),
             _dev_tensor(Dm, dev, (ns, n), "Dmix")]
-    check(lib().kx_transport_ex(mech.handle, n, *args, *ptrs, PRECISION[precision],
-                                _stream_ptr(stream, dev)))
+    flag = PRECISION[precision] | (KX_DKJ_SYMMETRIC if symmetric else 0)
+    check(lib().kx_transport_ex(mech.handle, n, *args, *ptrs, flag, _stream_ptr(stream, dev)))
     return out
 
 
