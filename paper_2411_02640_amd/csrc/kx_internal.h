@@ -124,6 +124,11 @@ struct MechDev {
                                // 16 * slot_in_chunk per lane and group (a species with
                                // |nu''-nu'| = 2 or 3 lists the slot that many times);
                                // padding entries read the zero slot after the chunk
+    const int32_t *gmgrp;      // [nchunks] the rates kernel's lists: groups per chunk
+    const int32_t *gmoff;      // [nchunks] first group of each chunk
+    const uint4 *gment;        // [group][64 * gpass][2]: as gent, one list per species
+                               // with the +q and -q entries together, the sign of an
+                               // entry in bit 31 (set: -q) above its LDS byte offset
     // transport (FP64)
     const double *W;           // [ns]
     const double *visc;        // [ns][order]

@@ -441,6 +441,9 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     std::vector<int32_t> gpos(nchunks), gneg(nchunks), goff(nchunks);
     std::vector<uint32_t> gent;  // 8 per (group, lane)
     size_t ngroups = 0;
+    std::vector<int32_t> mgrp(nchunks), moff(nchunks);
+    std::vector<uint32_t> ment;  // signed lists of the rates kernel, 8 per (group, lane)
+    size_t nmgroups = 0;
     for (int c = 0; c < nchunks; ++c) {
         std::vector<std::vector<uint32_t>> pos(gw), neg(gw);
         for (int s = c * chunk; s < std::min(nr, (c + 1) * chunk); ++s) {
@@ -468,6 +471,28 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
         gpos[c] = (int32_t)((lp + 7) / 8);
         gneg[c] = (int32_t)((ln + 7) / 8);
         goff[c] = (int32_t)ngroups;
+        // the rates kernel's lists: one list per species with the sign of each
+        // entry in bit 31 (+q entries first), padded to whole groups of eight
+        {
+            size_t lm = 0;
+            for (int k = 0; k < gw; ++k) lm = std::max(lm, pos[k].size() + neg[k].size());
+            mgrp[c] = (int32_t)((lm + 7) / 8);
+            moff[c] = (int32_t)nmgroups;
+            const uint32_t zpad = (uint32_t)(16 * chunk);
+            for (int g = 0; g < mgrp[c]; ++g)
+                for (int k = 0; k < gw; ++k)
+                    for (int u = 0; u < 8; ++u) {
+                        const size_t e = (size_t)g * 8 + u;
+                        const size_t np_ = pos[k].size();
+                        uint32_t v = zpad;
+                        if (e < np_)
+                            v = pos[k][e];
+                        else if (e < np_ + neg[k].size())
+                            v = neg[k][e - np_] | 0x80000000u;
+                        ment.push_back(v);
+                    }
+            nmgroups += mgrp[c];
+        }
         const uint32_t pad = (uint32_t)(16 * chunk);  // the zero slot
         for (int side = 0; side < 2; ++side) {
             const auto &lists = side ? neg : pos;
@@ -482,6 +507,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
         }
     }
     if (gent.empty()) gent.resize(8, 0);
+    if (ment.empty()) ment.resize(8, 0);
 
     // ---- QSS species: index per species, per reaction (kernel order) the QSS
     // species of either side, and per QSS species the reactions of its balance
@@ -596,6 +622,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     const size_t o_sp = add_vec(b, spv), o_gpos = add_vec(b, gpos), o_gneg = add_vec(b, gneg);
     const size_t o_goff = add_vec(b, goff);
     const size_t o_gent = add_vec(b, gent);
+    const size_t o_mgrp = add_vec(b, mgrp), o_moff = add_vec(b, moff), o_ment = add_vec(b, ment);
     const size_t o_W = add_vec(b, W), o_visc = add_vec(b, visc), o_cond = add_vec(b, cond);
     const size_t o_wil = add_vec(b, wilke), o_df = add_vec(b, dfit), o_dd = add_vec(b, ddiag);
     const size_t o_wq = add_vec(b, wq), o_wq32 = add_vec(b, to32(wq));
@@ -659,6 +686,9 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     v.gneg = (const int32_t *)at(o_gneg);
     v.goff = (const int32_t *)at(o_goff);
     v.gent = (const uint4 *)at(o_gent);
+    v.gmgrp = (const int32_t *)at(o_mgrp);
+    v.gmoff = (const int32_t *)at(o_moff);
+    v.gment = (const uint4 *)at(o_ment);
     v.W = (const double *)at(o_W);
     v.visc = (const double *)at(o_visc);
     v.cond = (const double *)at(o_cond);
@@ -698,6 +728,7 @@ bool rebase_tables(const kx_mech *m, const void *base, MechDev *out)
                    : nullptr
     KX_REBASE(rxn); KX_REBASE(aux); KX_REBASE(eff); KX_REBASE(plog); KX_REBASE(sp);
     KX_REBASE(gpos); KX_REBASE(gneg); KX_REBASE(goff); KX_REBASE(gent);
+    KX_REBASE(gmgrp); KX_REBASE(gmoff); KX_REBASE(gment);
     KX_REBASE(W); KX_REBASE(visc); KX_REBASE(cond); KX_REBASE(wq); KX_REBASE(wilke);
     KX_REBASE(dfit); KX_REBASE(ddiag);
     KX_REBASE(visc32); KX_REBASE(cond32); KX_REBASE(wq32); KX_REBASE(wilke32);

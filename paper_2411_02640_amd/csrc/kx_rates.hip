@@ -392,8 +392,137 @@ __device__ __forceinline__ unsigned lds_base()
     return (unsigned)(size_t)(__attribute__((address_space(3))) double *)lds;
 }
 
+// ---- phase 3: wdot_k = sum_i nu_ki R_i for the PS points of a step, one
+// chunk of reactions.  Lane = species (SPL per lane); a group is eight list
+// entries, summed plainly per point (the mixed path compensates the running
+// sum across groups).  All reads of a group (or of each half of it, for four
+// points) are issued before the first sum (left to itself the scheduler waits
+// for each read in turn), and two groups are handled per trip with
+// alternating offset registers (the next group's offsets in flight).
+//
+// gather_signed: one list per species with the sign of each entry in bit 31,
+// turned into the factor +-1 of an exact FMA (used with four points per step,
+// where the +q and -q lists padded separately cost a third more reads).
+template <bool MIXED, int SPL, bool DIRECT, int PS>
+__device__ __forceinline__ void gather_signed(const MechDev &m, int c, int gw, int lane,
+                                              const char *qb, double (&acc)[SPL][PS],
+                                              double (&cmp)[SPL][PS])
+{
+    const int ngrp = m.gmgrp[c];
+    const uint4 *ge = m.gment + ((size_t)m.gmoff[c] * gw + lane) * 2;
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+        const uint4 *g = ge + 2 * kWave * s;
+        auto group = [&](const uint4 &v0, const uint4 &v1) {
+            const unsigned raw[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+            double gs[PS];
+#pragma unroll
+            for (int h = 0; h < PS / 2; ++h) {
+                double2 q2[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const unsigned off = raw[u] & 0x7fffffffu;
+                    q2[u] = DIRECT ? lds_read16(off + h * kSqHalf)
+                                   : *reinterpret_cast<const double2 *>(qb + off + h * kSqHalf);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // DS reads
+                __builtin_amdgcn_sched_group_barrier(0x002, 24, 0);  // VALU
+                auto sgn = [&](int u) {
+                    return __hiloint2double((int)((raw[u] & 0x80000000u) | 0x3ff00000u), 0);
+                };
+                double g0 = q2[0].x * sgn(0), g1 = q2[0].y * sgn(0);
+#pragma unroll
+                for (int u = 1; u < 8; ++u) {
+                    const double sg = sgn(u);
+                    g0 = fma(q2[u].x, sg, g0);
+                    g1 = fma(q2[u].y, sg, g1);
+                }
+                gs[2 * h] = g0;
+                gs[2 * h + 1] = g1;
+            }
+#pragma unroll
+            for (int j = 0; j < PS; ++j) accumulate<MIXED>(acc[s][j], cmp[s][j], gs[j]);
+        };
+        uint4 a0 = make_uint4(0, 0, 0, 0), a1 = a0, b0 = a0, b1 = a0;
+        if (ngrp > 0) {
+            a0 = g[0];
+            a1 = g[1];
+        }
+        int it = 0;
+        for (; it + 1 < ngrp; it += 2) {
+            b0 = g[(size_t)(it + 1) * 2 * gw];
+            b1 = g[(size_t)(it + 1) * 2 * gw + 1];
+            group(a0, a1);
+            if (it + 2 < ngrp) {
+                a0 = g[(size_t)(it + 2) * 2 * gw];
+                a1 = g[(size_t)(it + 2) * 2 * gw + 1];
+            }
+            group(b0, b1);
+        }
+        if (it < ngrp) group(a0, a1);
+    }
+}
+
+// gather_split: a +q list and a -q list per species, each padded to whole
+// groups (the group's sum is negated for the -q groups); two points per step.
+template <bool MIXED, int SPL, bool DIRECT, int PS>
+__device__ __forceinline__ void gather_split(const MechDev &m, int c, int gw, int lane,
+                                             const char *qb, double (&acc)[SPL][PS],
+                                             double (&cmp)[SPL][PS])
+{
+    const int npos = m.gpos[c], ngrp = npos + m.gneg[c];
+    const uint4 *ge = m.gent + ((size_t)m.goff[c] * gw + lane) * 2;
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+        const uint4 *g = ge + 2 * kWave * s;
+        auto group = [&](const uint4 &v0, const uint4 &v1, int it) {
+            const unsigned off[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+            double2 q2[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                q2[u] = DIRECT ? lds_read16(off[u])
+                               : *reinterpret_cast<const double2 *>(qb + off[u]);
+            __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // DS reads
+            __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);  // VALU
+            double g0 = q2[0].x, g1 = q2[0].y;
+#pragma unroll
+            for (int u = 1; u < 8; ++u) {
+                g0 += q2[u].x;
+                g1 += q2[u].y;
+            }
+            if (it >= npos) {
+                g0 = -g0;
+                g1 = -g1;
+            }
+            accumulate<MIXED>(acc[s][0], cmp[s][0], g0);
+            accumulate<MIXED>(acc[s][1], cmp[s][1], g1);
+        };
+        uint4 a0 = make_uint4(0, 0, 0, 0), a1 = a0, b0 = a0, b1 = a0;
+        if (ngrp > 0) {
+            a0 = g[0];
+            a1 = g[1];
+        }
+        int it = 0;
+        for (; it + 1 < ngrp; it += 2) {
+            b0 = g[(size_t)(it + 1) * 2 * gw];
+            b1 = g[(size_t)(it + 1) * 2 * gw + 1];
+            group(a0, a1, it);
+            if (it + 2 < ngrp) {
+                a0 = g[(size_t)(it + 2) * 2 * gw];
+                a1 = g[(size_t)(it + 2) * 2 * gw + 1];
+            }
+            group(b0, b1, it + 1);
+        }
+        if (it < ngrp) group(a0, a1, it);
+    }
+}
+
+// `lane` is threadIdx.x; the batch kernel passes it through an opaque move in
+// each trip of its tile loop, so that the tile's lane-dependent addresses are
+// not hoisted out of the loop (kept live across tiles they cost registers).
 template <bool MIXED, int SPL, bool DIRECT>
-__device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t i0, int npts,
+__device__ __forceinline__ void rates_tile(int lane, const MechDev &m, int64_t ld, int64_t i0,
+                                           int npts,
                                            int tp, const double *__restrict__ T,
                                            const double *__restrict__ P,
                                            const double *__restrict__ Y,
@@ -406,7 +535,6 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
     constexpr int NGW = kWave / TP;                 // species groups of the W-bar pass
     const int ns = m.ns;
     const int ys = TP + 1;
-    const int lane = threadIdx.x;
     double *sq = lds;
     double *pairs = sq + (PS == 4 ? 2 * kSqHalf / 8 : 2 * (m.chunk + 1));
     PointConst *pc = reinterpret_cast<PointConst *>(pairs + 2 * PS * (ns + 1));
@@ -552,64 +680,10 @@ __device__ __forceinline__ void rates_tile(const MechDev &m, int64_t ld, int64_t
                 if (PS == 4) sq[kSqHalf / 8 + 2 * r + jl] = R[NPT - 1];
             }
             wave_sync();
-            const int npos = m.gpos[c], ngrp = npos + m.gneg[c];
-            const uint4 *ge = m.gent + ((size_t)m.goff[c] * gw + lane) * 2;
-#pragma unroll
-            for (int s = 0; s < SPL; ++s) {
-                const uint4 *g = ge + 2 * kWave * s;
-                // one group: eight entries summed plainly per point (the mixed
-                // path compensates the running sum across groups); all reads of
-                // a group (or of each half of it, for four points) are issued
-                // before the first sum (left to itself the scheduler waits for
-                // each read in turn)
-                auto group = [&](const uint4 &v0, const uint4 &v1, int it) {
-                    const unsigned off[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-                    double gs[PS];
-#pragma unroll
-                    for (int h = 0; h < PS / 2; ++h) {
-                        double2 q2[8];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u)
-                            q2[u] = DIRECT ? lds_read16(off[u] + h * kSqHalf)
-                                           : *reinterpret_cast<const double2 *>(
-                                                 qb + off[u] + h * kSqHalf);
-                        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // DS reads
-                        __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);  // VALU
-                        double g0 = q2[0].x, g1 = q2[0].y;
-#pragma unroll
-                        for (int u = 1; u < 8; ++u) {
-                            g0 += q2[u].x;
-                            g1 += q2[u].y;
-                        }
-                        gs[2 * h] = g0;
-                        gs[2 * h + 1] = g1;
-                    }
-#pragma unroll
-                    for (int j = 0; j < PS; ++j) {
-                        const double t = it >= npos ? -gs[j] : gs[j];
-                        accumulate<MIXED>(acc[s][j], cmp[s][j], t);
-                    }
-                };
-                // two groups per trip with alternating offset registers (the
-                // next group's offsets in flight, and no copies between trips)
-                uint4 a0 = make_uint4(0, 0, 0, 0), a1 = a0, b0 = a0, b1 = a0;
-                if (ngrp > 0) {
-                    a0 = g[0];
-                    a1 = g[1];
-                }
-                int it = 0;
-                for (; it + 1 < ngrp; it += 2) {
-                    b0 = g[(size_t)(it + 1) * 2 * gw];
-                    b1 = g[(size_t)(it + 1) * 2 * gw + 1];
-                    group(a0, a1, it);
-                    if (it + 2 < ngrp) {
-                        a0 = g[(size_t)(it + 2) * 2 * gw];
-                        a1 = g[(size_t)(it + 2) * 2 * gw + 1];
-                    }
-                    group(b0, b1, it + 1);
-                }
-                if (it < ngrp) group(a0, a1, it);
-            }
+            if (PS == 4)
+                gather_signed<MIXED, SPL, DIRECT, PS>(m, c, gw, lane, qb, acc, cmp);
+            else
+                gather_split<MIXED, SPL, DIRECT, PS>(m, c, gw, lane, qb, acc, cmp);
             wave_sync();
         }
         // the rates of progress were stored as points (0, 1) and (2, 3); the
@@ -656,7 +730,7 @@ __global__ __launch_bounds__(kWave, SPL == 1 ? 3 : 2) void rates_kernel(MechDev 
 {
     const int64_t i0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * tp;
     const int np = (int)min((int64_t)tp, n - i0);
-    rates_tile<MIXED, SPL, DIRECT>(m, n, i0, np, tp, T, P, Y, wdot);
+    rates_tile<MIXED, SPL, DIRECT>(threadIdx.x, m, n, i0, np, tp, T, P, Y, wdot);
 }
 
 // Batched requests.  The batch's tiles are split into kXcds contiguous ranges,
@@ -689,7 +763,9 @@ __global__ __launch_bounds__(kWave, SPL == 1 ? 3 : 2) void rates_batch_kernel(Me
             const WorkItem it = wl->items[r];
             const int64_t i0 = (int64_t)(t - wl->start[0][r]) * tp;
             const int np = (int)min((int64_t)tp, it.n - i0);
-            rates_tile<MIXED, SPL, DIRECT>(m, it.n, i0, np, tp, it.T, it.p, it.Y, it.wdot);
+            int lane;
+            asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"((int)threadIdx.x));
+            rates_tile<MIXED, SPL, DIRECT>(lane, m, it.n, i0, np, tp, it.T, it.p, it.Y, it.wdot);
         }
     }
 }
