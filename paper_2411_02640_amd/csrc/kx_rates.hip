@@ -316,9 +316,8 @@ __device__ __forceinline__ void rates_of_progress(const MechDev &m, const RxnWor
 
 // Gibbs energy g = G/RT of one species at one temperature (eq:Ck with the
 // coefficients pre-scaled: g = c0 (1 - ln T) + c1 T + ... + c4 T^4 + c5 / T + c6).
-__device__ __forceinline__ double gibbs(const DevSpecies &S, double T, double lnT, double invT)
+__device__ __forceinline__ double gibbs(const double (&g)[7], double T, double lnT, double invT)
 {
-    const double *g = (T < S.t_mid) ? S.g_lo : S.g_hi;
     const double poly = T * fma(T, fma(T, fma(T, g[4], g[3]), g[2]), g[1]);
     return fma(g[0], 1.0 - lnT, poly) + fma(g[5], invT, g[6]);
 }
@@ -626,12 +625,26 @@ __device__ __forceinline__ void rates_tile(int lane, const MechDev &m, int64_t l
         for (int s = 0; s < SPL; ++s) {
             const int k = lane + kWave * s;
             if (k < ns) {
+                // both temperature ranges' coefficients are read once per step
+                // and selected per point (one read per point would cost the
+                // vector-memory unit four times as many loads)
                 const DevSpecies &S = m.sp[k];
+                double glo[7], ghi[7];
+#pragma unroll
+                for (int e = 0; e < 7; ++e) {
+                    glo[e] = S.g_lo[e];
+                    ghi[e] = S.g_hi[e];
+                }
+                const double tmid = S.t_mid, iw = S.inv_W;
 #pragma unroll
                 for (int j = 0; j < PS; ++j) {
                     const PointConst &q = ps[j];
-                    const double ak = q.P0 * kexp(-gibbs(S, q.T, q.lnT, q.invT));
-                    const double Ck = Yt[k * ys + pl + j] * S.inv_W * q.cf;
+                    double g[7];
+                    const bool lo = q.T < tmid;
+#pragma unroll
+                    for (int e = 0; e < 7; ++e) g[e] = lo ? glo[e] : ghi[e];
+                    const double ak = q.P0 * kexp(-gibbs(g, q.T, q.lnT, q.invT));
+                    const double Ck = Yt[k * ys + pl + j] * iw * q.cf;
                     double *pr = pairs + 2 * (ns + 1) * j + 2 * k;
                     pr[0] = ak;
                     pr[1] = Ck * krcp(ak);
