@@ -57,6 +57,26 @@ __device__ __forceinline__ double exp_mixed(double x)
     return ldexp((double)er, (int)nd);
 }
 
+// The falloff data of a reaction: k_0's Arrhenius parameters and the blend
+// parameters (loaded with the third-body data, for the same reason).
+struct Falloff {
+    double lnA0, beta0, ER0;
+    double fp[5];
+    int has_T2;
+};
+
+__device__ __forceinline__ Falloff load_falloff(const DevAux &ax)
+{
+    Falloff f;
+    f.lnA0 = ax.lnA0;
+    f.beta0 = ax.beta0;
+    f.ER0 = ax.ER0;
+#pragma unroll
+    for (int e = 0; e < 5; ++e) f.fp[e] = ax.fp[e];
+    f.has_T2 = ax.has_T2;
+    return f;
+}
+
 // Falloff blending factor F (eq:blend), Troe and SRI in one code path (so a
 // wave mixing the two runs it once):
 //   Troe  log10 F = log10 F_cent / (1 + f1^2), f1 = (l + c) / (n - 0.14 (l + c)),
@@ -66,7 +86,7 @@ __device__ __forceinline__ double exp_mixed(double x)
 // with l = log10 P_r.  Both are ln F = ln B / (1 + w^2) + extra, where B is
 // F_cent or the SRI bracket, w = f1 or l, and extra = 0 or ln d + e ln T.  The
 // base-10 logarithms are formed from natural ones.
-__device__ __forceinline__ double blend_F64(const DevAux &ax, bool sri, double T, double lnT,
+__device__ __forceinline__ double blend_F64(const Falloff &ax, bool sri, double T, double lnT,
                                             double invT, double lnPr)
 {
     constexpr double kInvLn10 = 0.43429448190325182765;
@@ -83,7 +103,7 @@ __device__ __forceinline__ double blend_F64(const DevAux &ax, bool sri, double T
 }
 
 // The same in FP32 from l = log10 P_r (computed by the caller without overflow).
-__device__ __forceinline__ float blend_F32(const DevAux &ax, bool sri, float T, float lnT,
+__device__ __forceinline__ float blend_F32(const Falloff &ax, bool sri, float T, float lnT,
                                            float invT, float lPr)
 {
     const float a0 = (float)ax.fp[0], a1 = (float)ax.fp[1], a2 = (float)ax.fp[2];
@@ -150,24 +170,53 @@ __device__ __forceinline__ double as_double(unsigned lo, unsigned hi)
     return __hiloint2double((int)hi, (int)lo);
 }
 
+// The third-body data of a reaction: the default efficiency, the inline
+// efficiencies (alpha - default) and their LDS offsets, and the count of
+// further ones.  Loaded as one batch as soon as the reaction record is decoded,
+// so that its memory latency overlaps the Arrhenius exponentials (loaded where
+// the sum is formed, each of its dependent batches stalls the wave).
+struct ThirdBody {
+    double def;
+    double dalpha[kInlineEff];
+    unsigned eoff2[kInlineEff / 2];  // two 16-bit offsets per word (unpacked where used)
+    int ext_off, ext_cnt;
+};
+
+__device__ __forceinline__ ThirdBody load_third_body(const DevAux &ax)
+{
+    ThirdBody t;
+    t.def = ax.eff_default;
+#pragma unroll
+    for (int e = 0; e < kInlineEff; ++e) t.dalpha[e] = ax.dalpha[e];
+    const unsigned *eo = reinterpret_cast<const unsigned *>(ax.eoff);
+#pragma unroll
+    for (int e = 0; e < kInlineEff / 2; ++e) t.eoff2[e] = eo[e];
+    t.ext_off = ax.ext_off;
+    t.ext_cnt = ax.ext_cnt;
+    return t;
+}
+
 // [X]_i = default [M] + sum over listed species of (alpha - default) C_k.
-__device__ __forceinline__ double third_body(const MechDev &m, const DevAux &ax,
+__device__ __forceinline__ double third_body(const MechDev &m, const ThirdBody &tb,
                                              const char *__restrict__ pb, double Mconc)
 {
-    double X = ax.eff_default * Mconc;
+    double X = tb.def * Mconc;
     // the reads are issued four at a time (left to itself the scheduler waits
     // for each read in turn; eight in flight would cost registers)
 #pragma unroll
     for (int e0 = 0; e0 < kInlineEff; e0 += 4) {
         Pair s[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) s[e] = load_pair(pb, ax.eoff[e0 + e]);
+        for (int e = 0; e < 4; ++e) {
+            const int ee = e0 + e;
+            s[e] = load_pair(pb, (tb.eoff2[ee / 2] >> (16 * (ee & 1))) & 0xFFFFu);
+        }
         __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) X = fma(ax.dalpha[e0 + e], s[e].a * s[e].b, X);
+        for (int e = 0; e < 4; ++e) X = fma(tb.dalpha[e0 + e], s[e].a * s[e].b, X);
     }
-    for (int e = 0; e < ax.ext_cnt; ++e) {
-        const DevEff f = m.eff[ax.ext_off + e];
+    for (int e = 0; e < tb.ext_cnt; ++e) {
+        const DevEff f = m.eff[tb.ext_off + e];
         const Pair s = load_pair(pb, 16 * f.sp);
         X = fma(f.dalpha, s.a * s.b, X);
     }
@@ -197,6 +246,12 @@ __device__ __forceinline__ void rates_of_progress(const MechDev &m, const RxnWor
     const unsigned aux = w.w2.w >> 16;
     const unsigned o0 = w.w2.x & 0xFFFFu, o1 = w.w2.x >> 16;
     const unsigned o3 = w.w2.y >> 16, o4 = w.w2.z & 0xFFFFu;
+
+    const bool has_tb = type != KX_RXN_ELEMENTARY && type != KX_RXN_PLOG;
+    const bool has_fo = has_tb && type != KX_RXN_THREEBODY;
+    ThirdBody tb;
+    Falloff fo;
+    if (has_tb) tb = load_third_body(m.aux[aux]);
 
     // exponent of k_f (eq:k_f); k_f = A without an exponential when beta = E_R = 0
     // (such reactions are sorted together, so the branch is mostly wave-uniform),
@@ -273,33 +328,33 @@ __device__ __forceinline__ void rates_of_progress(const MechDev &m, const RxnWor
     double c[NPT];
 #pragma unroll
     for (int j = 0; j < NPT; ++j) c[j] = 1.0;
-    if (type != KX_RXN_ELEMENTARY && type != KX_RXN_PLOG) {
-        const DevAux &ax = m.aux[aux];
+    if (has_tb) {
         double X[NPT];
 #pragma unroll
         for (int j = 0; j < NPT; ++j) {
-            X[j] = third_body(m, ax, pb[j], q[j].M);
+            X[j] = third_body(m, tb, pb[j], q[j].M);
             c[j] = X[j];
         }
         if (type != KX_RXN_THREEBODY) {
+            fo = load_falloff(m.aux[aux]);
 #pragma unroll
             for (int j = 0; j < NPT; ++j) {
                 // P_r = k_0 [X] / k_inf = e0 [X] with e0 = exp(x_0 - x_inf) (no division)
                 const double d0 =
-                    fma(ax.beta0, q[j].lnT, fma(-ax.ER0, q[j].invT, ax.lnA0)) - xf[j];
+                    fma(fo.beta0, q[j].lnT, fma(-fo.ER0, q[j].invT, fo.lnA0)) - xf[j];
                 const double e0 = MIXED ? exp_mixed(d0) : kexp(d0);
                 const double Pr = e0 * X[j];
                 double F = 1.0;
                 if (type == KX_RXN_TROE || type == KX_RXN_SRI) {
                     const bool sri = type == KX_RXN_SRI;
                     if (MIXED) {
-                        F = (double)blend_F32(ax, sri, (float)q[j].T, (float)q[j].lnT,
+                        F = (double)blend_F32(fo, sri, (float)q[j].T, (float)q[j].lnT,
                                               (float)q[j].invT, log10_wide(Pr));
                     } else {
                         // ln max(P_r, DBL_MIN) without forming the logarithm of P_r
                         const double lnPr =
                             fmax(d0 + kln(fmax(X[j], DBL_MIN)), -708.39641853226410622);
-                        F = blend_F64(ax, sri, q[j].T, q[j].lnT, q[j].invT, lnPr);
+                        F = blend_F64(fo, sri, q[j].T, q[j].lnT, q[j].invT, lnPr);
                     }
                 }
                 // eq:c_i: P_r/(1+P_r) F; chemically activated: F/(1+P_r) with k_0 =
