@@ -565,6 +565,22 @@ def main():
                                 "achieved": ofl * n / (oms * 1e-3) / 1e12,
                                 "frac": ofl * n / (oms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS,
                                 "ms": oms, "traffic": profiled_traffic(other)}
+    if other == "transport":
+        # the matrix-core work the kernel issues (16x16x4 FP64 tiles over the
+        # padded species: ceil(ns/16) row blocks x ceil(ns/4) K-steps x
+        # (3 Wilke products + one per fit order) per 16 points), against the
+        # rate that instruction sustains on this GPU (probe above)
+        ns_ = mech["n_species"]
+        mb_, ks_ = -(-ns_ // 16), -(-ns_ // 4)
+        mfl = mb_ * ks_ * (3 + int(mech["fit_order"])) * 2048 / 16
+        rate = mfl * n / (oms * 1e-3) / 1e12
+        peak_m = mp["mfma_tflops_measured"]["f64_16x16x4"]
+        roofline["other_kernel"].update({
+            "mfma_flops_per_point_issued": mfl, "mfma_tflops_issued": rate,
+            "mfma_tflops_measured": mp["mfma_tflops_measured"],
+            "mfma_frac_of_measured_16x16x4": rate / peak_m})
+        log(f"transport issues {rate:.1f} TFLOP/s of 16x16x4 FP64 MFMA work; the "
+            f"instruction sustains {peak_m:.1f} on this GPU ({rate / peak_m:.2f})")
 
     extra = None
     if not args.no_extra:

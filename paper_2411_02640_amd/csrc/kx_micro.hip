@@ -13,6 +13,11 @@
 // add issues like an FMA, so the add probe removes the bookkeeping and the FMA
 // probe (one FMA per step) is the unit.
 //
+// The matrix-core probes (ops 10..13) issue one MFMA per step into each of
+// eight independent accumulators per wave, on the same grid; they measure the
+// rate each instruction sustains on this GPU, against which the transport
+// kernel's matrix-core throughput is read.
+//
 // This file is a measuring tool: it is built into its own library, which the
 // benchmark loads; the chemistry library does not contain it.
 #include <hip/hip_runtime.h>
@@ -36,7 +41,61 @@ enum Op {
     kOpExp32 = 7,    // FP32: v = __expf(v) - 2
     kOpRcp32 = 8,    // FP32: v = 1 / v + 1/2 (correctly rounded division)
     kOpFma32 = 9,    // FP32: v = v * c + d (also the bookkeeping of the FP32 probes)
+    kOpMfma64x16 = 10,  // v_mfma_f64_16x16x4_f64 (2048 flops)
+    kOpMfma64x4 = 11,   // v_mfma_f64_4x4x4_4b_f64 (512 flops)
+    kOpMfma32x16 = 12,  // v_mfma_f32_16x16x4_f32 (2048 flops)
+    kOpMfma32x32 = 13,  // v_mfma_f32_32x32x2_f32 (4096 flops)
 };
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// Eight accumulators per wave, each advanced by one MFMA per step.
+template <int OP>
+__device__ __forceinline__ double mfma_probe(int iters, double seed)
+{
+    const double a = seed + threadIdx.x * 1e-3, b = seed - threadIdx.x * 1e-3;
+    const float af = (float)a, bf = (float)b;
+    double r = 0.0;
+    if (OP == kOpMfma64x16) {
+        v4d c[8];
+        for (int q = 0; q < 8; ++q) c[q] = v4d{seed, 0.0, 0.0, 0.0};
+        for (int it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) c[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c[q], 0, 0, 0);
+        }
+        for (int q = 0; q < 8; ++q) r += c[q][q & 3];
+    } else if (OP == kOpMfma64x4) {
+        double c[8];
+        for (int q = 0; q < 8; ++q) c[q] = seed;
+        for (int it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) c[q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c[q], 0, 0, 0);
+        }
+        for (int q = 0; q < 8; ++q) r += c[q];
+    } else if (OP == kOpMfma32x16) {
+        v4f c[8];
+        for (int q = 0; q < 8; ++q) c[q] = v4f{(float)seed, 0.0f, 0.0f, 0.0f};
+        for (int it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) c[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf, c[q], 0, 0, 0);
+        }
+        for (int q = 0; q < 8; ++q) r += c[q][q & 3];
+    } else {
+        v16f c[8];
+        for (int q = 0; q < 8; ++q) {
+            c[q] = v16f{};
+            c[q][0] = (float)seed;
+        }
+        for (int it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) c[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(af, bf, c[q], 0, 0, 0);
+        }
+        for (int q = 0; q < 8; ++q) r += c[q][q];
+    }
+    return r;
+}
 
 __device__ __forceinline__ double exp_mixed_probe(double x)
 {
@@ -49,6 +108,10 @@ __device__ __forceinline__ double exp_mixed_probe(double x)
 template <int OP>
 __global__ __launch_bounds__(256) void probe_kernel(int iters, double seed, double *out)
 {
+    if (OP >= kOpMfma64x16) {
+        out[blockIdx.x * blockDim.x + threadIdx.x] = mfma_probe<OP>(iters, seed);
+        return;
+    }
     if (OP >= kOpExp32) {
         float v[kValues];
 #pragma unroll
@@ -106,13 +169,13 @@ double seed_of(int op)
 
 extern "C" {
 
-// Time `reps` launches of the probe for operation `op` (0..9, see Op) with
+// Time `reps` launches of the probe for operation `op` (0..13, see Op) with
 // `iters` loop trips on a grid of `blocks` workgroups of 256 threads; `out`
 // is device scratch of blocks * 256 doubles.  Writes the mean milliseconds per
 // launch to *ms.  Returns 0, or -1 for a bad argument, -3 for a HIP error.
 int kx_micro_time(int op, int iters, int blocks, int reps, double *out, double *ms)
 {
-    if (op < 0 || op > 9 || iters <= 0 || blocks <= 0 || reps <= 0 || !out || !ms) return -1;
+    if (op < 0 || op > 13 || iters <= 0 || blocks <= 0 || reps <= 0 || !out || !ms) return -1;
     void (*k)(int, double, double *) = nullptr;
     switch (op) {
         case 0: k = probe_kernel<0>; break;
@@ -124,7 +187,11 @@ int kx_micro_time(int op, int iters, int blocks, int reps, double *out, double *
         case 6: k = probe_kernel<6>; break;
         case 7: k = probe_kernel<7>; break;
         case 8: k = probe_kernel<8>; break;
-        default: k = probe_kernel<9>; break;
+        case 9: k = probe_kernel<9>; break;
+        case 10: k = probe_kernel<10>; break;
+        case 11: k = probe_kernel<11>; break;
+        case 12: k = probe_kernel<12>; break;
+        default: k = probe_kernel<13>; break;
     }
     const double seed = seed_of(op);
     hipEvent_t e0, e1;

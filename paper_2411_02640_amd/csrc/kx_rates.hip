@@ -329,14 +329,18 @@ __device__ __forceinline__ void rates_of_progress(const MechDev &m, const RxnWor
 #pragma unroll
     for (int j = 0; j < NPT; ++j) c[j] = 1.0;
     if (has_tb) {
+        // FP64: the falloff data is read before the third-body sums, whose LDS
+        // reads and products then cover its memory latency (the mixed path
+        // reads it where it is used: the earlier read measured slower there)
+        if (!MIXED && has_fo) fo = load_falloff(m.aux[aux]);
         double X[NPT];
 #pragma unroll
         for (int j = 0; j < NPT; ++j) {
             X[j] = third_body(m, tb, pb[j], q[j].M);
             c[j] = X[j];
         }
-        if (type != KX_RXN_THREEBODY) {
-            fo = load_falloff(m.aux[aux]);
+        if (has_fo) {
+            if (MIXED) fo = load_falloff(m.aux[aux]);
 #pragma unroll
             for (int j = 0; j < NPT; ++j) {
                 // P_r = k_0 [X] / k_inf = e0 [X] with e0 = exp(x_0 - x_inf) (no division)
@@ -386,6 +390,32 @@ __device__ __forceinline__ void accumulate(double &acc, double &cmp, double t)
         acc = sum;
     } else {
         acc += t;
+    }
+}
+
+// Two groups' partial sums ga, gb per trip of a gather loop: FP64 adds each to
+// the running sum as it is formed (first_of_pair, then second_of_pair); the
+// mixed path adds their sum with one compensated step (the two groups' plain
+// sum carries FP64 rounding, far below the mixed path's error).
+template <bool MIXED, int PS>
+__device__ __forceinline__ void first_of_pair(double (&acc)[PS], const double (&ga)[PS])
+{
+    if (!MIXED) {
+#pragma unroll
+        for (int j = 0; j < PS; ++j) acc[j] += ga[j];
+    }
+}
+
+template <bool MIXED, int PS>
+__device__ __forceinline__ void second_of_pair(double (&acc)[PS], double (&cmp)[PS],
+                                               const double (&ga)[PS], const double (&gb)[PS])
+{
+#pragma unroll
+    for (int j = 0; j < PS; ++j) {
+        if (MIXED)
+            accumulate<true>(acc[j], cmp[j], ga[j] + gb[j]);
+        else
+            acc[j] += gb[j];
     }
 }
 
@@ -449,7 +479,7 @@ __device__ __forceinline__ unsigned lds_base()
 // ---- phase 3: wdot_k = sum_i nu_ki R_i for the PS points of a step, one
 // chunk of reactions.  Lane = species (SPL per lane); a group is eight list
 // entries, summed plainly per point (the mixed path compensates the running
-// sum across groups).  All reads of a group (or of each half of it, for four
+// sum once per two groups).  All reads of a group (or of each half of it, for four
 // points) are issued before the first sum (left to itself the scheduler waits
 // for each read in turn), and two groups are handled per trip with
 // alternating offset registers (the next group's offsets in flight).
@@ -467,9 +497,8 @@ __device__ __forceinline__ void gather_signed(const MechDev &m, int c, int gw, i
 #pragma unroll
     for (int s = 0; s < SPL; ++s) {
         const uint4 *g = ge + 2 * kWave * s;
-        auto group = [&](const uint4 &v0, const uint4 &v1) {
+        auto group = [&](const uint4 &v0, const uint4 &v1, double (&gs)[PS]) {
             const unsigned raw[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-            double gs[PS];
 #pragma unroll
             for (int h = 0; h < PS / 2; ++h) {
                 double2 q2[8];
@@ -494,8 +523,6 @@ __device__ __forceinline__ void gather_signed(const MechDev &m, int c, int gw, i
                 gs[2 * h] = g0;
                 gs[2 * h + 1] = g1;
             }
-#pragma unroll
-            for (int j = 0; j < PS; ++j) accumulate<MIXED>(acc[s][j], cmp[s][j], gs[j]);
         };
         uint4 a0 = make_uint4(0, 0, 0, 0), a1 = a0, b0 = a0, b1 = a0;
         if (ngrp > 0) {
@@ -506,14 +533,22 @@ __device__ __forceinline__ void gather_signed(const MechDev &m, int c, int gw, i
         for (; it + 1 < ngrp; it += 2) {
             b0 = g[(size_t)(it + 1) * 2 * gw];
             b1 = g[(size_t)(it + 1) * 2 * gw + 1];
-            group(a0, a1);
+            double ga[PS], gb[PS];
+            group(a0, a1, ga);
+            first_of_pair<MIXED, PS>(acc[s], ga);
             if (it + 2 < ngrp) {
                 a0 = g[(size_t)(it + 2) * 2 * gw];
                 a1 = g[(size_t)(it + 2) * 2 * gw + 1];
             }
-            group(b0, b1);
+            group(b0, b1, gb);
+            second_of_pair<MIXED, PS>(acc[s], cmp[s], ga, gb);
         }
-        if (it < ngrp) group(a0, a1);
+        if (it < ngrp) {
+            double ga[PS];
+            group(a0, a1, ga);
+#pragma unroll
+            for (int j = 0; j < PS; ++j) accumulate<MIXED>(acc[s][j], cmp[s][j], ga[j]);
+        }
     }
 }
 
@@ -529,7 +564,7 @@ __device__ __forceinline__ void gather_split(const MechDev &m, int c, int gw, in
 #pragma unroll
     for (int s = 0; s < SPL; ++s) {
         const uint4 *g = ge + 2 * kWave * s;
-        auto group = [&](const uint4 &v0, const uint4 &v1, int it) {
+        auto group = [&](const uint4 &v0, const uint4 &v1, int it, double (&gs)[PS]) {
             const unsigned off[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
             double2 q2[8];
 #pragma unroll
@@ -548,8 +583,8 @@ __device__ __forceinline__ void gather_split(const MechDev &m, int c, int gw, in
                 g0 = -g0;
                 g1 = -g1;
             }
-            accumulate<MIXED>(acc[s][0], cmp[s][0], g0);
-            accumulate<MIXED>(acc[s][1], cmp[s][1], g1);
+            gs[0] = g0;
+            gs[1] = g1;
         };
         uint4 a0 = make_uint4(0, 0, 0, 0), a1 = a0, b0 = a0, b1 = a0;
         if (ngrp > 0) {
@@ -560,14 +595,22 @@ __device__ __forceinline__ void gather_split(const MechDev &m, int c, int gw, in
         for (; it + 1 < ngrp; it += 2) {
             b0 = g[(size_t)(it + 1) * 2 * gw];
             b1 = g[(size_t)(it + 1) * 2 * gw + 1];
-            group(a0, a1, it);
+            double ga[PS], gb[PS];
+            group(a0, a1, it, ga);
+            first_of_pair<MIXED, PS>(acc[s], ga);
             if (it + 2 < ngrp) {
                 a0 = g[(size_t)(it + 2) * 2 * gw];
                 a1 = g[(size_t)(it + 2) * 2 * gw + 1];
             }
-            group(b0, b1, it + 1);
+            group(b0, b1, it + 1, gb);
+            second_of_pair<MIXED, PS>(acc[s], cmp[s], ga, gb);
         }
-        if (it < ngrp) group(a0, a1, it);
+        if (it < ngrp) {
+            double ga[PS];
+            group(a0, a1, it, ga);
+#pragma unroll
+            for (int j = 0; j < PS; ++j) accumulate<MIXED>(acc[s][j], cmp[s][j], ga[j]);
+        }
     }
 }
 
@@ -596,6 +639,14 @@ __device__ __forceinline__ void rates_tile(int lane, const MechDev &m, int64_t l
     const char *qb = reinterpret_cast<const char *>(sq);
     (void)tp;
 
+    // the temperature and pressure of the tile's points are read first, so
+    // that their memory latency overlaps the Y tile's
+    double Tl = 0.0, Pl = 0.0;
+    if (lane < TP) {
+        const int64_t i = i0 + min(lane, npts - 1);
+        Tl = T[i];
+        Pl = P[i];
+    }
     // the tile's Y, eight row loads per lane in flight before the first LDS
     // store (a loop of load-wait-store would pay one memory latency per row)
     constexpr int kLd = 8;
@@ -637,20 +688,18 @@ __device__ __forceinline__ void rates_tile(int lane, const MechDev &m, int64_t l
     }
     __syncthreads();
     if (lane < TP) {
-        const int c = min(lane, npts - 1);
-        const int64_t i = i0 + c;
         double wsum = 0.0;
 #pragma unroll
         for (int g = 0; g < NGW; ++g) wsum += sq[g * TP + lane];
         PointConst q;
-        q.T = T[i];
+        q.T = Tl;
         q.lnT = kln(q.T);
         q.invT = krcp(q.T);
         const double invRT = krcp(kRu * q.T);
-        q.M = P[i] * invRT;
+        q.M = Pl * invRT;
         q.P0 = kPatm * invRT;
         q.cf = q.M * krcp(wsum);
-        q.lnp = kln(P[i]);
+        q.lnp = kln(Pl);
         q.pad = 0.0;
         pc[lane] = q;
     }

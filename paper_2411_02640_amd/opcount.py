@@ -30,6 +30,9 @@ PRICE = {"exp": 24, "log": 24, "div": 8, "sqrt": 8}
 # square root times the argument (one more multiply each).
 _PROBE = {"add": 0, "fma": 1, "exp": 2, "log": 3, "rcp": 4, "rsqrt": 5, "exp_mixed": 6,
           "exp32": 7, "rcp32": 8, "fma32": 9}
+# matrix-core probes: op and flops per instruction
+_MFMA_PROBE = {"f64_16x16x4": (10, 2048), "f64_4x4x4_4b": (11, 512),
+               "f32_16x16x4": (12, 2048), "f32_32x32x2": (13, 4096)}
 
 
 def measure_prices(iters: int = 400, blocks: int = 256 * 16, reps: int = 5) -> dict:
@@ -74,8 +77,21 @@ def measure_prices(iters: int = 400, blocks: int = 256 * 16, reps: int = 5) -> d
     # achieved FP64 FMA rate of the probe (a check of the 78.6 TFLOP/s peak)
     n_fma = blocks * 256 * iters * 8
     rate = 2.0 * n_fma / (ms["fma"] * 1e-3) / 1e12
+    # sustained rates of the matrix-core instructions (eight independent
+    # accumulators per wave, one MFMA each per step)
+    mfma = {}
+    for name, (op, flops) in _MFMA_PROBE.items():
+        t = ctypes.c_double()
+        rc = lib.kx_micro_time(op, iters, blocks, reps, ctypes.c_void_p(out.data_ptr()),
+                               ctypes.byref(t))
+        if rc != 0:
+            raise RuntimeError(f"kx_micro_time({name}) failed: {rc}")
+        ms[name] = t.value
+        waves = blocks * 256 // 64
+        mfma[name] = flops * 8.0 * iters * waves / (t.value * 1e-3) / 1e12
+    torch.cuda.synchronize()
     return {"prices": prices, "mixed_prices": mixed, "probe_ms": ms,
-            "fma_tflops_measured": rate}
+            "fma_tflops_measured": rate, "mfma_tflops_measured": mfma}
 
 
 def flops_priced(counts: dict, prices: dict) -> float:
