@@ -293,10 +293,12 @@ kx_status kx_qss_concentrations(const kx_mech *mech, int64_t n, const double *T,
  * outputs of admitted requests; a scheduler thread admits queued requests in
  * arrival order whenever a slot and arena space are free, groups admitted
  * requests by (mechanism, precision) into batches of up to 64, and runs each
- * batch as work-stealing kernels over a device work list, replayed from a HIP
- * graph, on one of several streams -- batches of different groups overlap on
- * the device.  Every request is cut into the same tiles as a direct call, so
- * its outputs are bit-identical alone and in a batch.
+ * batch over a device work list on one of several streams -- batches of
+ * different groups overlap on the device.  A batch of fewer than 2^17 points
+ * replays a captured HIP graph of work-stealing kernels; a bigger one is
+ * launched directly with one rates workgroup per tile.  Every request is cut
+ * into the same tiles as a direct call, so its outputs are bit-identical alone
+ * and in a batch.
  * ------------------------------------------------------------------------ */
 typedef struct kx_server kx_server;
 typedef int64_t kx_ticket;
@@ -337,7 +339,7 @@ typedef struct {
 typedef struct {
     int64_t submitted, completed, cancelled, failed;
     int64_t queued, in_flight;          /* now */
-    int64_t batches, graph_launches;
+    int64_t batches, graph_launches;   /* graph_launches: batches replayed from a graph */
     int64_t arena_in_use, arena_capacity;  /* bytes; in use includes resident tables */
     int64_t resident_mechs, resident_bytes;
 } kx_server_stats;
@@ -411,13 +413,13 @@ kx_status kx_server_stats_get(kx_server *srv, kx_server_stats *stats);
  * Batched evaluation without allocation.  For callers that cannot allocate
  * device or pinned memory while they run: code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc.  It runs the request
- * server's batch kernels (the same tiles, so every item's outputs are
- * bit-identical to kx_production_rates / kx_transport and to a served request
- * on the same inputs) over up to KX_BATCH_MAX_ITEMS point sets of one
- * mechanism, without a server: the work list and tile counters live in a
- * fixed device array of the library (about 5 KB per device, held until the
- * process ends), written by a setup kernel on `stream` (no memset, no
- * host-to-device copy).  Calls that overlap on one device race for that
+ * server's batch kernels for big batches (one workgroup per tile, the same
+ * tiles, so every item's outputs are bit-identical to kx_production_rates /
+ * kx_transport and to a served request on the same inputs) over up to
+ * KX_BATCH_MAX_ITEMS point sets of one mechanism, without a server: the work
+ * list lives in a fixed device array of the library (about 5 KB per device,
+ * held until the process ends), written by a setup kernel on `stream` (no
+ * memset, no host-to-device copy).  Calls that overlap on one device race for that
  * array: issue them on one stream, or order them.
  * ------------------------------------------------------------------------ */
 #define KX_BATCH_MAX_ITEMS 32

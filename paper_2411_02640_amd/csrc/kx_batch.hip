@@ -1,11 +1,11 @@
 // kx_batch.hip -- production rates (and transport) of several point sets of
 // one mechanism in one launch sequence, with no allocation.
 //
-// The batch kernels the request server runs take their work list and tile
-// counters from device memory.  Here that memory is a file-scope device array,
-// `scratch`, of fixed size: a setup kernel writes the work list (from its
-// by-value argument) and zeroes the counters, then the rates batch kernel and,
-// if asked for, the transport batch kernel run over it.  No device or pinned
+// The batch kernels the request server runs for big batches (one workgroup
+// per tile) take their work list from device memory.  Here that memory is a
+// file-scope device array, `scratch`, of fixed size: a setup kernel writes the
+// work list (from its by-value argument), then the rates kernel and, if asked
+// for, the transport kernel run over it with grids of the host's tile counts.  No device or pinned
 // memory is allocated and no host-to-device copy is made, so the call can be
 // captured into a HIP graph or issued from a loop that must not allocate.
 // Every call on a device uses that device's one copy of the array.
@@ -19,10 +19,8 @@
 namespace kx {
 namespace {
 
-// The work list followed by the tile counters, 256-byte aligned.
-constexpr size_t kCounterOffset = (sizeof(WorkList) + 255) & ~size_t(255);
-constexpr size_t kScratchBytes = kCounterOffset + 256;
-static_assert(kBatchCounters * sizeof(int) <= 256, "counters fit their 256-byte slot");
+// The work list, 256-byte aligned.
+constexpr size_t kScratchBytes = (sizeof(WorkList) + 255) & ~size_t(255);
 
 __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
@@ -41,8 +39,8 @@ struct BatchArgs {
 };
 
 // Writes the work list (tile ranges of every item, in item order, as the
-// server cuts them) and zeroes the counters.  One thread.
-__global__ void batch_setup_kernel(BatchArgs a, WorkList *wl, int *counters)
+// server cuts them).  One thread.
+__global__ void batch_setup_kernel(BatchArgs a, WorkList *wl)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     wl->nitems = a.nitems;
@@ -56,7 +54,6 @@ __global__ void batch_setup_kernel(BatchArgs a, WorkList *wl, int *counters)
     }
     wl->start[0][a.nitems] = wl->ntiles[0] = tr;
     wl->start[1][a.nitems] = wl->ntiles[1] = tt;
-    for (int c = 0; c < kBatchCounters; ++c) counters[c] = 0;
 }
 
 kx_status scratch_address(int device, void **out)
@@ -144,17 +141,11 @@ extern "C" kx_status kx_batch_noalloc(const kx_mech *mech, int32_t ops, int32_t 
     kx_status st = scratch_address(mech->device, &base);
     if (st != KX_OK) return st;
     WorkList *wl = static_cast<WorkList *>(base);
-    int *counters = reinterpret_cast<int *>(static_cast<unsigned char *>(base) + kCounterOffset);
-    st = prepare_rates_batch(mech->dev, precision);
-    if (st == KX_OK && tr) st = prepare_transport_batch(mech->dev, precision);
-    if (st != KX_OK) return st;
-    hipLaunchKernelGGL(batch_setup_kernel, dim3(1), dim3(64), 0, stream, a, wl, counters);
+    hipLaunchKernelGGL(batch_setup_kernel, dim3(1), dim3(64), 0, stream, a, wl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kx_batch_noalloc: setup kernel launch");
-    st = launch_rates_batch(mech->dev, wl, counters, precision, kRatesBatchGrid, stream);
-    if (st == KX_OK && tr)
-        st = launch_transport_batch(mech->dev, wl, counters + kXcds, precision,
-                                    kTransportBatchGrid, stream);
+    st = launch_rates_items(mech->dev, wl, tiles_r, precision, stream);
+    if (st == KX_OK && tr) st = launch_transport_items(mech->dev, wl, tiles_t, precision, stream);
     if (st != KX_OK) return st;
     return ok();
 }

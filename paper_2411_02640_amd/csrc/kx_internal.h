@@ -180,6 +180,30 @@ struct WorkList {
     WorkItem items[kMaxBatch];
 };
 
+// The item that holds tile t of op: the last item whose first tile is <= t.
+// A batch kernel takes its tiles in increasing order (within an XCD range), so
+// the search starts from the previous tile's item r -- amortised O(1) instead of
+// a walk over the items per tile (each step a dependent scalar load) -- and
+// restarts from item 0 when t lies before item r.
+__device__ __forceinline__ int work_item_of(const WorkList *wl, int op, int t, int r)
+{
+    if (wl->start[op][r] > t) r = 0;
+    while (r + 1 < wl->nitems && wl->start[op][r + 1] <= t) ++r;
+    return r;
+}
+
+// The same in one step for a kernel that runs one tile per workgroup: lane l
+// of each wave reads the first tile of item l + 1 and the wave counts the
+// items after the first whose first tile is <= t (a work list holds at most
+// kMaxBatch = 64 items).  Wave-uniform result.
+__device__ __forceinline__ int work_item_ballot(const WorkList *wl, int op, int t)
+{
+    const int l = (int)(threadIdx.x & 63);
+    const bool below = l + 1 < wl->nitems && wl->start[op][l + 1] <= t;
+    return __builtin_amdgcn_readfirstlane(__popcll(__builtin_amdgcn_ballot_w64(below)));
+}
+static_assert(kMaxBatch <= 64, "work_item_ballot covers the items with one wave");
+
 }  // namespace kx
 
 struct kx_mech {
@@ -220,6 +244,13 @@ int transport_tile_points(const MechDev &m, int precision);
 // prepare_rates_batch sets the kernel's dynamic-LDS limit (call it before
 // capturing a launch into a graph).
 kx_status prepare_rates_batch(const MechDev &m, int precision);
+// One workgroup per tile of the work list (`ntiles` = wl->ntiles[0] for rates,
+// wl->ntiles[1] for transport, known to the host that wrote the list); no
+// counters.
+kx_status launch_rates_items(const MechDev &m, const WorkList *wl, int64_t ntiles, int precision,
+                             hipStream_t s);
+kx_status launch_transport_items(const MechDev &m, const WorkList *wl, int64_t ntiles,
+                                 int precision, hipStream_t s);
 kx_status launch_rates_batch(const MechDev &m, const WorkList *wl, int *counter, int precision,
                              int grid, hipStream_t s);
 kx_status launch_transport_batch(const MechDev &m, const WorkList *wl, int *counter,

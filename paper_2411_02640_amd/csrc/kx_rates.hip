@@ -852,11 +852,18 @@ __global__ __launch_bounds__(kWave, SPL == 1 ? 3 : 2) void rates_kernel(MechDev 
 
 // Batched requests.  The batch's tiles are split into kXcds contiguous ranges,
 // one per XCD (workgroup b runs on XCD b mod kXcds); a workgroup takes tiles
-// of its own XCD's range from that range's counter, so neighbouring tiles --
+// of its own XCD's range from that range's counter (kTicketTiles consecutive
+// tiles per ticket), so neighbouring tiles --
 // which share cache lines of Y and wdot -- meet in the same L2 as in a direct
 // launch, and then helps with the other ranges in turn.  Every workgroup
 // exits after the last range is exhausted.  Tile t belongs to the last item
 // whose first tile is <= t.
+//
+// Tiles per ticket: a ticket's atomic returns after the wave's next memory
+// wait (the wait counter is in order), so each ticket costs the wave about one
+// atomic round trip; four tiles per ticket spread it.
+constexpr int kTicketTiles = 4;
+
 template <bool MIXED, int SPL, bool DIRECT>
 __global__ __launch_bounds__(kWave, SPL == 1 ? 3 : 2) void rates_batch_kernel(MechDev m,
                                                             const WorkList *__restrict__ wl,
@@ -864,19 +871,24 @@ __global__ __launch_bounds__(kWave, SPL == 1 ? 3 : 2) void rates_batch_kernel(Me
 {
     const int ntiles = wl->ntiles[0];
     const int x0 = (int)(blockIdx.x % kXcds);
+    int r = 0;  // item of the previous tile
     for (int step = 0; step < kXcds; ++step) {
         const int x = (x0 + step) % kXcds;
         const int lo = (int)((int64_t)ntiles * x / kXcds);
         const int hi = (int)((int64_t)ntiles * (x + 1) / kXcds);
         int tn = 0;
         if (threadIdx.x == 0) tn = atomicAdd(counter + x, 1);
+        int t0 = 0, k = kTicketTiles;  // tiles t0 .. t0 + kTicketTiles - 1 of a ticket
         for (;;) {
-            const int t = lo + __builtin_amdgcn_readfirstlane(tn);  // lane 0's ticket
+            if (k == kTicketTiles) {
+                t0 = lo + kTicketTiles * __builtin_amdgcn_readfirstlane(tn);  // lane 0's ticket
+                k = 0;
+                // the next ticket is taken now, so its round trip overlaps these tiles
+                if (t0 < hi && threadIdx.x == 0) tn = atomicAdd(counter + x, 1);
+            }
+            const int t = t0 + k++;
             if (t >= hi) break;
-            // the next ticket is taken now, so its round trip overlaps this tile
-            if (threadIdx.x == 0) tn = atomicAdd(counter + x, 1);
-            int r = 0;
-            while (r + 1 < wl->nitems && wl->start[0][r + 1] <= t) ++r;
+            r = work_item_of(wl, 0, t, r);
             const WorkItem it = wl->items[r];
             const int64_t i0 = (int64_t)(t - wl->start[0][r]) * tp;
             const int np = (int)min((int64_t)tp, it.n - i0);
@@ -885,6 +897,24 @@ __global__ __launch_bounds__(kWave, SPL == 1 ? 3 : 2) void rates_batch_kernel(Me
             rates_tile<MIXED, SPL, DIRECT>(lane, m, it.n, i0, np, tp, it.T, it.p, it.Y, it.wdot);
         }
     }
+}
+
+// Batched requests, one tile per workgroup (grid = the batch's tiles, mapped
+// to XCDs as in a direct launch; the item of tile t by work_item_ballot).
+// Persistent workgroups that take tickets measured about a tenth slower per
+// tile than this one-tile form.
+template <bool MIXED, int SPL, bool DIRECT>
+__global__ __launch_bounds__(kWave, SPL == 1 ? 3 : 2) void rates_items_kernel(
+    MechDev m, const WorkList *__restrict__ wl, int tp)
+{
+    const int ntiles = wl->ntiles[0];
+    const int t = (int)xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    const int r = work_item_ballot(wl, 0, t);
+    const WorkItem it = wl->items[r];
+    const int64_t i0 = (int64_t)(t - wl->start[0][r]) * tp;
+    const int np = (int)min((int64_t)tp, it.n - i0);
+    rates_tile<MIXED, SPL, DIRECT>(threadIdx.x, m, it.n, i0, np, tp, it.T, it.p, it.Y, it.wdot);
 }
 
 size_t rates_lds_bytes(const MechDev &m, int tp)
@@ -967,6 +997,41 @@ auto pick_batch(const MechDev &m, int precision)
     return precision == KX_MIXED ? pick(std::true_type{}) : pick(std::false_type{});
 }
 }  // namespace
+
+namespace {
+auto pick_items(const MechDev &m, int precision)
+{
+    const int spl = rates_spl(m);
+    auto pick = [&](auto mixed) {
+        constexpr bool M = decltype(mixed)::value;
+        return spl == 1
+                   ? pick_direct(rates_items_kernel<M, 1, true>, rates_items_kernel<M, 1, false>)
+                   : (spl == 2 ? pick_direct(rates_items_kernel<M, 2, true>,
+                                             rates_items_kernel<M, 2, false>)
+                               : pick_direct(rates_items_kernel<M, 4, true>,
+                                             rates_items_kernel<M, 4, false>));
+    };
+    return precision == KX_MIXED ? pick(std::true_type{}) : pick(std::false_type{});
+}
+}  // namespace
+
+kx_status launch_rates_items(const MechDev &m, const WorkList *wl, int64_t ntiles, int precision,
+                             hipStream_t s)
+{
+    if (ntiles <= 0) return ok();
+    if (ntiles > 0x7fffffff) return fail(KX_EINVAL, "production rates: too many tiles");
+    const int tp = rates_tile_points(m);
+    const size_t lds = rates_lds_bytes(m, tp);
+    if (lds > 160 * 1024)
+        return fail(KX_EUNSUPPORTED, "production rates: mechanism too large for LDS");
+    auto kern = pick_items(m, precision);
+    kx_status st = set_lds(kern, lds);
+    if (st != KX_OK) return st;
+    hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(kWave), lds, s, m, wl, tp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "rates items kernel launch");
+    return ok();
+}
 
 kx_status prepare_rates_batch(const MechDev &m, int precision)
 {

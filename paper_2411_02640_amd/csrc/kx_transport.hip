@@ -694,6 +694,7 @@ __global__ __launch_bounds__(kBlock) void transport_mfma_batch_kernel(
 {
     __shared__ int tile;
     const int ntiles = wl->ntiles[1];
+    int r = 0;  // item of the previous tile
     for (;;) {
         if (threadIdx.x == 0) tile = atomicAdd(counter, 1);
         __syncthreads();
@@ -702,14 +703,28 @@ __global__ __launch_bounds__(kBlock) void transport_mfma_batch_kernel(
         const int t = __builtin_amdgcn_readfirstlane(tile);
         __syncthreads();
         if (t >= ntiles) break;
-        int r = 0;
-        while (r + 1 < wl->nitems && wl->start[1][r + 1] <= t) ++r;
+        r = work_item_of(wl, 1, t, r);
         const WorkItem it = wl->items[r];
         int tid;
         asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
         transport_mfma_tile<F, NP, ORDER>(tid, m, it.n, (int64_t)(t - wl->start[1][r]) * NP, it.T,
                                           it.p, it.Y, it.mu, it.lam, it.Dmix);
     }
+}
+
+// Batched requests, one tile per workgroup (grid = the batch's transport
+// tiles).  Uniform per workgroup, so a workgroup past the last tile returns
+// before any barrier.
+template <class F, int NP, int ORDER>
+__global__ __launch_bounds__(kBlock) void transport_mfma_items_kernel(
+    MechDev m, const WorkList *__restrict__ wl)
+{
+    const int t = (int)blockIdx.x;
+    if (t >= wl->ntiles[1]) return;
+    const int r = work_item_ballot(wl, 1, t);
+    const WorkItem it = wl->items[r];
+    transport_mfma_tile<F, NP, ORDER>(threadIdx.x, m, it.n, (int64_t)(t - wl->start[1][r]) * NP,
+                                      it.T, it.p, it.Y, it.mu, it.lam, it.Dmix);
 }
 
 template <class F, int ORDER, int KIND, int P, int KB>
@@ -733,19 +748,31 @@ __global__ __launch_bounds__(kBlock) void transport_batch_kernel(MechDev m,
 {
     __shared__ int tile;
     const int ntiles = wl->ntiles[1];
+    int r = 0;  // item of the previous tile
     for (;;) {
         if (threadIdx.x == 0) tile = atomicAdd(counter, 1);
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(tile);  // wave-uniform
         __syncthreads();
         if (t >= ntiles) break;
-        int r = 0;
-        while (r + 1 < wl->nitems && wl->start[1][r + 1] <= t) ++r;
+        r = work_item_of(wl, 1, t, r);
         const WorkItem it = wl->items[r];
         transport_tile<F, ORDER, KIND, P, KB>(m, it.n,
                                               (int64_t)(t - wl->start[1][r]) * kBlock * P, it.T,
                                               it.p, it.Y, it.mu, it.lam, it.Dmix);
     }
+}
+
+template <class F, int ORDER, int KIND, int P, int KB>
+__global__ __launch_bounds__(kBlock) void transport_items_kernel(MechDev m,
+                                                                 const WorkList *__restrict__ wl)
+{
+    const int t = (int)blockIdx.x;
+    if (t >= wl->ntiles[1]) return;
+    const int r = work_item_ballot(wl, 1, t);
+    const WorkItem it = wl->items[r];
+    transport_tile<F, ORDER, KIND, P, KB>(m, it.n, (int64_t)(t - wl->start[1][r]) * kBlock * P,
+                                          it.T, it.p, it.Y, it.mu, it.lam, it.Dmix);
 }
 
 __global__ void zero_kernel(int *p, int count)
@@ -824,25 +851,28 @@ bool use_mfma(const MechDev &m)
     return m.diff_kind == 1 && m.gfrag != nullptr && m.ns >= kMfmaMinSpecies;
 }
 
-template <class F, bool BATCH> const void *mfma_kernel(const MechDev &m, int np)
+// FORM 0: direct launch, 1: work-stealing batch, 2: one tile per workgroup
+template <class F, int FORM> const void *mfma_kernel(const MechDev &m, int np)
 {
     const bool o5 = m.fit_order == 5;
 #define KX_PICK(NPV)                                                                        \
-    (BATCH ? (o5 ? (const void *)transport_mfma_batch_kernel<F, NPV, 5>                     \
-                 : (const void *)transport_mfma_batch_kernel<F, NPV, 0>)                    \
-           : (o5 ? (const void *)transport_mfma_kernel<F, NPV, 5>                           \
-                 : (const void *)transport_mfma_kernel<F, NPV, 0>))
+    (FORM == 1 ? (o5 ? (const void *)transport_mfma_batch_kernel<F, NPV, 5>                 \
+                     : (const void *)transport_mfma_batch_kernel<F, NPV, 0>)                \
+     : FORM == 2 ? (o5 ? (const void *)transport_mfma_items_kernel<F, NPV, 5>               \
+                       : (const void *)transport_mfma_items_kernel<F, NPV, 0>)              \
+                 : (o5 ? (const void *)transport_mfma_kernel<F, NPV, 5>                     \
+                       : (const void *)transport_mfma_kernel<F, NPV, 0>))
     return np == 64 ? KX_PICK(64) : (np == 32 ? KX_PICK(32) : KX_PICK(16));
 #undef KX_PICK
 }
 
-template <class F, bool BATCH> kx_status mfma_prepare(const MechDev &m, size_t *lds)
+template <class F, int FORM> kx_status mfma_prepare(const MechDev &m, size_t *lds)
 {
     const int np = mfma_np<F>(m);
     *lds = mfma_lds<F>(m, np);
     if (*lds > 160 * 1024)
         return fail(KX_EUNSUPPORTED, "transport: mechanism too large for the LDS tiles");
-    hipError_t e = hipFuncSetAttribute(mfma_kernel<F, BATCH>(m, np),
+    hipError_t e = hipFuncSetAttribute(mfma_kernel<F, FORM>(m, np),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)*lds);
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute (transport)");
     return KX_OK;
@@ -860,8 +890,8 @@ kx_status prepare_transport_batch(const MechDev &m, int precision)
 {
     if (!use_mfma(m)) return KX_OK;
     size_t lds = 0;
-    return precision == KX_MIXED ? mfma_prepare<float, true>(m, &lds)
-                                 : mfma_prepare<double, true>(m, &lds);
+    return precision == KX_MIXED ? mfma_prepare<float, 1>(m, &lds)
+                                 : mfma_prepare<double, 1>(m, &lds);
 }
 
 namespace {
@@ -890,14 +920,14 @@ kx_status go_transport(const MechDev &m, int64_t n, const double *T, const doubl
     }
     if (use_mfma(m)) {
         size_t lds = 0;
-        kx_status st = mfma_prepare<F, false>(m, &lds);
+        kx_status st = mfma_prepare<F, 0>(m, &lds);
         if (st != KX_OK) return st;
         const int np = mfma_np<F>(m);
         const int64_t nblk = (n + np - 1) / np;
         if (nblk > 0x7fffffff) return fail(KX_EINVAL, "transport: n too large");
         void *args[] = {(void *)&m, (void *)&n, (void *)&T, (void *)&p, (void *)&Y,
                         (void *)&mu, (void *)&lam, (void *)&Dmix};
-        hipError_t e = hipLaunchKernel(mfma_kernel<F, false>(m, np), dim3((unsigned)nblk),
+        hipError_t e = hipLaunchKernel(mfma_kernel<F, 0>(m, np), dim3((unsigned)nblk),
                                        dim3(kBlock), args, lds, s);
         if (e != hipSuccess) return hip_fail(e, "transport kernel launch");
         return ok();
@@ -925,7 +955,7 @@ kx_status go_transport_batch(const MechDev &m, const WorkList *wl, int *counter,
         const int np = mfma_np<F>(m);
         const size_t lds = mfma_lds<F>(m, np);
         void *args[] = {(void *)&m, (void *)&wl, (void *)&counter};
-        hipError_t e = hipLaunchKernel(mfma_kernel<F, true>(m, np), dim3(grid), dim3(kBlock),
+        hipError_t e = hipLaunchKernel(mfma_kernel<F, 1>(m, np), dim3(grid), dim3(kBlock),
                                        args, lds, s);
         if (e != hipSuccess) return hip_fail(e, "transport batch kernel launch");
         return ok();
@@ -941,7 +971,41 @@ kx_status go_transport_batch(const MechDev &m, const WorkList *wl, int *counter,
     if (e != hipSuccess) return hip_fail(e, "transport batch kernel launch");
     return ok();
 }
+template <class F>
+kx_status go_transport_items(const MechDev &m, const WorkList *wl, int64_t ntiles, hipStream_t s)
+{
+    if (ntiles <= 0) return ok();
+    if (ntiles > 0x7fffffff) return fail(KX_EINVAL, "transport: too many tiles");
+    if (use_mfma(m)) {
+        size_t lds = 0;
+        kx_status st = mfma_prepare<F, 2>(m, &lds);
+        if (st != KX_OK) return st;
+        const int np = mfma_np<F>(m);
+        void *args[] = {(void *)&m, (void *)&wl};
+        hipError_t e = hipLaunchKernel(mfma_kernel<F, 2>(m, np), dim3((unsigned)ntiles),
+                                       dim3(kBlock), args, lds, s);
+        if (e != hipSuccess) return hip_fail(e, "transport items kernel launch");
+        return ok();
+    }
+    constexpr int PP = TransportShape<F>::P, KB = TransportShape<F>::KB;
+    const bool o5 = m.fit_order == 5;
+    auto k = m.diff_kind == 0 ? (o5 ? transport_items_kernel<F, 5, 0, PP, KB>
+                                    : transport_items_kernel<F, 0, 0, PP, KB>)
+                              : (o5 ? transport_items_kernel<F, 5, 1, PP, KB>
+                                    : transport_items_kernel<F, 0, 1, PP, KB>);
+    hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(kBlock), 0, s, m, wl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "transport items kernel launch");
+    return ok();
+}
 }  // namespace
+
+kx_status launch_transport_items(const MechDev &m, const WorkList *wl, int64_t ntiles,
+                                 int precision, hipStream_t s)
+{
+    if (precision == KX_MIXED) return go_transport_items<float>(m, wl, ntiles, s);
+    return go_transport_items<double>(m, wl, ntiles, s);
+}
 
 kx_status launch_transport(const kx_mech *mech, int64_t n, const double *T, const double *p,
                            const double *Y, double *mu, double *lam, double *Dmix,
