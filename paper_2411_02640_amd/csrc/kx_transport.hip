@@ -77,11 +77,14 @@ template <> __device__ __forceinline__ float rsqrt_acc<float>(float x) { return 
 template <class F> __device__ __forceinline__ F rcp_acc(F x);
 template <> __device__ __forceinline__ double rcp_acc<double>(double x) { return krcp(x); }
 template <> __device__ __forceinline__ float rcp_acc<float>(float x) { return 1.0f / x; }
-// Reciprocal in the matrix-core kernel's epilogue: FP64 as rcp_acc; FP32 from
-// v_rcp_f32 with one Newton step (about 1 ulp, without the IEEE division's
-// scaling and fix-up steps).
+// Reciprocals in the matrix-core kernel, where each result is a term of a sum
+// of positive terms or a factor of one output: FP64 from v_rcp_f64 with one
+// Newton step (about 2^-48 relative; FP64 vector instructions also cost the
+// matrix pipe, so the second step is left out), FP32 from v_rcp_f32 with one
+// Newton step (about 1 ulp, without the IEEE division's scaling and fix-up
+// steps).
 template <class F> __device__ __forceinline__ F rcp_mfma(F x);
-template <> __device__ __forceinline__ double rcp_mfma<double>(double x) { return krcp(x); }
+template <> __device__ __forceinline__ double rcp_mfma<double>(double x) { return krcp1(x); }
 template <> __device__ __forceinline__ float rcp_mfma<float>(float x)
 {
     const float r = __builtin_amdgcn_rcpf(x);
@@ -516,7 +519,7 @@ __device__ __forceinline__ void transport_mfma_tile(int tid, const MechDev &m, i
             const F lj = NP == 64 ? horner<ORDER>(Tb::cond(m) + j * order, (F)up, order)
                                   : horner_v<ORDER>(Tb::cond(m) + j * order, (F)up, order);
             s1 = fma(X, (double)lj, s1);
-            s2 = fma(X, (double)rcp_acc(lj), s2);
+            s2 = fma(X, (double)rcp_mfma(lj), s2);
             const F ej = NP == 64 ? horner<ORDER>(Tb::visc(m) + j * order, (F)up, order)
                                   : horner_v<ORDER>(Tb::visc(m) + j * order, (F)up, order);
             Xs[(size_t)j * LD + p] = (F)X;
@@ -655,7 +658,7 @@ __device__ __forceinline__ void transport_mfma_tile(int tid, const MechDev &m, i
                     const F gk = horner_v<ORDER>(Tb::ddiag(m) + k * order, (F)P.u, order);
                     D = 1.0 / ((double)gk * P.pr);
                 } else {
-                    D = (P.wbar - Zk * wk[e]) * krcp(P.wbar * (double)S[nb][e] * P.pr);
+                    D = (P.wbar - Zk * wk[e]) * krcp1(P.wbar * (double)S[nb][e] * P.pr);
                 }
                 if (i < n) Dmix[(int64_t)k * n + i] = D;
             }
