@@ -117,6 +117,10 @@ struct MechDev {
     const DevEff *eff;         // [neff]
     const DevPlog *plog;       // [nplog]
     const DevSpecies *sp;      // [ns]
+    const double *gsoa;        // [ceil(ns/64)][16][64] the rates kernel's species data by
+                               // field in blocks of 64 species, so that the lanes of a
+                               // wave read one contiguous 512-byte row: field 0..6 g_lo,
+                               // 7..13 g_hi, 14 T_mid, 15 1/W of species 64 blk + lane
     const int32_t *gpos;       // [nchunks] groups of eight +q entries of the gather
     const int32_t *gneg;       // [nchunks] groups of eight -q entries
     const int32_t *goff;       // [nchunks] first group of each chunk

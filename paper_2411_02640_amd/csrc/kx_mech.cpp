@@ -559,6 +559,16 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
         s.inv_W = 1.0 / W[k];
         spv[k] = s;
     }
+    std::vector<double> gsoa((size_t)((ns + kWave - 1) / kWave) * 16 * kWave, 0.0);
+    for (int k = 0; k < ns; ++k) {
+        double *g = gsoa.data() + (size_t)(k / kWave) * 16 * kWave + k % kWave;
+        for (int e = 0; e < 7; ++e) {
+            g[e * kWave] = spv[k].g_lo[e];
+            g[(7 + e) * kWave] = spv[k].g_hi[e];
+        }
+        g[14 * kWave] = spv[k].t_mid;
+        g[15 * kWave] = spv[k].inv_W;
+    }
 
     // ---- transport tables
     const int nkb = (ns + kKB - 1) / kKB;
@@ -620,6 +630,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     const size_t o_rxn = add_vec(b, rx), o_aux = add_vec(b, aux), o_eff = add_vec(b, eff);
     const size_t o_plog = add_vec(b, plog);
     const size_t o_sp = add_vec(b, spv), o_gpos = add_vec(b, gpos), o_gneg = add_vec(b, gneg);
+    const size_t o_gsoa = add_vec(b, gsoa);
     const size_t o_goff = add_vec(b, goff);
     const size_t o_gent = add_vec(b, gent);
     const size_t o_mgrp = add_vec(b, mgrp), o_moff = add_vec(b, moff), o_ment = add_vec(b, ment);
@@ -682,6 +693,7 @@ kx_status build_mech(const kx_mech_desc *d, int device, bool host_only, kx_mech 
     v.eff = (const DevEff *)at(o_eff);
     v.plog = (const DevPlog *)at(o_plog);
     v.sp = (const DevSpecies *)at(o_sp);
+    v.gsoa = (const double *)at(o_gsoa);
     v.gpos = (const int32_t *)at(o_gpos);
     v.gneg = (const int32_t *)at(o_gneg);
     v.goff = (const int32_t *)at(o_goff);
@@ -727,6 +739,7 @@ bool rebase_tables(const kx_mech *m, const void *base, MechDev *out)
     v.f = m->dev.f ? reinterpret_cast<decltype(v.f)>(nb + (reinterpret_cast<const char *>(m->dev.f) - old)) \
                    : nullptr
     KX_REBASE(rxn); KX_REBASE(aux); KX_REBASE(eff); KX_REBASE(plog); KX_REBASE(sp);
+    KX_REBASE(gsoa);
     KX_REBASE(gpos); KX_REBASE(gneg); KX_REBASE(goff); KX_REBASE(gent);
     KX_REBASE(gmgrp); KX_REBASE(gmoff); KX_REBASE(gment);
     KX_REBASE(W); KX_REBASE(visc); KX_REBASE(cond); KX_REBASE(wq); KX_REBASE(wilke);

@@ -676,7 +676,7 @@ __device__ __forceinline__ void rates_tile(int lane, const MechDev &m, int64_t l
 #pragma unroll
             for (int u = 0; u < kLd; ++u) {
                 const int k = k0 + u * NGW;
-                iw[u] = k < ns ? m.sp[k].inv_W : 0.0;
+                iw[u] = k < ns ? m.gsoa[((size_t)(k / kWave) * 16 + 15) * kWave + k % kWave] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < kLd; ++u) {
@@ -731,15 +731,19 @@ __device__ __forceinline__ void rates_tile(int lane, const MechDev &m, int64_t l
             if (k < ns) {
                 // both temperature ranges' coefficients are read once per step
                 // and selected per point (one read per point would cost the
-                // vector-memory unit four times as many loads)
-                const DevSpecies &S = m.sp[k];
+                // vector-memory unit four times as many loads), from the
+                // by-field table (a wave's read is one contiguous row)
+                const double *gs = m.gsoa + (size_t)s * 16 * kWave + lane;
+                // the same rows every step: read them per step (kept in
+                // registers across the steps they would cost spills)
+                asm volatile("" : "+v"(gs));
                 double glo[7], ghi[7];
 #pragma unroll
                 for (int e = 0; e < 7; ++e) {
-                    glo[e] = S.g_lo[e];
-                    ghi[e] = S.g_hi[e];
+                    glo[e] = gs[e * kWave];
+                    ghi[e] = gs[(7 + e) * kWave];
                 }
-                const double tmid = S.t_mid, iw = S.inv_W;
+                const double tmid = gs[14 * kWave], iw = gs[15 * kWave];
 #pragma unroll
                 for (int j = 0; j < PS; ++j) {
                     const PointConst &q = ps[j];
