@@ -300,3 +300,58 @@ def test_inputs_ready_event(kx, mechs):
         srv.release(t)
     finally:
         srv.close()
+
+
+def test_big_batches_one_tile_kernels(kx, mechs):
+    """Batches of 2^17 points or more run the one-workgroup-per-tile kernels
+    (no graph).  Three requests per (mechanism, precision) group, 140 015 points
+    in all, queued behind a request that holds the arena so that each group
+    forms one batch: the 9-species mechanism (vector-ALU transport), a
+    53-species mechanism with fits of D_kj (vector-ALU transport) and syn53
+    (matrix-core transport), both precisions.  Every output equals the direct
+    call bit for bit, and every group ran without its graph."""
+    mdl = I.make_mechanism(I.MechSpec(53, 266, 30, 0, 29, seed=53325, diff_fit_kind=0,
+                                      name="syn53d"))
+    ms = {"syn9": mechs["syn9"], "syn53": mechs["syn53"], "syn53d": (kx.Mechanism(mdl, 0), mdl)}
+    sizes = [70001, 50003, 20011]
+    assert sum(sizes) >= 1 << 17
+    cases = []
+    for name in ms:
+        for prec in ("fp64", "mixed"):
+            for j, n in enumerate(sizes):
+                (Td, pd, Yd), _ = _inputs(ms[name][1]["n_species"], n, 900 + 10 * len(cases) + j)
+                cases.append((name, n, prec, Td, pd, Yd))
+    ns53 = ms["syn53"][1]["n_species"]
+    total = sum(_footprint(ms[c[0]][1]["n_species"], c[1], True) for c in cases)
+    n_blk = -(-total // (8 * ns53))
+    (Tb, pb, Yb), _ = _inputs(ns53, n_blk, 899)
+    res = _resident(*(dm for dm, _ in ms.values()))
+    budget = max(total, _footprint(ns53, n_blk, False)) + res
+    srv = kx.Server(0, hbm_budget=budget, max_slots=64)
+    try:
+        for dm, _ in ms.values():
+            srv.add_mech(dm)
+        blocker = srv.submit(ms["syn53"][0], Tb, pb, Yb)
+        assert srv.wait(blocker, WAIT_S)["state"] == "done"
+        reqs = [(srv.submit(ms[c[0]][0], *c[3:], transport=True, precision=c[2]), c)
+                for c in cases]
+        assert srv.stats()["queued"] == len(cases)
+        before = srv.stats()
+        srv.release(blocker)
+        for t, (name, n, prec, Td, pd, Yd) in reqs:
+            _say("request", t, name, "n =", n, prec)
+            r = srv.wait(t, WAIT_S)
+            assert r["state"] == "done", r
+            got = srv.outputs(t)
+            ref = _direct(kx, ms[name][0], Td, pd, Yd, True, prec)
+            for g, e, what in zip(got, ref, ("wdot", "mu", "lambda", "Dmix")):
+                assert _same(g, e), (name, n, prec, what)
+            srv.release(t)
+        st = srv.stats()
+        _say(st)
+        batches = st["batches"] - before["batches"]
+        graphs = st["graph_launches"] - before["graph_launches"]
+        assert batches == 6 and graphs == 0, (batches, graphs)
+    finally:
+        srv.close()
+        ms["syn53d"][0].close()
