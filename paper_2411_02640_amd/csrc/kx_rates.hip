@@ -1,34 +1,40 @@
 // kx_rates.hip -- species net production rates on gfx950.
 //
 // Work decomposition.  A workgroup is one wave that owns a tile of `tp`
-// consecutive points: the tile of Y is staged through LDS with coalesced row
-// loads, and the same LDS tile later receives wdot and is written back with
-// coalesced row stores.  The wave takes the tile's points two at a time and
-// runs three phases, with lanes spread over species, then (reaction, point)
-// pairs, then species again:
+// consecutive points (8; 2 above 128 species): the tile's T and p are read
+// first, the tile of Y is staged through LDS with coalesced row loads, and the
+// same LDS tile later receives wdot and is written back with coalesced row
+// stores.  The wave takes the tile's points four at a time (two above 128
+// species) and runs three phases per step, with lanes spread over species,
+// then (reaction, point) pairs, then species again:
 //
-//  1. species (lane = k, both points): C_k, the Gibbs energy g_k = G_k/RT of
-//     eq:Ck (range by T_mid), a_k = (p_atm/RT) exp(-g_k) and b_k = C_k / a_k
-//     into LDS as one 16-byte pair per species and point.  With these,
-//     prod_k C_k^nu' = A' B' and prod_k C_k^nu'' / K_c = A' B''
+//  1. species (lane = k, every point of the step): C_k, the Gibbs energy
+//     g_k = G_k/RT of eq:Ck (range by T_mid; both ranges' coefficients read
+//     once per step from a by-field table), a_k = (p_atm/RT) exp(-g_k) and
+//     b_k = C_k / a_k into LDS as one 16-byte pair per species and point.
+//     With these, prod_k C_k^nu' = A' B' and prod_k C_k^nu'' / K_c = A' B''
 //     (A' = prod_reac a^nu', B' = prod_reac b^nu', B'' = prod_prod b^nu''), since
 //     K_c = prod_k a_k^(nu''-nu') by eq:K_p and K_c = K_p (p_atm/RT)^(sum nu).
 //     So K_c needs one exponential per species instead of one per reaction and
 //     the rate of progress needs no division:
 //         R_i = c_i k_f A' (B' - B'')                   (eq:r_i, eq:c_i)
 //     and B' - B'' is the near-equilibrium difference, formed in FP64.
-//  2. reactions (lanes 2r, 2r+1 = reaction r at the two points): k_f
-//     (eq:arrhenius, with the beta = E_R = 0 shortcut of eq:k_f), [X]_i, the
-//     Lindemann / Troe factor (eq:blend) and R_i into LDS, one chunk of
-//     reactions at a time.  Reactions are sorted heaviest type first, so the
-//     falloff code runs for 32 reactions x 2 points per 64-lane iteration.
-//     Each reaction side is three molecule slots (unused ones hit a dummy
-//     species with a = b = 1), so the products A', B', B'' are branch-free.
-//  3. species (lane = k, both points): wdot_k = sum_i nu_ki R_i gathered from
-//     species-major lists of +R and -R entries (a net |nu| of 2 or 3 is listed
-//     that many times); one 16-byte LDS read returns R_i at both points.  The
-//     summation order is fixed, so results are deterministic; the mixed path
-//     accumulates with Neumaier compensation.
+//  2. reactions (lanes 2r, 2r+1 = reaction r, each at half of the step's
+//     points): k_f (eq:arrhenius, with the beta = E_R = 0 shortcut of eq:k_f),
+//     [X]_i, the Lindemann / Troe factor (eq:blend) and R_i into LDS, one
+//     chunk of reactions at a time; the 48-byte record is read and decoded
+//     once per two rates of progress, a third-body reaction's efficiency data
+//     loaded with it.  Reactions are sorted heaviest type first, so the
+//     falloff code runs for 32 reactions per 64-lane iteration.  Each reaction
+//     side is three molecule slots (unused ones hit a dummy species with
+//     a = b = 1), so the products A', B', B'' are branch-free.
+//  3. species (lane = k, every point of the step): wdot_k = sum_i nu_ki R_i
+//     gathered from species-major lists of R slots (a net |nu| of 2 or 3 is
+//     listed that many times); one 16-byte LDS read returns R_i at two points.
+//     With four points per step a species has one list, each entry's sign in
+//     its bit 31; with two, separate +R and -R lists.  The summation order is
+//     fixed, so results are deterministic; the mixed path adds each two list
+//     groups' sum with one Neumaier-compensated step.
 #include <float.h>
 
 #include <type_traits>
