@@ -1,22 +1,27 @@
 // kx_transport.hip -- mixture-averaged transport and mixture thermo on gfx950.
 //
-// Each lane evaluates P grid points.  Every mechanism constant is
-// wave-uniform, so it is read with scalar loads into scalar registers and used
-// directly as an instruction operand; one fetched coefficient serves the P
-// points of all 64 lanes.  The quadratic sums run over a block of KB species k
-// held in registers while j streams over all species; X_j is recomputed from
-// Y_j (a coalesced re-read) instead of being held per lane.
-//
+// Three evaluations of the same sums (App. A.3):
+//  * the matrix-core kernel (tables holding fits of 1/D_kj and at least 24
+//    species): the pair sums as products of fixed matrices with per-point
+//    stacks on 16x16x4 MFMAs, described where it is defined below;
+//  * the vector-ALU kernel (tables of D_kj fits, or fewer species): each lane
+//    evaluates P grid points, every mechanism constant is wave-uniform and read
+//    with scalar loads into scalar registers, used directly as an instruction
+//    operand (one fetched coefficient serves the P points of all 64 lanes); the
+//    quadratic sums run over a block of KB species k held in registers while j
+//    streams over all species, and X_j is recomputed from Y_j (a coalesced
+//    re-read) instead of being held per lane;
+//  * the symmetric evaluation of D_kj fits (KX_DKJ_SYMMETRIC, §2.2.2 / §2.3.2),
+//    described where it is defined below.
+// Common to them:
 //  * pure species (App. A.3 "Polynomial fits"): eta_k, lambda_k, D_kj as
 //    polynomials in u = (ln T - L0)/h (Horner), D_kj divided by p/p_atm;
 //  * Wilke / Bird viscosity with phi_kj = c1_kj (1 + sigma_k rho_j)^2, where
 //    c1_kj = (8 (1 + W_k/W_j))^(-1/2), sigma_k = sqrt(eta_k) / W_k^(1/4) and
 //    rho_j = W_j^(1/4) / sqrt(eta_j): (W_j/W_k)^(1/4) separates into
 //    per-species factors, so each pair reads one coefficient;
-//  * Mathur conductivity; eq:mix_diff for D_km with the full (k, j) matrix
-//    evaluated (no symmetric reuse, so only the KB accumulators are live),
-//    1/D_kj by v_rcp_f64 and one Newton step (each term of this positive
-//    sum then carries about 2^-48 relative error).
+//  * Mathur conductivity; eq:mix_diff for D_km, the reciprocals of the
+//    positive sums by v_rcp_f64 and one Newton step (about 2^-48 relative).
 #include <float.h>
 
 #include <type_traits>
