@@ -444,17 +444,19 @@ struct MfmaPoint {
 template <class F, int NP>
 __host__ __device__ constexpr size_t mfma_lds_bytes_np(int kstep)
 {
-    // X and rho tiles, point table, partial sums (4 per (group, point) in the
-    // prologue, 16 per point for mu)
+    // X and rho tiles, point table, partial sums (per (group, point) in the
+    // prologue: 3 sums, and the normalisation sum in a slot of its own; 16 per
+    // point for mu)
     return 2 * (size_t)(4 * kstep) * (NP + kMfmaPad) * sizeof(F) + NP * sizeof(MfmaPoint) +
-           (size_t)((kBlock / NP) * 3 > 16 ? (kBlock / NP) * 3 : 16) * NP * sizeof(double);
+           (size_t)4 * kBlock * sizeof(double);
 }
 
 // `tid` is threadIdx.x; the batch kernel passes it through an opaque move in
 // each trip of its tile loop, so that the tile's lane-dependent addresses are
 // not hoisted out of the loop (kept live across tiles they cost the kernel
-// its occupancy).
-template <class F, int NP, int ORDER>
+// its occupancy).  LOOP: the workgroup takes another tile after this one (its
+// LDS is then reused).
+template <class F, int NP, int ORDER, bool LOOP>
 __device__ __forceinline__ void transport_mfma_tile(int tid, const MechDev &m, int64_t n,
                                                     int64_t base,
                                                     const double *__restrict__ T,
@@ -478,7 +480,8 @@ __device__ __forceinline__ void transport_mfma_tile(int tid, const MechDev &m, i
     F *Xs = reinterpret_cast<F *>(smem_d);
     F *Rs = Xs + (size_t)Kp * LD;
     MfmaPoint *pt = reinterpret_cast<MfmaPoint *>(Rs + (size_t)Kp * LD);
-    double *part = reinterpret_cast<double *>(pt + NP);
+    double *part = reinterpret_cast<double *>(pt + NP);  // [NG][3][NP], then mu's [16][NP]
+    double *part1 = part + 3 * kBlock;                   // [NG][NP]: sum of Y_j / W_j
 
     // ---- prologue: thread = (point p, species group g)
     const int p = t % NP;
@@ -506,13 +509,20 @@ __device__ __forceinline__ void transport_mfma_tile(int tid, const MechDev &m, i
             s += yw[q];
         }
     }
-    part[g * NP + p] = s;
+    part1[g * NP + p] = s;
     __syncthreads();
     double sYW = 0.0;
 #pragma unroll
-    for (int q = 0; q < NG; ++q) sYW += part[q * NP + p];
+    for (int q = 0; q < NG; ++q) sYW += part1[q * NP + p];
     const double xf = krcp(sYW);
-    __syncthreads();  // partials are reused below
+    if (t < NP) {
+        MfmaPoint P;
+        P.u = up;
+        P.xf = xf;
+        P.wbar = 0.0;  // the epilogue adds the group partials
+        P.pr = Pp[ip] * (1.0 / kPatm);
+        pt[p] = P;
+    }
     double wb = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
     for (int q = 0; q < kJmax; ++q) {
@@ -538,23 +548,15 @@ __device__ __forceinline__ void transport_mfma_tile(int tid, const MechDev &m, i
     part[(g * 3 + 1) * NP + p] = s1;
     part[(g * 3 + 2) * NP + p] = s2;
     __syncthreads();
-    if (t < NP) {
-        double W = 0.0, a1 = 0.0, a2 = 0.0;
+    if (t < NP && base + p < n) {
+        double a1 = 0.0, a2 = 0.0;
 #pragma unroll
         for (int q = 0; q < NG; ++q) {
-            W += part[(q * 3 + 0) * NP + p];
             a1 += part[(q * 3 + 1) * NP + p];
             a2 += part[(q * 3 + 2) * NP + p];
         }
-        MfmaPoint P;
-        P.u = up;
-        P.xf = xf;
-        P.wbar = W;
-        P.pr = Pp[ip] * (1.0 / kPatm);
-        pt[p] = P;
-        if (base + p < n) lam[base + p] = 0.5 * (a1 + krcp(a2));  // Mathur
+        lam[base + p] = 0.5 * (a1 + krcp(a2));  // Mathur
     }
-    __syncthreads();
 
     // ---- products on the matrix cores: wave w takes row blocks w, w + 4, ...
     const int col = lane & 15, jr = lane >> 4;
@@ -643,6 +645,9 @@ __device__ __forceinline__ void transport_mfma_tile(int tid, const MechDev &m, i
             const int pp = 16 * nb + col;
             const int64_t i = base + pp;
             const MfmaPoint P = pt[pp];
+            double wbar = 0.0;
+#pragma unroll
+            for (int q = 0; q < NG; ++q) wbar += part[(q * 3 + 0) * NP + pp];
             double yk[4];
             if (!F64) {
                 const int64_t ic = min(i, n - 1);
@@ -663,7 +668,7 @@ __device__ __forceinline__ void transport_mfma_tile(int tid, const MechDev &m, i
                     const F gk = horner_v<ORDER>(Tb::ddiag(m) + k * order, (F)P.u, order);
                     D = 1.0 / ((double)gk * P.pr);
                 } else {
-                    D = (P.wbar - Zk * wk[e]) * krcp1(P.wbar * (double)S[nb][e] * P.pr);
+                    D = (wbar - Zk * wk[e]) * krcp1(wbar * (double)S[nb][e] * P.pr);
                 }
                 if (i < n) Dmix[(int64_t)k * n + i] = D;
             }
@@ -680,7 +685,7 @@ __device__ __forceinline__ void transport_mfma_tile(int tid, const MechDev &m, i
         for (int q = 0; q < 16; ++q) v += part[q * NP + t];
         mu[base + t] = v;
     }
-    __syncthreads();  // LDS reused by the next tile
+    if (LOOP) __syncthreads();  // LDS reused by the next tile
 }
 
 template <class F, int NP, int ORDER>
@@ -692,12 +697,14 @@ __global__ __launch_bounds__(kBlock) void transport_mfma_kernel(MechDev m, int64
                                                                 double *__restrict__ lam,
                                                                 double *__restrict__ Dmix)
 {
-    transport_mfma_tile<F, NP, ORDER>(threadIdx.x, m, n, (int64_t)blockIdx.x * NP, T, Pp, Y, mu,
+    transport_mfma_tile<F, NP, ORDER, false>(threadIdx.x, m, n, (int64_t)blockIdx.x * NP, T, Pp, Y, mu,
                                       lam, Dmix);
 }
 
+// At most 256 VGPRs (two waves per SIMD): the FP64 form for fits of any order
+// would otherwise take 258 and run one wave per SIMD.
 template <class F, int NP, int ORDER>
-__global__ __launch_bounds__(kBlock) void transport_mfma_batch_kernel(
+__global__ __launch_bounds__(kBlock, 2) void transport_mfma_batch_kernel(
     MechDev m, const WorkList *__restrict__ wl, int *__restrict__ counter)
 {
     __shared__ int tile;
@@ -715,7 +722,7 @@ __global__ __launch_bounds__(kBlock) void transport_mfma_batch_kernel(
         const WorkItem it = wl->items[r];
         int tid;
         asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
-        transport_mfma_tile<F, NP, ORDER>(tid, m, it.n, (int64_t)(t - wl->start[1][r]) * NP, it.T,
+        transport_mfma_tile<F, NP, ORDER, true>(tid, m, it.n, (int64_t)(t - wl->start[1][r]) * NP, it.T,
                                           it.p, it.Y, it.mu, it.lam, it.Dmix);
     }
 }
@@ -731,7 +738,7 @@ __global__ __launch_bounds__(kBlock) void transport_mfma_items_kernel(
     if (t >= wl->ntiles[1]) return;
     const int r = work_item_ballot(wl, 1, t);
     const WorkItem it = wl->items[r];
-    transport_mfma_tile<F, NP, ORDER>(threadIdx.x, m, it.n, (int64_t)(t - wl->start[1][r]) * NP,
+    transport_mfma_tile<F, NP, ORDER, false>(threadIdx.x, m, it.n, (int64_t)(t - wl->start[1][r]) * NP,
                                       it.T, it.p, it.Y, it.mu, it.lam, it.Dmix);
 }
 
