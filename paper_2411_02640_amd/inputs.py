@@ -241,7 +241,8 @@ def transport_fit_grid():
     return np.exp(np.linspace(math.log(T_FIT_LO), math.log(T_FIT_HI), 64))
 
 
-def transport_fits(W, sigma_cm, eps, zrot298, natoms, cp_over_r, diff_fit_kind: int = 1):
+def transport_fits(W, sigma_cm, eps, zrot298, natoms, cp_over_r, diff_fit_kind: int = 1,
+                   order: int = FIT_ORDER):
     """ln T polynomial fits (App. A.3 "Polynomial fits", in the centred variable
     u) of the pure-species viscosity and conductivity and of the binary
     diffusion coefficients at 1 atm (or their reciprocals, diff_fit_kind 1),
@@ -249,7 +250,8 @@ def transport_fits(W, sigma_cm, eps, zrot298, natoms, cp_over_r, diff_fit_kind: 
 
     W[ns] g/mol, sigma_cm[ns], eps[ns] (epsilon/k, K), zrot298[ns], natoms[ns]
     (1 atom, 2 linear, >= 3 nonlinear), cp_over_r[ns, 64] on the grid.
-    Returns visc_fit[ns, 5], cond_fit[ns, 5], diff_fit[ns, ns, 5].
+    Returns visc_fit[ns, order], cond_fit[ns, order], diff_fit[ns, ns, order]
+    (order coefficients, constant term first).
     """
     ns = len(W)
     Tg = transport_fit_grid()
@@ -266,12 +268,12 @@ def transport_fits(W, sigma_cm, eps, zrot298, natoms, cp_over_r, diff_fit_kind: 
         cv_r = cp_over_r[k] - 1.0
         lam[k] = _pure_conductivity(Tg, W[k], eta[k], rhoD_eta, cv_r, natoms[k],
                                     zrot298[k], eps[k])
-    visc_fit = _weighted_polyfit(ug, eta, FIT_ORDER)
-    cond_fit = _weighted_polyfit(ug, lam, FIT_ORDER)
+    visc_fit = _weighted_polyfit(ug, eta, order)
+    cond_fit = _weighted_polyfit(ug, lam, order)
     iu = np.triu_indices(ns)
     target = Dg[iu] if diff_fit_kind == 0 else 1.0 / Dg[iu]
-    dfit_u = _weighted_polyfit(ug, target, FIT_ORDER)
-    diff_fit = np.empty((ns, ns, FIT_ORDER))
+    dfit_u = _weighted_polyfit(ug, target, order)
+    diff_fit = np.empty((ns, ns, order))
     diff_fit[iu] = dfit_u
     diff_fit[(iu[1], iu[0])] = dfit_u
     return visc_fit, cond_fit, diff_fit
@@ -367,6 +369,8 @@ class MechSpec:
     # reaction side holds two QSS molecules, then dropped from the efficiency
     # lists (the third-body sums run over transported species only)
     n_qss: int = 0
+    # coefficients of the transport fits (polynomial degree + 1)
+    fit_order: int = FIT_ORDER
 
     @property
     def n_reactions(self) -> int:
@@ -588,7 +592,7 @@ def make_mechanism(spec: MechSpec) -> dict:
     Tg = transport_fit_grid()
     cp_r = np.stack([_cp_model(Tg, clo[k], chi[k], theta[k]) for k in range(ns)])
     visc_fit, cond_fit, diff_fit = transport_fits(W, sigma, eps, zrot, natoms, cp_r,
-                                                  spec.diff_fit_kind)
+                                                  spec.diff_fit_kind, spec.fit_order)
 
     sri = chem_act = plog = orders = None
     reversible = np.ones(nr, np.int32)
@@ -680,7 +684,7 @@ def make_mechanism(spec: MechSpec) -> dict:
         "eff_sp": eff_sp,
         "eff_val": eff_val,
         "eff_default": eff_default,
-        "fit_order": FIT_ORDER,
+        "fit_order": spec.fit_order,
         "fit_L0": FIT_L0,
         "fit_h": FIT_H,
         "diff_fit_kind": spec.diff_fit_kind,

@@ -397,6 +397,36 @@ def test_symmetric_diffusion_fits(kx):
         assert torch.equal(x, y)
 
 
+def test_other_fit_orders(kx):
+    """Transport fits with 3, 4, 7 and 8 coefficients (every other test
+    mechanism has 5; these run the kernels' forms for any fit order): the
+    matrix-core kernel (1/D_kj fits), the vector-ALU kernel and the symmetric
+    evaluation (D_kj fits), FP64 and mixed, 4133 points, against the oracle."""
+    import dataclasses
+    T, p, Y = I.make_states(53, I.StateSpec(4133, seed=92, p_atm_range=(1.0, 40.0),
+                                            dirichlet_alpha=0.3))
+    Td, pd, Yd = to_dev(T, p, Y)
+    for fo, kind, sym in ((4, 1, False), (8, 1, False), (3, 0, False), (7, 0, True)):
+        spec = dataclasses.replace(I.MECH_53, fit_order=fo, diff_fit_kind=kind,
+                                   name=f"syn53_fit{fo}_kind{kind}")
+        m = I.make_mechanism(spec)
+        assert m["fit_order"] == fo
+        dm = kx.Mechanism(m, 0)
+        try:
+            rmu, rlam, rDm = O.OracleMech(m).transport(T, p, Y)
+            for prec, tol in (("fp64", PM.REL_FP64), ("mixed", PM.REL_MIXED)):
+                _say("fit order", fo, "diffusion fit kind", kind, "symmetric" if sym else "",
+                     prec, "n =", T.size)
+                out = kx.transport(dm, Td, pd, Yd, precision=prec, symmetric=sym)
+                torch.cuda.synchronize()
+                for name, g, rr in zip(("mu", "lambda", "Dmix"), out, (rmu, rlam, rDm)):
+                    rep = PM.rel_report(g.cpu().numpy(), rr, tol)
+                    _say("  ", name, rep)
+                    assert rep["ok"], (spec.name, prec, name, rep)
+        finally:
+            dm.close()
+
+
 def test_near_equilibrium_states_fp64(kx, mech53):
     om = O.OracleMech(mech53)
     T, p, Y = O.equilibrium_states(om, 2048, seed=31, perturb=1e-6)

@@ -270,6 +270,36 @@ def test_served_large_mechanisms_equal_direct(kx, mech100, mech200):
             dm.close()
 
 
+def test_served_other_fit_order_equals_direct(kx):
+    """A mechanism with 4-coefficient transport fits (the batch and one-tile
+    kernels' forms for any fit order) served in small batches (graph replay)
+    and then in big ones (one workgroup per tile), both precisions: every
+    output equals the direct call bit for bit."""
+    import dataclasses
+    mech = I.make_mechanism(dataclasses.replace(I.MECH_53, fit_order=4, name="syn53_fit4"))
+    dm = kx.Mechanism(mech, 0)
+    srv = kx.Server(0, hbm_budget=4 << 30, max_slots=16)
+    try:
+        for group in ([(3001, "fp64"), (129, "mixed")], [(150001, "fp64"), (140003, "mixed")]):
+            cases = []
+            for i, (n, prec) in enumerate(group):
+                (Td, pd, Yd), _ = _inputs(53, n, 700 + n % 97 + i)
+                cases.append((srv.submit(dm, Td, pd, Yd, transport=True, precision=prec),
+                              n, prec, Td, pd, Yd))
+            for t, n, prec, Td, pd, Yd in cases:
+                _say("request", t, "syn53_fit4 n =", n, prec)
+                r = srv.wait(t, WAIT_S)
+                assert r["state"] == "done", r
+                got = srv.outputs(t)
+                ref = _direct(kx, dm, Td, pd, Yd, True, prec)
+                for g, e, what in zip(got, ref, ("wdot", "mu", "lambda", "Dmix")):
+                    assert _same(g, e), (n, prec, what)
+                srv.release(t)
+    finally:
+        srv.close()
+        dm.close()
+
+
 def test_inputs_ready_event(kx, mechs):
     """A request whose inputs are still being written on another stream when it
     is submitted: the server waits for the event recorded after that work, and

@@ -756,6 +756,33 @@ def test_fit_evaluation_matches_kinetic_theory(mech53):
         assert D[k, j] == pytest.approx(Dref, rel=3e-2)
 
 
+def test_fit_evaluation_at_other_orders():
+    """Fits with 3 to 8 coefficients: the oracle evaluates all of them in the
+    right order, so with 8 coefficients it reproduces the kinetic-theory values
+    to 1e-3, and the binary-diffusion error falls as the order grows (a dropped
+    or misplaced coefficient of the longer polynomials would show in both)."""
+    import dataclasses
+    err = {}
+    for fo in (3, 5, 8):
+        m = I.make_mechanism(dataclasses.replace(I.MECH_53, fit_order=fo))
+        om = O.OracleMech(m)
+        W = m["composition"] @ m["elem_mass"]
+        e_eta = e_D = 0.0
+        for T in (420.0, 1111.0, 2600.0):
+            eta, lam, D = om.pure_transport(T, O.PATM)
+            ref = np.array([I._pure_viscosity(T, W[k], m["_sigma_cm"][k], m["_eps_k"][k])
+                            for k in range(om.ns)])
+            e_eta = max(e_eta, float(np.max(np.abs(eta / ref - 1.0))))
+            for k, j in ((3, 17), (0, 52), (20, 21)):
+                Dref = I._binary_diffusion_1atm(T, W[k], W[j], m["_sigma_cm"][k],
+                                                m["_sigma_cm"][j], m["_eps_k"][k],
+                                                m["_eps_k"][j])
+                e_D = max(e_D, abs(D[k, j] / Dref - 1.0))
+        err[fo] = (e_eta, e_D)
+    assert err[8][0] < 1e-3 and err[8][1] < 1e-3, err
+    assert err[3][1] > err[5][1] > err[8][1], err
+
+
 # ---------------------------------------------------- QSS species (planned, §4)
 def _qss_closed_form(m, T, p, Y):
     """wdot (A, B, D) and C_Q of the chain mechanism written out by hand."""
