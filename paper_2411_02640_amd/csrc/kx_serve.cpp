@@ -238,11 +238,13 @@ void begin_batch(kx_server *s, Slot &sl, std::vector<Req *> &batch)
     }
 }
 
-// Enqueue a begun batch on its slot's stream: work list, waits on the inputs'
-// events, graph replay, completion event.  Called WITHOUT the lock: it reads
-// only the requests of this batch (fixed while they run) and the slot, which
-// no other thread touches while it is busy.  Returns whether the graph was
-// launched (false: nothing usable was enqueued).
+// Enqueue a begun batch on its slot's stream: waits on the inputs' events, the
+// work list, then a graph replay (or, for a big batch, the one-tile kernels),
+// and the completion event.  Called WITHOUT the lock: it reads only the
+// requests of this batch (fixed while they run) and the slot, which no other
+// thread touches while it is busy.  Returns whether the batch was enqueued
+// (false: nothing usable was, and the stream has drained); *used_graph tells
+// whether a graph replay runs it.
 bool enqueue_batch(kx_server *s, Slot &sl, const ServedMech &sm, hipGraphExec_t graph,
                    hipGraphExec_t *new_graph, bool *used_graph)
 {
