@@ -5,9 +5,10 @@
 // per tile) take their work list from device memory.  Here that memory is a
 // file-scope device array, `scratch`, of fixed size: a setup kernel writes the
 // work list (from its by-value argument), then the rates kernel and, if asked
-// for, the transport kernel run over it with grids of the host's tile counts.  No device or pinned
-// memory is allocated and no host-to-device copy is made, so the call can be
-// captured into a HIP graph or issued from a loop that must not allocate.
+// for, the transport kernel run over it with grids of the host's tile counts.
+// No device or pinned memory is allocated and no host-to-device copy is made,
+// so the call can be captured into a HIP graph or issued from a loop that must
+// not allocate.
 // Every call on a device uses that device's one copy of the array.
 #include <hip/hip_runtime.h>
 
@@ -125,18 +126,24 @@ extern "C" kx_status kx_batch_noalloc(const kx_mech *mech, int32_t ops, int32_t 
     a.transport_tp = ttp;
     a.transport = tr;
 
+    // the mechanism's device is current for the calls below (the scratch address
+    // is that device's), the caller's device again on return
     struct Guard {
         int prev = -1;
+        hipError_t err = hipSuccess;
         explicit Guard(int dev)
         {
-            if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+            err = hipGetDevice(&prev);
+            if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
         }
         ~Guard()
         {
             int cur = -1;
-            if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+            if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
+                (void)hipSetDevice(prev);
         }
     } g(mech->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "kx_batch_noalloc: hipSetDevice");
     void *base = nullptr;
     kx_status st = scratch_address(mech->device, &base);
     if (st != KX_OK) return st;
