@@ -611,10 +611,12 @@ kx_status kx_server_add_mech(kx_server *s, const kx_mech *m)
     if (!s->simulate) {
         int prev = 0;
         hipGetDevice(&prev);
-        hipSetDevice(s->device);
+        hipError_t e = hipSetDevice(s->device);
+        if (e != hipSuccess) st = hip_fail(e, "kx_server_add_mech: hipSetDevice");
         char *dst = s->arena_base + off;
-        hipError_t e = hipMemcpy(dst, m->blob, (size_t)m->bytes, hipMemcpyDeviceToDevice);
-        if (e != hipSuccess) st = hip_fail(e, "kx_server_add_mech: table copy");
+        if (st == KX_OK &&
+            (e = hipMemcpy(dst, m->blob, (size_t)m->bytes, hipMemcpyDeviceToDevice)) != hipSuccess)
+            st = hip_fail(e, "kx_server_add_mech: table copy");
         if (st == KX_OK && !rebase_tables(m, dst, &sm.dev))
             st = fail(KX_EINVAL, "kx_server_add_mech: internal error: table pointers not moved");
         // every (stream, precision, ops) graph of this mechanism, captured now
